@@ -1,0 +1,153 @@
+"""CPU oracle for the Matching Pursuit decoder.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import anything from this package.
+The GPU library never calls it and shares no code with it.
+
+Contents
+* :func:`solve` / :func:`correlate` -- the plain FP64 MP of Section 3
+  (eqs. 8-12, argmax tie rule of eq. 16), in C (``mp_oracle.c``).
+* :mod:`oracle.exact` -- exact rational MP and brute-force pins.
+* :mod:`oracle.quant` -- reference BF16 / FP8-e4m3fn quantisers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmporacle.so")
+
+CONVERGED, MAX_ITERS, STALLED, ZERO_INPUT = 0, 1, 2, 3
+REASONS = {CONVERGED: "converged", MAX_ITERS: "max_iters", STALLED: "stalled",
+           ZERO_INPUT: "zero_input"}
+
+_lib = None
+
+
+def load_library(path: str):
+    """Open a compiled oracle (the default one, or a test-built variant)."""
+    lib = ctypes.CDLL(path)
+    p, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    for suf in ("f32", "f64"):
+        f = getattr(lib, "mpo_solve_" + suf)
+        f.restype = ctypes.c_int
+        f.argtypes = [p, i64, i64, i64, p, dbl, i64, p, p, p, p, p, p, p, p, p, p, i64]
+        g = getattr(lib, "mpo_correlate_" + suf)
+        g.restype = None
+        g.argtypes = [p, i64, i64, i64, p, p]
+    lib.mpo_num_threads.restype = ctypes.c_int
+    lib.mpo_set_num_threads.argtypes = [ctypes.c_int]
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    _lib = load_library(LIB_PATH)
+    return _lib
+
+
+def num_threads() -> int:
+    return _load().mpo_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().mpo_set_num_threads(int(n))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _psi_view(psi: np.ndarray):
+    """(pointer-able array, suffix, n, m, ld) for a column-major dictionary."""
+    if psi.ndim != 2:
+        raise ValueError("psi must be 2-D (N, M)")
+    n, m = psi.shape
+    if psi.dtype == np.float32:
+        suf = "f32"
+    elif psi.dtype == np.float64:
+        suf = "f64"
+    else:
+        raise TypeError("psi must be float32 or float64")
+    if psi.flags.f_contiguous:
+        base, ld = psi, n
+    else:
+        base, ld = np.asfortranarray(psi), n
+    return base, suf, n, m, ld
+
+
+@dataclass
+class Result:
+    x: np.ndarray          # (M,) float64 estimate x~
+    r: np.ndarray          # (N,) float64 residual
+    iters: int
+    reason: int
+    yy: float              # ||y||^2
+    rr: float              # ||r||^2 at exit
+    idx: np.ndarray        # (iters,) int32 selected indices (trace)
+    coef: np.ndarray       # (iters,) float64 selected coefficients
+    rr_trace: np.ndarray   # (iters,) float64 ||r||^2 after each step
+    gap: np.ndarray        # (iters,) float64 top-two |c| gap before each step
+
+
+def solve(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
+          trace: bool = True, lib=None) -> Result:
+    """FP64 Matching Pursuit on the given dictionary (FP32 or FP64 storage)."""
+    lib = _load() if lib is None else lib
+    base, suf, n, m, ld = _psi_view(psi)
+    y32 = np.ascontiguousarray(y, dtype=np.float32)
+    if y32.shape != (n,):
+        raise ValueError("y must have shape (N,)")
+    x = np.zeros(m, dtype=np.float64)
+    r = np.zeros(n, dtype=np.float64)
+    iters = np.zeros(1, dtype=np.int64)
+    reason = np.zeros(1, dtype=np.int32)
+    yy = np.zeros(1, dtype=np.float64)
+    rr = np.zeros(1, dtype=np.float64)
+    cap = int(max_iters) if trace else 0
+    ti = np.zeros(max(cap, 1), dtype=np.int32)
+    tc = np.zeros(max(cap, 1), dtype=np.float64)
+    tr = np.zeros(max(cap, 1), dtype=np.float64)
+    tg = np.zeros(max(cap, 1), dtype=np.float64)
+    rc = getattr(lib, "mpo_solve_" + suf)(
+        _ptr(base), n, m, ld, _ptr(y32), float(eps), int(max_iters),
+        _ptr(x), _ptr(r), _ptr(iters), _ptr(reason), _ptr(yy), _ptr(rr),
+        _ptr(ti), _ptr(tc), _ptr(tr), _ptr(tg), cap)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (code {rc})")
+    t = int(iters[0])
+    k = min(t, cap)
+    return Result(x, r, t, int(reason[0]), float(yy[0]), float(rr[0]),
+                  ti[:k].copy(), tc[:k].copy(), tr[:k].copy(), tg[:k].copy())
+
+
+def correlate(psi: np.ndarray, r: np.ndarray, lib=None) -> np.ndarray:
+    """c = Psi^T r in FP64 (eq. 9's inner products), sequential per column."""
+    lib = _load() if lib is None else lib
+    base, suf, n, m, ld = _psi_view(psi)
+    r64 = np.ascontiguousarray(r, dtype=np.float64)
+    if r64.shape != (n,):
+        raise ValueError("r must have shape (N,)")
+    c = np.zeros(m, dtype=np.float64)
+    getattr(lib, "mpo_correlate_" + suf)(_ptr(base), n, m, ld, _ptr(r64), _ptr(c))
+    return c
+
+
+def top_two(c: np.ndarray):
+    """(argmax index with smallest-index tie rule, top-two |c| gap)."""
+    a = np.abs(c)
+    i = int(np.argmax(a))  # numpy returns the first occurrence of the maximum
+    if a.size == 1:
+        return i, float(a[0])
+    second = float(np.max(np.delete(a, i)))
+    return i, float(a[i]) - second

@@ -1,0 +1,68 @@
+"""The seeded input generators: determinism and the workload recipe."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import mpgen
+
+
+def test_same_seed_same_problem():
+    a = mpgen.make_problem("c0", 3)
+    b = mpgen.make_problem("c0", 3)
+    assert np.array_equal(a.psi, b.psi) and np.array_equal(a.y, b.y)
+    assert np.array_equal(a.support, b.support)
+    c = mpgen.make_problem("c0", 4)
+    assert not np.array_equal(a.psi, c.psi)
+
+
+@pytest.mark.parametrize("name", ["c0", "c1a"])
+def test_problem_recipe(name):
+    w = mpgen.workload(name)
+    p = mpgen.make_problem(name, 0)
+    assert p.psi.shape == (w["n"], w["m"]) and p.psi.dtype == np.float32
+    assert p.psi.flags.f_contiguous
+    norms = np.linalg.norm(np.asarray(p.psi, dtype=np.float64), axis=0)
+    assert np.all(np.abs(norms - 1.0) < 1e-6)
+    assert len(np.unique(p.support)) == w["k"] == np.count_nonzero(p.x)
+    y64 = np.asarray(p.psi, dtype=np.float64)[:, p.support] @ p.x[p.support].astype(np.float64)
+    assert np.array_equal(p.y, y64.astype(np.float32))
+    assert p.eps == w["eps"] and p.max_iters == w["max_iters"]
+
+
+def test_loguniform_values():
+    p = mpgen.make_problem("c0", 0, dist="loguniform")
+    v = np.abs(p.x[p.support])
+    assert np.all((v >= 1e-3 * (1 - 1e-6)) & (v <= 1.0))
+
+
+def test_batch_recipe():
+    bt = mpgen.make_batch(0, b=8, n=64, m=256, kmin=2, kmax=6)
+    assert bt.x.shape == (256, 8) and bt.y.shape == (64, 8)
+    assert np.all((bt.k >= 2) & (bt.k <= 6))
+    for j in range(8):
+        assert np.count_nonzero(bt.x[:, j]) == bt.k[j]
+        sup = np.flatnonzero(bt.x[:, j])
+        y = mpgen.encode(bt.psi, bt.x[:, j], sup)
+        assert np.array_equal(y, bt.y[:, j])
+    assert np.array_equal(bt.max_iters, 20 * bt.k)
+
+
+def test_ragged_recipe():
+    probs = mpgen.make_ragged(0, count=6, n_choices=(16, 32))
+    assert len(probs) == 6
+    for p in probs:
+        assert p.n in (16, 32) and p.m == 4 * p.n
+        assert len(p.support) == p.n // 16
+
+
+def test_hadamard_orthonormal():
+    h = mpgen.hadamard_dictionary(64).astype(np.float64)
+    assert np.array_equal(h.T @ h, np.eye(64))
+
+
+def test_rational_columns_exact_unit_norm():
+    rng = np.random.default_rng(0)
+    cols = mpgen.rational_unit_dictionary(rng, 5, 7)
+    for c in cols:
+        assert sum(v * v for v in c) == 1

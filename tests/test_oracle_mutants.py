@@ -1,0 +1,115 @@
+"""Planted mistakes in the oracle must be caught by the pins (CPU only).
+
+Each mutant is the oracle's C source with one plausible slip substituted in,
+compiled with gcc to a temporary library.  The pin battery below (the same
+facts as ``test_oracle_pins.py``: hand-derived ties, best one-term fits,
+energy bookkeeping, reconstruction, stop counts) must fail on every mutant and
+pass on the unmodified source.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import mpgen
+import oracle
+from oracle import build as obuild
+from oracle.exact import best_one_term
+
+SRC = obuild.SRC
+
+MUTANTS = {
+    "signed_argmax": ("double a = fabs(c[j]);", "double a = c[j];"),
+    "tie_to_largest_index": ("if (a > b) {", "if (a >= b) {"),
+    "update_sign": ("r_out[k] -= ci * (double)col[k];", "r_out[k] += ci * (double)col[k];"),
+    "coef_assign_not_accumulate": ("x_out[i] += ci;", "x_out[i] = ci;"),
+    "eps_not_squared": ("const double thr = eps * eps * yy;", "const double thr = eps * yy;"),
+    "cap_off_by_one": ("if (t >= max_iters)", "if (t > max_iters)"),
+    "dropped_last_term": ("for (int64_t i = 0; i < n; ++i) s += (double)col[i] * r[i];",
+                          "for (int64_t i = 0; i + 1 < n; ++i) s += (double)col[i] * r[i];"),
+    "stale_norm": ("rr = sumsq(r_out, n);", "rr = rr - ci * ci * 0.5;"),
+}
+
+
+def _build_variant(tmp_path, name, sub):
+    src = open(SRC).read()
+    old, new = sub
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    out = str(tmp_path / f"lib_{name}.so")
+    obuild.build(src=str(path), out=out)
+    return oracle.load_library(out)
+
+
+def _pin_battery(lib):
+    """Return the list of pins that fail for this compiled oracle."""
+    with np.errstate(all="ignore"):   # mutants may overflow; that is a failure too
+        return _run_battery(lib)
+
+
+def _run_battery(lib):
+    failed = []
+    # 1. hand-derived Hadamard tie example (eq. 16)
+    psi = mpgen.hadamard_dictionary(16)
+    x = np.zeros(16, np.float32)
+    x[[3, 7, 11, 12, 14, 15]] = [-0.5, 0.5, 0.5, 0.25, -0.25, 0.125]
+    y = mpgen.encode(psi, x)
+    res = oracle.solve(psi, y, 0.0, 20, lib=lib)
+    if res.idx.tolist() != [3, 7, 11, 12, 14, 15] or not np.array_equal(res.x, x.astype(float)):
+        failed.append("hadamard_ties")
+    # 2. each step is the best one-term fit (brute force through lstsq)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((24, 40))
+    psi64 = np.asfortranarray(g / np.linalg.norm(g, axis=0))
+    xs = np.zeros(40)
+    xs[[2, 9, 33]] = [1.0, -2.0, 0.5]
+    y2 = (psi64 @ xs).astype(np.float32)
+    full = oracle.solve(psi64, y2, 0.0, 10, lib=lib)
+    r = y2.astype(np.float64)
+    for t in range(min(10, full.iters)):
+        j, a, r = best_one_term(psi64, r)
+        if full.idx[t] != j or abs(full.coef[t] - a) > 1e-12:
+            failed.append("best_one_term")
+            break
+    if full.iters != 10:
+        failed.append("best_one_term_iters")
+    # 3. energy identity and reconstruction on a real workload
+    p = mpgen.make_problem("c0", 0)
+    res = oracle.solve(p.psi, p.y, p.eps, p.max_iters, lib=lib)
+    psi32 = np.asarray(p.psi, dtype=np.float64)
+    defect = p.y.astype(np.float64) - psi32 @ res.x - res.r
+    if np.linalg.norm(defect) > 1e-13 * np.linalg.norm(p.y):
+        failed.append("reconstruction")
+    if res.iters:
+        nrm2 = np.sum(psi32 ** 2, axis=0)
+        pre = np.r_[res.yy, res.rr_trace[:-1]]
+        pred = pre - 2 * res.coef ** 2 + res.coef ** 2 * nrm2[res.idx]
+        if np.any(np.abs(res.rr_trace - pred) > 1e-12 * pre):
+            failed.append("energy")
+        rr_direct = float(res.r @ res.r)
+        if abs(rr_direct - res.rr) > 1e-12 * res.yy:
+            failed.append("norm_consistency")
+    if res.reason != oracle.CONVERGED or not res.rr <= p.eps ** 2 * res.yy:
+        failed.append("converged")
+    # 4. stop counts: cap binds exactly, eps between tails fixes the count
+    res = oracle.solve(psi, y, 0.0, 2, lib=lib)
+    if res.iters != 2 or res.reason != oracle.MAX_ITERS:
+        failed.append("cap")
+    res = oracle.solve(psi, y, 0.25, 20, lib=lib)
+    if res.iters != 5:
+        failed.append("eps_stop_count")
+    return failed
+
+
+def test_unmodified_oracle_passes_battery():
+    assert _pin_battery(oracle._load()) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistakes_are_caught(tmp_path, name):
+    lib = _build_variant(tmp_path, name, MUTANTS[name])
+    failed = _pin_battery(lib)
+    assert failed, f"mutant {name} passed every pin"
