@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the Matching Pursuit decoder on one MI355X.
+
+A step is one whole decode (Section 3 loop until ||r|| <= eps ||y|| or T
+steps) of one synthetic signal through the C ABI (mp_solve), with the
+dictionary and y already resident in HBM.  Default workload: N=8192,
+M=32768 (1 GiB FP32 dictionary), K=512, eps=1e-5, T=20K.
+
+Prints ONE JSON line.  `value` is MP iterations per second over the timed
+steps; `roofline` is the correlation kernel's algorithmic HBM bandwidth
+(dictionary + residual bytes per launch / mean launch time from HIP events on
+the decode stream) against the 8 TB/s peak; `cpu_baseline` is the FP64
+oracle timed on a bounded sample of the same decode on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MP iters/s & achieved HBM GB/s (1 signal); signals/s batched BF16 vs FP32"
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "corr_f32_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_0809_1833_amd", "csrc", "k_f32.hip")
+
+WORKLOADS = {
+    "c1b": "N=8192, M=32768 (FP32 dictionary 1 GiB), K=512, eps=1e-5, T=10240, single signal",
+    "c1a": "N=2048, M=8192 (FP32 dictionary 64 MiB), K=128, eps=1e-5, T=2560, single signal",
+    "c0": "N=256, M=1024, K=10, eps=1e-6, T=2000, single signal",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_counters(n, m):
+    """HBM bytes per correlation launch from committed rocprofv3 counter runs,
+    or None when absent or taken on a different kernel source."""
+    try:
+        with open(PMC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_hash() or d.get("n") != n or d.get("m") != m:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(p, budget_s=15.0):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.solve(p.psi, p.y, p.eps, 2, trace=False)
+    per = max((time.perf_counter() - t0) / 2.0, 1e-6)
+    iters = int(max(3, min(p.max_iters, budget_s / per)))
+    t0 = time.perf_counter()
+    res = oracle.solve(p.psi, p.y, p.eps, iters, trace=False)
+    dt = time.perf_counter() - t0
+    return dict(value=round(res.iters / dt, 3), unit="iters/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"first {res.iters} MP iterations of the same decode (FP64, "
+                       f"{dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1b", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the decoder is built and measured on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mpgen
+    from paper_0809_1833_amd.mp import Decoder
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"[bench] generating {args.workload} seed {args.seed}")
+    p = mpgen.make_problem(args.workload, args.seed)
+    n, m = p.n, p.m
+    psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
+    y = torch.from_numpy(p.y).cuda()
+    stream = torch.cuda.current_stream()
+    dec = Decoder(psi)
+    del psi
+    x = torch.empty(m, dtype=torch.float32, device="cuda")
+    r = torch.empty(n, dtype=torch.float32, device="cuda")
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        dec.solve(y, p.eps, p.max_iters, x=x, r=r)
+    dec.set_profiling(True)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} decodes")
+    iters = 0
+    kt_ms, kt_n = 0.0, 0
+    stops = set()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream)
+        iters += out["iters"]
+        ms, cnt = dec.kernel_time()
+        kt_ms += ms * cnt
+        kt_n += cnt
+        stops.add(out["stop"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dec.set_profiling(False)
+    log(f"[bench] {iters} iterations in {dt:.3f} s")
+
+    bytes_per_launch = 4.0 * n * m + 4.0 * n          # dictionary + residual, once each
+    bytes_per_iter = 4.0 * n * m + 12.0 * n           # + chosen column, residual read/write
+    avg_ms = kt_ms / max(kt_n, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kt_n else None
+    traffic = traffic_from_counters(n, m)
+    line = {
+        "metric": METRIC,
+        "value": round(iters / dt, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian unit-column dictionary, K-sparse N(0,1) signal)",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "iters_per_decode": iters // max(args.steps, 1),
+                   "stop": sorted(stops), "seed": args.seed},
+        "effective_gbps_whole_step": round(iters * bytes_per_iter / dt / 1e9, 2),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_corr_f32",
+            "achieved": round(achieved, 2) if achieved else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+            "launches": kt_n,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(p)
+    dec.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * mp.h -- C ABI of the MI355X (gfx950) Matching Pursuit decoder, libmp.so.
+ *
+ * The decoder recovers a sparse x from y = Psi x, given y and the N x M
+ * dictionary Psi with unit-norm columns (Section 2, eqs. 2-4), by the Matching
+ * Pursuit iteration of Section 3 (eqs. 8-12):
+ *
+ *     t = 0, x~ = 0, r = y
+ *     while ||r||_2 > eps ||y||_2 and t < T:
+ *         i    = argmax_m |<r, psi_m>|   (smallest index on ties, as the
+ *                                          i?amax kernel of eq. 16)
+ *         x~_i += <r, psi_i>
+ *         r    -= <r, psi_i> psi_i
+ *         t    += 1
+ *
+ * Conventions shared by every entry point
+ *  - Indices are 0-based.
+ *  - Matrices are column-major: element (row n, column m) of a matrix with
+ *    leading dimension ld is at offset n + m * ld.  A dictionary column psi_m
+ *    is therefore contiguous.
+ *  - Pointers documented as "device" must point to memory of the current HIP
+ *    device; "host" pointers to ordinary host memory.  The library never
+ *    frees caller memory and never keeps a caller pointer past the call,
+ *    except where MP_BORROW_PSI says otherwise.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is ordered on that stream; every mp_solve* call returns only after its
+ *    decode has finished (the host needs the device's stop flag to know when
+ *    to stop issuing iterations).
+ *  - Errors are reported by return code only; nothing aborts the process.
+ *    mp_last_error(ctx) returns a human-readable detail for the last failed
+ *    call on a context.
+ *  - A context is not thread-safe: one call at a time per context.
+ *
+ * Stopping rule (the pseudo-code's test, on squared norms in FP64): the loop
+ * continues while ||r||^2 > eps^2 ||y||^2 and t < max_iters; it is tested
+ * before every step, so `iters` counts the updates done.  y = 0 takes no step
+ * (MP_STOP_ZERO_INPUT); a largest |<r, psi_m>| of exactly 0 ends the run
+ * without an update (MP_STOP_STALLED).
+ */
+#ifndef MP_H_
+#define MP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mp_status {
+    MP_OK = 0,
+    MP_EINVAL = 1,        /* an argument is out of range or NULL where not allowed */
+    MP_ENOTNORM = 2,      /* a dictionary column's L2 norm is not 1 within 1e-4 */
+    MP_ENONFINITE = 3,    /* NaN or Inf in the dictionary or in y */
+    MP_ENOMEM = 4,        /* a device or pinned-host allocation failed */
+    MP_EDEVICE = 5,       /* no usable HIP device, or a HIP runtime call failed */
+    MP_EUNSUPPORTED = 6   /* the request is valid but this build/device cannot do it */
+} mp_status;
+
+/* Storage of the dictionary copy the correlation pass streams. */
+typedef enum mp_dtype {
+    MP_F32 = 0,           /* FP32, as given */
+    MP_BF16 = 1,          /* BF16, round to nearest even from FP32 */
+    MP_FP8_E4M3 = 2       /* OCP FP8 E4M3 (e4m3fn) with one FP32 scale per column:
+                             s_m = fp32(max_n |psi_nm| / 448) (1 for a zero column),
+                             code = RNE-saturate(fp32(psi_nm / s_m)) */
+} mp_dtype;
+
+/* Why a decode stopped (mp_result.stop_reason). */
+enum {
+    MP_STOP_CONVERGED = 0,   /* ||r||^2 <= eps^2 ||y||^2 */
+    MP_STOP_MAX_ITERS = 1,   /* t reached max_iters */
+    MP_STOP_STALLED = 2,     /* max_m |<r, psi_m>| == 0 with r != 0 */
+    MP_STOP_ZERO_INPUT = 3   /* y == 0 */
+};
+
+/* mp_create flags */
+#define MP_SKIP_NORM_CHECK 0x1u   /* do not verify ||psi_m|| = 1 (finiteness is still checked) */
+
+typedef struct mp_ctx mp_ctx;
+
+typedef struct mp_opts {
+    double eps;           /* relative tolerance, >= 0 and finite */
+    int64_t max_iters;    /* iteration cap T, >= 0 */
+    int32_t rescore_k;    /* reduced-precision storage: how many best candidates of
+                             each pass are re-scored against the FP32 columns (1..8;
+                             0 means 8).  Ignored for MP_F32 storage. */
+    uint32_t flags;       /* reserved, must be 0 */
+} mp_opts;
+
+typedef struct mp_result {
+    int64_t iters;        /* updates performed */
+    double yy;            /* ||y||^2, FP64 */
+    double rr;            /* ||r||^2 at exit, FP64 (from the FP32 residual) */
+    int32_t stop_reason;  /* MP_STOP_* */
+    int32_t reserved;
+} mp_result;
+
+/* Optional per-step record, all arrays device memory of `cap` entries.
+   Step t (0-based) writes idx[t], coef[t] (the FP32 coefficient added to
+   x~), rr[t] (||r||^2 after the step, FP64) while t < cap; any array may be
+   NULL. */
+typedef struct mp_trace {
+    int32_t* idx;
+    float* coef;
+    double* rr;
+    int64_t cap;
+} mp_trace;
+
+/*
+ * mp_create -- take the dictionary Psi (Section 2, eqs. 3-4) and prepare it
+ * for decoding.  The one-time host-to-device dictionary set-up that every
+ * later decode reuses (the paper uploads the dictionary once for all signals).
+ *
+ *   out      host: receives the new context (set to NULL on failure)
+ *   psi      device: FP32 N x M column-major dictionary, leading dimension ld
+ *   n, m     rows N >= 1 and columns M >= 1 (M < 2^31, N <= 16384)
+ *   ld       leading dimension, ld >= n
+ *   storage  which copy the correlation pass streams (mp_dtype).  MP_BF16 and
+ *            MP_FP8_E4M3 keep an FP32 master as well, for re-scoring and the
+ *            residual update.
+ *   flags    MP_SKIP_NORM_CHECK or 0
+ *   stream   hipStream_t as void*
+ *
+ * The context copies psi (re-laid out with a padded leading dimension), so
+ * the caller may free psi when mp_create returns.
+ * Errors: MP_EINVAL (NULL, n < 1, m < 1, ld < n, size limits, unknown storage
+ * or flags), MP_ENONFINITE, MP_ENOTNORM, MP_ENOMEM, MP_EDEVICE,
+ * MP_EUNSUPPORTED (the device is not gfx950).
+ */
+mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_t ld,
+                    mp_dtype storage, uint32_t flags, void* stream);
+
+/*
+ * mp_solve -- decode one signal: the Section 3 loop, run entirely on the
+ * device (correlation, argmax, coefficient and residual update, FP64 stop
+ * test), with no host round trip per iteration.
+ *
+ *   ctx      from mp_create
+ *   y        device: N floats, not modified
+ *   x        device: M floats, overwritten with x~ (FP32)
+ *   r        device: N floats or NULL; receives the final residual (FP32)
+ *   opts     host: tolerance, cap, re-score count
+ *   res      host or NULL: iteration count, norms, stop reason
+ *   trace    host struct of device arrays, or NULL (see mp_trace)
+ *   stream   hipStream_t as void*
+ *
+ * y, x and r must not overlap.  Errors: MP_EINVAL (NULL ctx/y/x/opts, eps < 0
+ * or not finite, max_iters < 0, flags != 0, rescore_k outside 0..8),
+ * MP_ENONFINITE (y holds NaN/Inf; x and r are then unspecified), MP_EDEVICE.
+ */
+mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
+                   mp_result* res, const mp_trace* trace, void* stream);
+
+/*
+ * mp_destroy -- free everything the context owns.  NULL is a no-op.
+ */
+void mp_destroy(mp_ctx* ctx);
+
+/* Name of a status code (static string). */
+const char* mp_status_str(mp_status s);
+
+/* Detail of the last failed call on ctx ("" if none); the pointer stays valid
+   until the next call on ctx.  With ctx == NULL: the last mp_create failure
+   of the calling thread. */
+const char* mp_last_error(const mp_ctx* ctx);
+
+/*
+ * mp_get_storage -- copy out the dictionary copy the correlation pass reads,
+ * without its padding: FP32 (4-byte), BF16 (2-byte) or FP8 (1-byte) codes,
+ * column-major N x M with leading dimension N, and for MP_FP8_E4M3 the M
+ * per-column FP32 scales (scales may be NULL otherwise).
+ *
+ *   codes    device: N*M elements of the storage type's size
+ *   scales   device: M floats, or NULL
+ * Errors: MP_EINVAL, MP_EDEVICE.
+ */
+mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* stream);
+
+/*
+ * mp_kernel_time -- per-launch timing of the correlation kernel (the pass
+ * over the whole dictionary, eq. 9) during the last mp_solve, measured with
+ * HIP events on the stream it ran on.  Only launches that performed an
+ * iteration are counted.  Timing is recorded only while enabled with
+ * mp_set_profiling(ctx, 1); otherwise *launches is 0.
+ *
+ *   avg_ms    host: mean duration of one launch in milliseconds
+ *   launches  host: number of launches averaged
+ */
+mp_status mp_set_profiling(mp_ctx* ctx, int enable);
+mp_status mp_kernel_time(const mp_ctx* ctx, double* avg_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MP_H_ */

@@ -1,0 +1,329 @@
+// Host side of libmp.so: argument checking, context ownership, the iteration
+// driver, and the C ABI declared in include/mp.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "mp_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int64_t kMaxN = 16384;          // the residual is staged whole in LDS
+constexpr int64_t kLdAlign = 64;          // padded column length (floats): 256 B aligned
+constexpr int kMaxChunk = 64;             // iterations enqueued per host check
+constexpr double kNormTol = 1e-4;
+
+mp_status fail(mp_ctx* ctx, mp_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                            \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((ctx), MP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+void free_ctx(mp_ctx* c) {
+  if (!c) return;
+  (void)hipFree(c->psi32);
+  (void)hipFree(c->psiq);
+  (void)hipFree(c->scales);
+  (void)hipFree(c->r_work);
+  (void)hipFree(c->st);
+  (void)hipFree(c->partials);
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+// Enqueue one MP iteration of the FP32 path.
+hipError_t enqueue_iteration(mp_ctx* c, float* x, const mp_trace& tr, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
+  hipError_t e;
+  if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+  e = mp::launch_corr_f32(c->psi32, c->ld, c->m, c->r_work, c->geom, c->partials, c->st, s);
+  if (e != hipSuccess) return e;
+  if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
+  return mp::launch_select_update_f32(c->partials, c->geom.grid, c->psi32, c->ld, c->n, x,
+                                      c->r_work, c->st, tr, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mp_status_str(mp_status s) {
+  switch (s) {
+    case MP_OK: return "MP_OK";
+    case MP_EINVAL: return "MP_EINVAL";
+    case MP_ENOTNORM: return "MP_ENOTNORM";
+    case MP_ENONFINITE: return "MP_ENONFINITE";
+    case MP_ENOMEM: return "MP_ENOMEM";
+    case MP_EDEVICE: return "MP_EDEVICE";
+    case MP_EUNSUPPORTED: return "MP_EUNSUPPORTED";
+  }
+  return "MP_UNKNOWN";
+}
+
+const char* mp_last_error(const mp_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_t ld,
+                    mp_dtype storage, uint32_t flags, void* stream) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, MP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!psi) return fail(nullptr, MP_EINVAL, "psi is NULL");
+  if (n < 1 || m < 1) return fail(nullptr, MP_EINVAL, "n and m must be >= 1");
+  if (ld < n) return fail(nullptr, MP_EINVAL, "ld must be >= n");
+  if (n > kMaxN) return fail(nullptr, MP_EINVAL, "n exceeds 16384");
+  if (m >= (int64_t{1} << 31)) return fail(nullptr, MP_EINVAL, "m must be < 2^31");
+  if (flags & ~MP_SKIP_NORM_CHECK) return fail(nullptr, MP_EINVAL, "unknown flags");
+  if (storage != MP_F32) {
+    if (storage == MP_BF16 || storage == MP_FP8_E4M3)
+      return fail(nullptr, MP_EUNSUPPORTED, "reduced-precision storage is not built yet");
+    return fail(nullptr, MP_EINVAL, "unknown storage type");
+  }
+  int dev = 0;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return fail(nullptr, MP_EDEVICE, "no HIP device");
+  HIP_TRY(nullptr, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(nullptr, hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, MP_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                              ", this library is built for gfx950");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  mp_ctx* c = new mp_ctx();
+  c->device = dev;
+  c->num_cus = prop.multiProcessorCount;
+  c->n = n;
+  c->m = m;
+  c->ld = round_up(n, kLdAlign);
+  c->storage = storage;
+  c->geom = mp::corr_f32_geometry(m, c->num_cus);
+
+  auto bail = [&](mp_status st, const std::string& msg) {
+    free_ctx(c);
+    return fail(nullptr, st, msg);
+  };
+  const size_t psi_bytes = static_cast<size_t>(c->ld) * static_cast<size_t>(m) * sizeof(float);
+  if (hipMalloc(&c->psi32, psi_bytes) != hipSuccess) return bail(MP_ENOMEM, "dictionary copy");
+  if (hipMalloc(&c->r_work, c->ld * sizeof(float)) != hipSuccess) return bail(MP_ENOMEM, "r");
+  if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
+  if (hipMalloc(&c->partials, sizeof(uint64_t) * c->geom.grid) != hipSuccess)
+    return bail(MP_ENOMEM, "partials");
+  if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
+    return bail(MP_ENOMEM, "pinned state");
+
+  hipError_t e = hipMemsetAsync(c->psi32, 0, psi_bytes, s);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(c->psi32, c->ld * sizeof(float), psi, ld * sizeof(float),
+                         n * sizeof(float), m, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
+
+  // Column norms in FP64 (eq. 4): finiteness always, unit norm unless skipped.
+  double* d_norm2 = nullptr;
+  if (hipMalloc(&d_norm2, sizeof(double) * m) != hipSuccess) return bail(MP_ENOMEM, "norms");
+  std::vector<double> norm2(static_cast<size_t>(m));
+  e = mp::launch_norms(c->psi32, c->ld, n, m, d_norm2, nullptr, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(norm2.data(), d_norm2, sizeof(double) * m, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_norm2);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("norms: ") + hipGetErrorString(e));
+  for (int64_t j = 0; j < m; ++j) {
+    if (!isfinite(norm2[j])) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "column %lld holds NaN or Inf", static_cast<long long>(j));
+      return bail(MP_ENONFINITE, buf);
+    }
+    if (!(flags & MP_SKIP_NORM_CHECK) && fabs(sqrt(norm2[j]) - 1.0) > kNormTol) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "column %lld has norm %.9g (must be 1 within 1e-4)",
+               static_cast<long long>(j), sqrt(norm2[j]));
+      return bail(MP_ENOTNORM, buf);
+    }
+  }
+  *out = c;
+  return MP_OK;
+}
+
+void mp_destroy(mp_ctx* ctx) { free_ctx(ctx); }
+
+mp_status mp_set_profiling(mp_ctx* ctx, int enable) {
+  if (!ctx) return MP_EINVAL;
+  if (enable && ctx->ev.empty()) {
+    ctx->ev.resize(2 * 2 * kMaxChunk, nullptr);
+    for (hipEvent_t& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
+  }
+  ctx->profiling = enable != 0;
+  return MP_OK;
+}
+
+mp_status mp_kernel_time(const mp_ctx* ctx, double* avg_ms, int64_t* launches) {
+  if (!ctx || !avg_ms || !launches) return MP_EINVAL;
+  *launches = ctx->prof_launches;
+  *avg_ms = ctx->prof_launches ? ctx->prof_ms / static_cast<double>(ctx->prof_launches) : 0.0;
+  return MP_OK;
+}
+
+mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* stream) {
+  if (!ctx || !codes) return MP_EINVAL;
+  mp_ctx* c = const_cast<mp_ctx*>(ctx);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->storage == MP_F32) {
+    HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(float), c->psi32, c->ld * sizeof(float),
+                                c->n * sizeof(float), c->m, hipMemcpyDeviceToDevice, s));
+  } else {
+    return fail(c, MP_EUNSUPPORTED, "storage not built");
+  }
+  (void)scales;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return MP_OK;
+}
+
+mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
+                   mp_result* res, const mp_trace* trace, void* stream) {
+  if (!ctx) return MP_EINVAL;
+  ctx->err.clear();
+  if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
+  if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
+    return fail(ctx, MP_EINVAL, "eps must be finite and >= 0");
+  if (opts->max_iters < 0) return fail(ctx, MP_EINVAL, "max_iters must be >= 0");
+  if (opts->flags != 0) return fail(ctx, MP_EINVAL, "opts.flags must be 0");
+  if (opts->rescore_k < 0 || opts->rescore_k > 8)
+    return fail(ctx, MP_EINVAL, "rescore_k must be in 0..8");
+  mp_trace tr{};
+  if (trace) {
+    if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
+    tr = *trace;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mp_ctx* c = ctx;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+
+  HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, c->r_work, c->st, opts->eps,
+                             static_cast<long long>(opts->max_iters), s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+
+  // Enqueue chunks of iterations; the kernels themselves stop doing work once
+  // the device state says the run is over.  Two chunks stay in flight: after
+  // enqueuing chunk k the host waits for the state copy that follows chunk k-1.
+  const long long T = opts->max_iters;
+  long long issued = 0;
+  int chunk = 4;
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
+  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
+  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
+  mp::DevState* h_slot = nullptr;
+  if (hipHostMalloc(&h_slot, 2 * sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess) {
+    (void)hipEventDestroy(done_ev[0]);
+    (void)hipEventDestroy(done_ev[1]);
+    return fail(c, MP_ENOMEM, "pinned state slots");
+  }
+  long long slot_base[2] = {0, 0};
+  int slot_len[2] = {0, 0};
+  mp_status status = MP_OK;
+  auto account = [&](int k) {
+    // after chunk slot k has completed: add the kernel time of the launches
+    // that did an iteration (iteration index < t after the chunk)
+    if (!c->profiling) return;
+    const long long t_after = h_slot[k].t;
+    for (int j = 0; j < slot_len[k]; ++j) {
+      if (slot_base[k] + j >= t_after) break;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
+                              c->ev[(k * kMaxChunk + j) * 2 + 1]) == hipSuccess) {
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+      }
+    }
+  };
+  bool finished = c->h_st->done != 0;
+  int next = 0;      // slot the next chunk goes to
+  int inflight = 0;  // chunks enqueued but not yet waited for
+  while (!finished && status == MP_OK) {
+    while (inflight < 2 && issued < T && status == MP_OK) {
+      const int k = next;
+      const int len = static_cast<int>(std::min<long long>(chunk, T - issued));
+      for (int j = 0; j < len; ++j) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->profiling) {
+          e0 = c->ev[(k * kMaxChunk + j) * 2];
+          e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
+        }
+        hipError_t e = enqueue_iteration(c, x, tr, s, e0, e1);
+        if (e != hipSuccess) {
+          status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+          break;
+        }
+      }
+      if (status != MP_OK) break;
+      slot_base[k] = issued;
+      slot_len[k] = len;
+      issued += len;
+      hipError_t e = hipMemcpyAsync(&h_slot[k], c->st, sizeof(mp::DevState),
+                                    hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(done_ev[k], s);
+      if (e != hipSuccess) {
+        status = fail(c, MP_EDEVICE, std::string("state copy: ") + hipGetErrorString(e));
+        break;
+      }
+      ++inflight;
+      next ^= 1;
+      chunk = std::min(chunk * 2, kMaxChunk);
+    }
+    if (status != MP_OK || inflight == 0) break;
+    const int old = inflight == 2 ? next : (next ^ 1);  // the older chunk in flight
+    hipError_t e = hipEventSynchronize(done_ev[old]);
+    if (e != hipSuccess) {
+      status = fail(c, MP_EDEVICE, std::string("sync: ") + hipGetErrorString(e));
+      break;
+    }
+    --inflight;
+    account(old);
+    if (h_slot[old].done) finished = true;
+  }
+  // drain the chunk still in flight (its launches return at once)
+  if (hipStreamSynchronize(s) != hipSuccess && status == MP_OK)
+    status = fail(c, MP_EDEVICE, "stream synchronize failed");
+  (void)hipHostFree(h_slot);
+  (void)hipEventDestroy(done_ev[0]);
+  (void)hipEventDestroy(done_ev[1]);
+  if (status != MP_OK) return status;
+
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  if (r)
+    HIP_TRY(c, hipMemcpyAsync(r, c->r_work, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  const mp::DevState& d = *c->h_st;
+  if (d.reason == mp::kStopNonFinite) return fail(c, MP_ENONFINITE, "y holds NaN or Inf");
+  if (res) {
+    res->iters = d.t;
+    res->yy = d.yy;
+    res->rr = d.rr;
+    res->stop_reason = d.reason;
+    res->reserved = 0;
+  }
+  return MP_OK;
+}
+
+}  // extern "C"

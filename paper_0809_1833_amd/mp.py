@@ -1,0 +1,259 @@
+"""Python binding of libmp.so (include/mp.h): argument marshalling only.
+
+Every step of the decode runs in the library's HIP kernels; this module only
+turns torch device tensors into pointers and sizes, and status codes into
+exceptions.  If libmp.so is missing it raises at import time -- there is no
+fallback.
+
+Low level: :func:`mp_create`, :func:`mp_solve`, :func:`mp_destroy`, ... with
+the C names.  High level: :class:`Decoder`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mp.h")
+
+MP_OK, MP_EINVAL, MP_ENOTNORM, MP_ENONFINITE, MP_ENOMEM, MP_EDEVICE, MP_EUNSUPPORTED = range(7)
+MP_F32, MP_BF16, MP_FP8_E4M3 = 0, 1, 2
+STOP_CONVERGED, STOP_MAX_ITERS, STOP_STALLED, STOP_ZERO_INPUT = 0, 1, 2, 3
+STOP_NAMES = {0: "converged", 1: "max_iters", 2: "stalled", 3: "zero_input"}
+MP_SKIP_NORM_CHECK = 0x1
+DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("max_iters", ctypes.c_int64),
+                ("rescore_k", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("yy", ctypes.c_double), ("rr", ctypes.c_double),
+                ("stop_reason", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("idx", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("rr", ctypes.c_void_p),
+                ("cap", ctypes.c_int64)]
+
+
+class MPError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {_status_str(status)}: {detail}")
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0809_1833_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i64, u32, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32
+    lib.mp_create.restype = ctypes.c_int
+    lib.mp_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), p, i64, i64, i64, ctypes.c_int,
+                              u32, p]
+    lib.mp_solve.restype = ctypes.c_int
+    lib.mp_solve.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
+                             ctypes.POINTER(Trace), p]
+    lib.mp_destroy.restype = None
+    lib.mp_destroy.argtypes = [p]
+    lib.mp_status_str.restype = ctypes.c_char_p
+    lib.mp_status_str.argtypes = [ctypes.c_int]
+    lib.mp_last_error.restype = ctypes.c_char_p
+    lib.mp_last_error.argtypes = [p]
+    lib.mp_get_storage.restype = ctypes.c_int
+    lib.mp_get_storage.argtypes = [p, p, p, p]
+    lib.mp_set_profiling.restype = ctypes.c_int
+    lib.mp_set_profiling.argtypes = [p, ctypes.c_int]
+    lib.mp_kernel_time.restype = ctypes.c_int
+    lib.mp_kernel_time.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    _lib = lib
+    return lib
+
+
+def library():
+    """The loaded ctypes library (raises if libmp.so is not built)."""
+    return _load()
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions include/mp.h declares."""
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    return sorted(set(re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(mp_\w+)\s*\(", text, flags=re.M)))
+
+
+def _status_str(s: int) -> str:
+    try:
+        return _load().mp_status_str(int(s)).decode()
+    except Exception:  # pragma: no cover - library missing
+        return str(s)
+
+
+def _check(status: int, where: str, ctx=None):
+    if status != MP_OK:
+        detail = _load().mp_last_error(ctx).decode(errors="replace")
+        raise MPError(status, where, detail)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ---- C-named wrappers --------------------------------------------------------
+
+def mp_create(psi_ptr: int, n: int, m: int, ld: int, storage: int = MP_F32, flags: int = 0,
+              stream: Optional[int] = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = _load().mp_create(ctypes.byref(h), psi_ptr, n, m, ld, storage, flags, stream)
+    _check(st, "mp_create", None)
+    return h
+
+
+def mp_solve(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
+             trace: Optional[Trace] = None, stream: Optional[int] = None) -> Result:
+    res = Result()
+    st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
+                          ctypes.byref(trace) if trace is not None else None, stream)
+    _check(st, "mp_solve", ctx)
+    return res
+
+
+def mp_destroy(ctx) -> None:
+    _load().mp_destroy(ctx)
+
+
+def mp_status_str(s: int) -> str:
+    return _status_str(s)
+
+
+def mp_last_error(ctx=None) -> str:
+    return _load().mp_last_error(ctx).decode(errors="replace")
+
+
+def mp_get_storage(ctx, codes_ptr: int, scales_ptr: Optional[int], stream=None) -> None:
+    _check(_load().mp_get_storage(ctx, codes_ptr, scales_ptr, stream), "mp_get_storage", ctx)
+
+
+def mp_set_profiling(ctx, enable: bool) -> None:
+    _check(_load().mp_set_profiling(ctx, 1 if enable else 0), "mp_set_profiling", ctx)
+
+
+def mp_kernel_time(ctx):
+    avg = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_load().mp_kernel_time(ctx, ctypes.byref(avg), ctypes.byref(n)), "mp_kernel_time",
+           ctx)
+    return avg.value, n.value
+
+
+# ---- torch-facing convenience ------------------------------------------------
+
+def _check_psi(psi: torch.Tensor):
+    if not psi.is_cuda or psi.dtype != torch.float32 or psi.dim() != 2:
+        raise ValueError("psi must be a 2-D float32 CUDA tensor of shape (N, M)")
+    n, m = psi.shape
+    if psi.stride(0) != 1 and n > 1:
+        raise ValueError("psi must be column-major: stride(0) == 1")
+    ld = psi.stride(1) if m > 1 else n
+    return n, m, max(ld, n)
+
+
+class Decoder:
+    """A dictionary prepared on the GPU (``mp_create``) and decodes against it.
+
+    ``psi``: (N, M) float32 CUDA tensor, column-major (``stride(0) == 1``).
+    ``storage``: ``"f32"``, ``"bf16"`` or ``"fp8"``.
+    """
+
+    def __init__(self, psi: torch.Tensor, storage: str = "f32", check_norms: bool = True,
+                 stream=None):
+        n, m, ld = _check_psi(psi)
+        self.n, self.m, self.storage = n, m, storage
+        flags = 0 if check_norms else MP_SKIP_NORM_CHECK
+        self._ctx = mp_create(psi.data_ptr(), n, m, ld, DTYPES[storage], flags,
+                              _stream_ptr(stream))
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            mp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def solve(self, y: torch.Tensor, eps: float, max_iters: int, x: Optional[torch.Tensor] = None,
+              r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
+              stream=None):
+        """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, trace...)."""
+        if not y.is_cuda or y.dtype != torch.float32 or y.numel() != self.n:
+            raise ValueError("y must be a float32 CUDA tensor of N elements")
+        y = y.contiguous()
+        dev = y.device
+        if x is None:
+            x = torch.empty(self.m, dtype=torch.float32, device=dev)
+        if r is None:
+            r = torch.empty(self.n, dtype=torch.float32, device=dev)
+        tr = None
+        tidx = tcoef = trr = None
+        if trace_cap > 0:
+            tidx = torch.full((trace_cap,), -1, dtype=torch.int32, device=dev)
+            tcoef = torch.zeros(trace_cap, dtype=torch.float32, device=dev)
+            trr = torch.zeros(trace_cap, dtype=torch.float64, device=dev)
+            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+        opts = Opts(float(eps), int(max_iters), int(rescore_k), 0)
+        res = mp_solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
+                       _stream_ptr(stream))
+        out = dict(x=x, r=r, iters=res.iters, yy=res.yy, rr=res.rr,
+                   stop=STOP_NAMES.get(res.stop_reason, res.stop_reason))
+        if tr is not None:
+            k = min(res.iters, trace_cap)
+            out.update(idx=tidx[:k], coef=tcoef[:k], rr_trace=trr[:k])
+        return out
+
+    def storage_copy(self, stream=None):
+        """The dictionary copy the correlation pass streams, unpadded:
+        (codes tensor (N, M) column-major view, scales or None)."""
+        dt = {"f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8}[self.storage]
+        codes = torch.empty((self.m, self.n), dtype=dt, device="cuda")
+        scales = torch.empty(self.m, dtype=torch.float32, device="cuda") \
+            if self.storage == "fp8" else None
+        mp_get_storage(self._ctx, codes.data_ptr(), _ptr(scales), _stream_ptr(stream))
+        return codes.t(), scales
+
+    def set_profiling(self, enable: bool = True):
+        mp_set_profiling(self._ctx, enable)
+
+    def kernel_time(self):
+        """(mean correlation-kernel launch time in ms, launches counted)."""
+        return mp_kernel_time(self._ctx)

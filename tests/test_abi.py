@@ -1,0 +1,69 @@
+"""The C-ABI library loads on a host without a GPU and exports every symbol
+include/mp.h declares; argument checks that need no device answer without one.
+No compute calls are made here."""
+from __future__ import annotations
+
+import ctypes
+
+import pytest
+
+from paper_0809_1833_amd import mp
+
+
+def test_header_declares_the_boundary():
+    names = mp.header_functions()
+    for required in ("mp_create", "mp_solve", "mp_destroy", "mp_status_str", "mp_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mp.library()
+    missing = [f for f in mp.header_functions() if not hasattr(lib, f)]
+    assert missing == []
+
+
+def test_status_strings():
+    assert mp.mp_status_str(mp.MP_OK) == "MP_OK"
+    assert mp.mp_status_str(mp.MP_ENOTNORM) == "MP_ENOTNORM"
+    assert mp.mp_status_str(99) == "MP_UNKNOWN"
+
+
+@pytest.mark.parametrize("kw,detail", [
+    (dict(psi=None), "psi is NULL"),
+    (dict(n=0), "n and m"),
+    (dict(m=0), "n and m"),
+    (dict(ld=3), "ld must be"),
+    (dict(n=16385, ld=16385), "16384"),
+    (dict(m=2 ** 31), "2^31"),
+    (dict(flags=0x10), "flags"),
+    (dict(storage=7), "storage"),
+])
+def test_create_rejects_bad_arguments(kw, detail):
+    args = dict(psi=0x1000, n=4, m=4, ld=4, storage=0, flags=0)
+    args.update(kw)
+    h = ctypes.c_void_p(123)
+    st = mp.library().mp_create(ctypes.byref(h), args["psi"], args["n"], args["m"], args["ld"],
+                                args["storage"], args["flags"], None)
+    assert st == mp.MP_EINVAL
+    assert h.value is None
+    assert detail in mp.mp_last_error(None)
+
+
+def test_create_null_out():
+    assert mp.library().mp_create(None, 0x1000, 4, 4, 4, 0, 0, None) == mp.MP_EINVAL
+
+
+def test_solve_and_destroy_accept_null_context():
+    lib = mp.library()
+    opts = mp.Opts(1e-5, 10, 0, 0)
+    assert lib.mp_solve(None, 1, 1, None, ctypes.byref(opts), None, None, None) == mp.MP_EINVAL
+    lib.mp_destroy(None)
+
+
+def test_create_without_device_reports_edevice():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    st = mp.library().mp_create(ctypes.byref(h), 0x1000, 4, 4, 4, 0, 0, None)
+    assert st == mp.MP_EDEVICE
