@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MP iters/s & achieved HBM GB/s (1 signal); signals/s batched BF16 vs FP32"
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "corr_f32_traffic.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "mp_step_f32_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_0809_1833_amd", "csrc", "k_f32.hip")
 
 WORKLOADS = {
@@ -81,6 +81,10 @@ def main():
     ap.add_argument("--workload", default="c1b", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=16,
+                    help="time every k-th iteration's kernel launch with HIP events")
+    ap.add_argument("--max-iters", type=int, default=None,
+                    help="cap each decode at this many iterations (short profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -96,6 +100,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"[bench] generating {args.workload} seed {args.seed}")
     p = mpgen.make_problem(args.workload, args.seed)
+    if args.max_iters is not None:
+        p.max_iters = min(p.max_iters, args.max_iters)
     n, m = p.n, p.m
     psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
     y = torch.from_numpy(p.y).cuda()
@@ -107,7 +113,7 @@ def main():
     log("[bench] warmup")
     for _ in range(args.warmup):
         dec.solve(y, p.eps, p.max_iters, x=x, r=r)
-    dec.set_profiling(True)
+    dec.set_profiling(args.profile_every)
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} decodes")
     iters = 0
@@ -123,7 +129,7 @@ def main():
         stops.add(out["stop"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    dec.set_profiling(False)
+    dec.set_profiling(0)
     log(f"[bench] {iters} iterations in {dt:.3f} s")
 
     bytes_per_launch = 4.0 * n * m + 4.0 * n          # dictionary + residual, once each
@@ -146,11 +152,12 @@ def main():
         "data": "synthetic (seeded Gaussian unit-column dictionary, K-sparse N(0,1) signal)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "iters_per_decode": iters // max(args.steps, 1),
-                   "stop": sorted(stops), "seed": args.seed},
+                   "stop": sorted(stops), "seed": args.seed,
+                   "max_iters": p.max_iters},
         "effective_gbps_whole_step": round(iters * bytes_per_iter / dt / 1e9, 2),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_corr_f32",
+            "kernel": "k_mp_step_f32",
             "achieved": round(achieved, 2) if achieved else None,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -20,8 +20,7 @@
  *    is therefore contiguous.
  *  - Pointers documented as "device" must point to memory of the current HIP
  *    device; "host" pointers to ordinary host memory.  The library never
- *    frees caller memory and never keeps a caller pointer past the call,
- *    except where MP_BORROW_PSI says otherwise.
+ *    frees caller memory and never keeps a caller pointer past the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
  *    is ordered on that stream; every mp_solve* call returns only after its
  *    decode has finished (the host needs the device's stop flag to know when
@@ -177,16 +176,19 @@ const char* mp_last_error(const mp_ctx* ctx);
 mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* stream);
 
 /*
- * mp_kernel_time -- per-launch timing of the correlation kernel (the pass
- * over the whole dictionary, eq. 9) during the last mp_solve, measured with
- * HIP events on the stream it ran on.  Only launches that performed an
- * iteration are counted.  Timing is recorded only while enabled with
- * mp_set_profiling(ctx, 1); otherwise *launches is 0.
+ * mp_set_profiling / mp_kernel_time -- per-launch timing of the kernel that
+ * makes one MP iteration (the pass over the whole dictionary, eq. 9, with the
+ * selection and update of eqs. 10-12 at its tail) during the last mp_solve,
+ * measured with HIP events recorded around the launch on the decode stream.
  *
- *   avg_ms    host: mean duration of one launch in milliseconds
- *   launches  host: number of launches averaged
+ *   every     0: off.  k > 0: time every k-th iteration's launch (events
+ *             around every launch add a little time between launches).
+ *   avg_ms    host: mean duration of one timed launch in milliseconds
+ *   launches  host: number of launches averaged (only launches that performed
+ *             an iteration are counted; 0 when profiling is off)
+ * Errors: MP_EINVAL (NULL ctx or outputs, every < 0), MP_EDEVICE.
  */
-mp_status mp_set_profiling(mp_ctx* ctx, int enable);
+mp_status mp_set_profiling(mp_ctx* ctx, int every);
 mp_status mp_kernel_time(const mp_ctx* ctx, double* avg_ms, int64_t* launches);
 
 #ifdef __cplusplus

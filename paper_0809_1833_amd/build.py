@@ -14,6 +14,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmp.so")
+PROBE_SRC = os.path.join(HERE, "probe", "stream_probe.hip")
+PROBE = os.path.join(HERE, "probe", "stream_probe")
 ROOT = os.path.dirname(HERE)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -65,7 +67,21 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for o in objs:
         os.remove(o)
     os.rmdir(objdir)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The streaming-bandwidth / counter-calibration probe (an executable)."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, *FLAGS, PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("probe build failed:\n" + r.stdout.decode(errors="replace"))
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":

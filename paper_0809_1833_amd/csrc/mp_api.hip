@@ -51,11 +51,11 @@ hipError_t enqueue_iteration(mp_ctx* c, float* x, const mp_trace& tr, hipStream_
                              hipEvent_t e0, hipEvent_t e1) {
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-  e = mp::launch_corr_f32(c->psi32, c->ld, c->m, c->r_work, c->geom, c->partials, c->st, s);
+  e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials, x,
+                             c->st, tr, s);
   if (e != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
-  return mp::launch_select_update_f32(c->partials, c->geom.grid, c->psi32, c->ld, c->n, x,
-                                      c->r_work, c->st, tr, s);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -134,6 +134,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
     e = hipMemcpy2DAsync(c->psi32, c->ld * sizeof(float), psi, ld * sizeof(float),
                          n * sizeof(float), m, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * c->geom.grid, s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
 
   // Column norms in FP64 (eq. 4): finiteness always, unit norm unless skipped.
@@ -165,13 +166,15 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
 
 void mp_destroy(mp_ctx* ctx) { free_ctx(ctx); }
 
-mp_status mp_set_profiling(mp_ctx* ctx, int enable) {
+mp_status mp_set_profiling(mp_ctx* ctx, int every) {
   if (!ctx) return MP_EINVAL;
-  if (enable && ctx->ev.empty()) {
+  if (every < 0) return fail(ctx, MP_EINVAL, "every must be >= 0");
+  if (every > 0 && ctx->ev.empty()) {
     ctx->ev.resize(2 * 2 * kMaxChunk, nullptr);
     for (hipEvent_t& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
   }
-  ctx->profiling = enable != 0;
+  ctx->profiling = every > 0;
+  ctx->prof_every = every > 0 ? every : 1;
   return MP_OK;
 }
 
@@ -249,6 +252,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     const long long t_after = h_slot[k].t;
     for (int j = 0; j < slot_len[k]; ++j) {
       if (slot_base[k] + j >= t_after) break;
+      if ((slot_base[k] + j) % c->prof_every != 0) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
                               c->ev[(k * kMaxChunk + j) * 2 + 1]) == hipSuccess) {
@@ -266,7 +270,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
       const int len = static_cast<int>(std::min<long long>(chunk, T - issued));
       for (int j = 0; j < len; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->profiling) {
+        if (c->profiling && (issued + j) % c->prof_every == 0) {
           e0 = c->ev[(k * kMaxChunk + j) * 2];
           e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
         }
@@ -316,6 +320,8 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   HIP_TRY(c, hipStreamSynchronize(s));
   const mp::DevState& d = *c->h_st;
   if (d.reason == mp::kStopNonFinite) return fail(c, MP_ENONFINITE, "y holds NaN or Inf");
+  if (d.reason == mp::kStopInternal)
+    return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
   if (res) {
     res->iters = d.t;
     res->yy = d.yy;

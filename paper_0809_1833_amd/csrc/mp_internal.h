@@ -11,11 +11,14 @@
 
 namespace mp {
 
-// Stop reason used internally for a non-finite y; the API maps it to MP_ENONFINITE.
+// Stop reasons used internally: a non-finite y (the API maps it to
+// MP_ENONFINITE) and a selected index outside the dictionary, which a correct
+// run never produces (MP_EDEVICE).
 constexpr int kStopNonFinite = -1;
+constexpr int kStopInternal = -2;
 
 // Solver state of one decode, resident in device memory for the whole run.
-// Written only by the single-workgroup select/update kernels (and init).
+// Written by k_init and by the last workgroup of each iteration's launch.
 struct alignas(64) DevState {
   double yy;            // ||y||^2
   double rr;            // ||r||^2 of the current residual
@@ -24,7 +27,9 @@ struct alignas(64) DevState {
   long long max_iters;  // cap T
   int done;             // 1 once the run has stopped
   int reason;           // MP_STOP_* or kStopNonFinite
-  int pad[6];
+  unsigned arrive;      // workgroups of the current launch that have published a key
+  int pad0;
+  int pad[4];
 };
 
 // A candidate packed into one 64-bit key so that "larger key" means larger
@@ -62,12 +67,9 @@ hipError_t launch_norms(const float* psi, int64_t ld, int64_t n, int64_t m, doub
                         int* nonfinite, hipStream_t s);
 hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t m, float* r,
                        DevState* st, double eps, long long max_iters, hipStream_t s);
-hipError_t launch_corr_f32(const float* psi, int64_t ld, int64_t m, const float* r,
-                           const CorrGeom& g, uint64_t* partials, const DevState* st,
-                           hipStream_t s);
-hipError_t launch_select_update_f32(const uint64_t* partials, int np, const float* psi,
-                                    int64_t ld, int64_t n, float* x, float* r, DevState* st,
-                                    mp_trace tr, hipStream_t s);
+hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* r,
+                              const CorrGeom& g, uint64_t* keys, float* x, DevState* st,
+                              mp_trace tr, hipStream_t s);
 
 }  // namespace mp
 
@@ -88,6 +90,7 @@ struct mp_ctx {
   mp::CorrGeom geom{};
   // profiling of the correlation kernel
   bool profiling = false;
+  int prof_every = 1;            // time every prof_every-th launch
   std::vector<hipEvent_t> ev;    // 2 slots x 2 events x max chunk
   double prof_ms = 0.0;
   int64_t prof_launches = 0;

@@ -152,8 +152,8 @@ def mp_get_storage(ctx, codes_ptr: int, scales_ptr: Optional[int], stream=None) 
     _check(_load().mp_get_storage(ctx, codes_ptr, scales_ptr, stream), "mp_get_storage", ctx)
 
 
-def mp_set_profiling(ctx, enable: bool) -> None:
-    _check(_load().mp_set_profiling(ctx, 1 if enable else 0), "mp_set_profiling", ctx)
+def mp_set_profiling(ctx, every: int) -> None:
+    _check(_load().mp_set_profiling(ctx, int(every)), "mp_set_profiling", ctx)
 
 
 def mp_kernel_time(ctx):
@@ -251,8 +251,9 @@ class Decoder:
         mp_get_storage(self._ctx, codes.data_ptr(), _ptr(scales), _stream_ptr(stream))
         return codes.t(), scales
 
-    def set_profiling(self, enable: bool = True):
-        mp_set_profiling(self._ctx, enable)
+    def set_profiling(self, every: int = 1):
+        """Time every ``every``-th iteration's launch (0 = off)."""
+        mp_set_profiling(self._ctx, int(every))
 
     def kernel_time(self):
         """(mean correlation-kernel launch time in ms, launches counted)."""

@@ -1,0 +1,85 @@
+"""Turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into HBM bytes per launch.
+
+Each counter is read in KiB per dispatch.  The scale factor of each counter
+comes from the probe's copy kernel, whose bytes read and written are known
+exactly: factor = known bytes / (counter KiB * 1024).  The result is written
+as JSON (by default ``profiles/<kernel>_traffic.json``) together with the
+SHA-256 prefix of the kernel's source file, so a benchmark can tell when the
+kernel has changed since the counters were taken.
+
+Usage (after the four counter runs described in the profile summaries):
+
+    python -m paper_0809_1833_amd.probe.traffic --kernel k_mp_step_f32 \\
+        --source paper_0809_1833_amd/csrc/k_f32.hip --n 8192 --m 32768 \\
+        --fetch gpurun_out/pmc_FETCH_SIZE --write gpurun_out/pmc_WRITE_SIZE \\
+        --copy-bytes 1073741824 --out profiles/mp_step_f32_traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+
+def _mean_counter(path: str, kernel_substr: str) -> tuple:
+    vals = []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if kernel_substr in row["Kernel_Name"]:
+                vals.append(float(row["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no dispatch of {kernel_substr} in {path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def source_sha(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--source", required=True)
+    ap.add_argument("--n", type=int, required=True)
+    ap.add_argument("--m", type=int, required=True)
+    ap.add_argument("--fetch", required=True, help="directory of the FETCH_SIZE runs")
+    ap.add_argument("--write", required=True, help="directory of the WRITE_SIZE runs")
+    ap.add_argument("--bench-prefix", default="bench")
+    ap.add_argument("--copy-prefix", default="copy")
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--algorithmic-bytes", type=float, default=None)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+
+    f_k, nf = _mean_counter(os.path.join(a.fetch, f"{a.bench_prefix}_counter_collection.csv"),
+                            a.kernel)
+    w_k, nw = _mean_counter(os.path.join(a.write, f"{a.bench_prefix}_counter_collection.csv"),
+                            a.kernel)
+    f_c, _ = _mean_counter(os.path.join(a.fetch, f"{a.copy_prefix}_counter_collection.csv"),
+                           "k_copy")
+    w_c, _ = _mean_counter(os.path.join(a.write, f"{a.copy_prefix}_counter_collection.csv"),
+                           "k_copy")
+    f_scale = a.copy_bytes / (f_c * 1024.0)
+    w_scale = a.copy_bytes / (w_c * 1024.0)
+    fetch = f_k * 1024.0 * f_scale
+    write = w_k * 1024.0 * w_scale
+    out = dict(kernel=a.kernel, kernel_sha=source_sha(a.source), n=a.n, m=a.m,
+               fetch_kib_per_dispatch=f_k, write_kib_per_dispatch=w_k,
+               dispatches=dict(fetch=nf, write=nw),
+               copy_fetch_kib=f_c, copy_write_kib=w_c, copy_bytes=a.copy_bytes,
+               fetch_scale=f_scale, write_scale=w_scale,
+               fetch_bytes_per_launch=round(fetch), write_bytes_per_launch=round(write),
+               bytes_per_launch=round(fetch + write))
+    if a.algorithmic_bytes:
+        out["algorithmic_bytes_per_launch"] = a.algorithmic_bytes
+        out["traffic_over_algorithmic"] = (fetch + write) / a.algorithmic_bytes
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -218,7 +218,14 @@ def test_storage_copy_is_exact():
 def test_profiling_counts_real_launches():
     p = mpgen.make_problem("c0", 0)
     with _decoder(p.psi) as dec:
-        dec.set_profiling(True)
+        dec.set_profiling(1)
         out = dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
         ms, n = dec.kernel_time()
-    assert n == out["iters"] and ms > 0
+        assert n == out["iters"] and ms > 0
+        dec.set_profiling(4)
+        out = dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
+        ms, n = dec.kernel_time()
+        assert n == (out["iters"] + 3) // 4 and ms > 0
+        dec.set_profiling(0)
+        dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
+        assert dec.kernel_time()[1] == 0
