@@ -33,6 +33,8 @@ WORKLOADS = {
     "c1b": "N=8192, M=32768 (FP32 dictionary 1 GiB), K=512, eps=1e-5, T=10240, single signal",
     "c1a": "N=2048, M=8192 (FP32 dictionary 64 MiB), K=128, eps=1e-5, T=2560, single signal",
     "c0": "N=256, M=1024, K=10, eps=1e-6, T=2000, single signal",
+    "c2": "N=8192, M=32768, K=256, eps=1e-5, T=5120, single signal, reduced-precision dictionary "
+          "with FP32 re-scoring of the 8 best candidates",
 }
 
 
@@ -80,6 +82,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1b", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8"],
+                    help="dictionary copy the correlation pass streams")
+    ap.add_argument("--dist", default="normal", choices=["normal", "loguniform"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every k-th iteration's kernel launch with HIP events")
@@ -99,14 +104,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"[bench] generating {args.workload} seed {args.seed}")
-    p = mpgen.make_problem(args.workload, args.seed)
+    p = mpgen.make_problem(args.workload, args.seed, dist=args.dist)
     if args.max_iters is not None:
         p.max_iters = min(p.max_iters, args.max_iters)
     n, m = p.n, p.m
     psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
     y = torch.from_numpy(p.y).cuda()
     stream = torch.cuda.current_stream()
-    dec = Decoder(psi)
+    dec = Decoder(psi, storage=args.storage)
     del psi
     x = torch.empty(m, dtype=torch.float32, device="cuda")
     r = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -132,11 +137,19 @@ def main():
     dec.set_profiling(0)
     log(f"[bench] {iters} iterations in {dt:.3f} s")
 
-    bytes_per_launch = 4.0 * n * m + 4.0 * n          # dictionary + residual, once each
-    bytes_per_iter = 4.0 * n * m + 12.0 * n           # + chosen column, residual read/write
+    # algorithmic bytes of one iteration's launch: the dictionary copy once,
+    # r once, and for the reduced-precision forms the FP8 scales and the 8
+    # FP32 candidate columns re-scored
+    esize = {"f32": 4.0, "bf16": 2.0, "fp8": 1.0}[args.storage]
+    bytes_per_launch = esize * n * m + 4.0 * n
+    if args.storage == "fp8":
+        bytes_per_launch += 4.0 * m
+    if args.storage != "f32":
+        bytes_per_launch += 8 * 4.0 * n
+    bytes_per_iter = bytes_per_launch + 8.0 * n       # + residual read and written by the update
     avg_ms = kt_ms / max(kt_n, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kt_n else None
-    traffic = traffic_from_counters(n, m)
+    traffic = traffic_from_counters(n, m) if args.storage == "f32" else None
     line = {
         "metric": METRIC,
         "value": round(iters / dt, 3),
@@ -148,16 +161,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"f32": "f32", "bf16": "bf16 storage, f32 accumulate",
+                  "fp8": "fp8-e4m3 storage, f32 accumulate"}[args.storage],
         "data": "synthetic (seeded Gaussian unit-column dictionary, K-sparse N(0,1) signal)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "storage": args.storage, "dist": args.dist,
                    "iters_per_decode": iters // max(args.steps, 1),
                    "stop": sorted(stops), "seed": args.seed,
                    "max_iters": p.max_iters},
         "effective_gbps_whole_step": round(iters * bytes_per_iter / dt / 1e9, 2),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_mp_step_f32",
+            "kernel": "k_mp_step_f32" if args.storage == "f32" else "k_mp_step_lp",
             "achieved": round(achieved, 2) if achieved else None,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -116,7 +116,9 @@ typedef struct mp_trace {
  *   ld       leading dimension, ld >= n
  *   storage  which copy the correlation pass streams (mp_dtype).  MP_BF16 and
  *            MP_FP8_E4M3 keep an FP32 master as well, for re-scoring and the
- *            residual update.
+ *            residual update: each pass keeps the 8 best reduced-precision
+ *            candidates, re-computes up to opts.rescore_k of them in FP32 and
+ *            selects the best re-computed one (smallest index on ties).
  *   flags    MP_SKIP_NORM_CHECK or 0
  *   stream   hipStream_t as void*
  *
@@ -124,7 +126,8 @@ typedef struct mp_trace {
  * the caller may free psi when mp_create returns.
  * Errors: MP_EINVAL (NULL, n < 1, m < 1, ld < n, size limits, unknown storage
  * or flags), MP_ENONFINITE, MP_ENOTNORM, MP_ENOMEM, MP_EDEVICE,
- * MP_EUNSUPPORTED (the device is not gfx950).
+ * MP_EUNSUPPORTED (the device is not gfx950, or it has more than 256 compute
+ * units).
  */
 mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_t ld,
                     mp_dtype storage, uint32_t flags, void* stream);

@@ -8,9 +8,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mp_internal.h"
+
 namespace mp {
 
 constexpr int kWave = 64;
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 __device__ inline float wave_sum(float v) {
 #pragma unroll
@@ -60,6 +64,145 @@ __device__ inline uint64_t block_max(uint64_t v, uint64_t* red) {
   s = wave_max(s);
   __syncthreads();
   return s;
+}
+
+// ---- FP32 inner product of one column with the LDS copy of r ----------------
+
+// U loads of 16 bytes in flight per lane, then U x 4 FMAs against the LDS
+// copy of r; advances i by 64 * U float4s.
+template <int U>
+__device__ inline void dot_block(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
+                                 int& i, float& acc) {
+  v4f a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const v4f b = r_lds[i + kWave * u];
+    acc = __builtin_fmaf(a[u].x, b.x, acc);
+    acc = __builtin_fmaf(a[u].y, b.y, acc);
+    acc = __builtin_fmaf(a[u].z, b.z, acc);
+    acc = __builtin_fmaf(a[u].w, b.w, acc);
+  }
+  i += kWave * U;
+}
+
+// <r, psi_col> for one column by one wave: blocks of 16 loads per lane while
+// they fit, then at most one block each of 8, 4, 2 and 1 (so short columns
+// still have several loads in flight), then a butterfly sum.
+__device__ inline float dot_column_f32(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
+                                       int ld4, int lane) {
+  float acc = 0.0f;
+  int i = lane;
+  while (i + kWave * 15 < ld4) dot_block<16>(p, r_lds, i, acc);
+  if (i + kWave * 7 < ld4) dot_block<8>(p, r_lds, i, acc);
+  if (i + kWave * 3 < ld4) dot_block<4>(p, r_lds, i, acc);
+  if (i + kWave * 1 < ld4) dot_block<2>(p, r_lds, i, acc);
+  if (i < ld4) dot_block<1>(p, r_lds, i, acc);
+  return wave_sum(acc);
+}
+
+// ---- hand-off from all workgroups of a launch to the last one ---------------
+//
+// Each workgroup publishes K keys into its own K slots of `keys` and counts
+// itself in; publish_arrive returns true (in every thread) only in the
+// workgroup that arrives last.
+//
+// The key slots and the arrival counter are only ever touched with atomic
+// read-modify-write operations at device scope.  Each one is performed at
+// the device's point of coherence for atomics and returns only once
+// performed, and every RMW returns the latest value of its word.  A
+// workgroup swaps its keys into its slots, waits for those swaps to return,
+// then increments the counter; the workgroup whose increment returns grid-1
+// issues its reads (take_slot: a swap with zero, which also clears the slot
+// for the next launch) after that, so they return the keys stored in this
+// launch.  Plain or relaxed loads are never used for these words: a relaxed
+// load is not ordered after other workgroups' RMWs and could return an older
+// value.  No cache write-back or invalidate is needed; everything else the
+// last workgroup reads was written by earlier launches.
+//
+// `mine` must hold the workgroup's j-th key in lane j of wave 0, j < K.
+template <int K>
+__device__ inline bool publish_arrive(uint64_t mine, uint64_t* keys, DevState* st) {
+  static_assert(K >= 1 && K <= kWave, "K keys per workgroup");
+  __shared__ int s_last;
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    uint64_t old = 0;
+    if (lane < K)
+      old = __hip_atomic_exchange(keys + static_cast<size_t>(blockIdx.x) * K + lane, mine,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Keys never have bit 63 set, so inc is 1; computing it from every lane's
+    // returned value makes the increment wait for all K swaps to be performed.
+    const unsigned long long high = __ballot((old >> 63) != 0);
+    if (lane == 0) {
+      const unsigned inc = 1u + (high != 0ull ? 1u : 0u);
+      const unsigned prev =
+          __hip_atomic_fetch_add(&st->arrive, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int last = prev == gridDim.x - 1;
+      if (last)
+        (void)__hip_atomic_exchange(&st->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = last;
+    }
+  }
+  __syncthreads();
+  return s_last != 0;
+}
+
+// Read (and clear) one published key slot; only in the last workgroup.
+__device__ inline uint64_t take_slot(uint64_t* slot) {
+  return __hip_atomic_exchange(slot, uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Selection and update, run by the last workgroup of a launch (NT threads).
+// `best` is the launch's winning key (largest |c|, smallest index).
+template <int NT>
+__device__ void select_update_tail(uint64_t best, const float* __restrict__ psi, int64_t ld,
+                                   int64_t n, int64_t m, float* __restrict__ x,
+                                   float* __restrict__ r, DevState* __restrict__ st,
+                                   const mp_trace& tr, double* dred) {
+  const int idx = key_index(best);
+  const float c = key_value(best);
+  if (idx < 0 || idx >= m) {  // cannot happen for a key a workgroup published
+    if (threadIdx.x == 0) {
+      st->done = 1;
+      st->reason = kStopInternal;
+    }
+    return;
+  }
+  if (c == 0.0f) {  // no atom correlates with r: MP cannot make progress
+    if (threadIdx.x == 0) {
+      st->done = 1;
+      st->reason = MP_STOP_STALLED;
+    }
+    return;
+  }
+  const float* col = psi + static_cast<int64_t>(idx) * ld;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    const float v = __builtin_fmaf(-c, col[i], r[i]);
+    r[i] = v;
+    s += static_cast<double>(v) * v;
+  }
+  const double rr = block_sum<NT>(s, dred);
+  if (threadIdx.x == 0) {
+    x[idx] += c;
+    const long long t = st->t;
+    if (t < tr.cap) {
+      if (tr.idx) tr.idx[t] = idx;
+      if (tr.coef) tr.coef[t] = c;
+      if (tr.rr) tr.rr[t] = rr;
+    }
+    st->t = t + 1;
+    st->rr = rr;
+    if (!(rr > st->thr)) {
+      st->done = 1;
+      st->reason = MP_STOP_CONVERGED;
+    } else if (t + 1 >= st->max_iters) {
+      st->done = 1;
+      st->reason = MP_STOP_MAX_ITERS;
+    }
+  }
 }
 
 }  // namespace mp

@@ -13,8 +13,6 @@
 
 namespace mp {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-
 // ---------------------------------------------------------------------------
 // Column norms (set-up check of eq. 4): norm2[m] = sum_n psi_nm^2 in FP64.
 // One wave per column.
@@ -104,141 +102,12 @@ hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t 
 // streams each column with 16-byte non-temporal loads (lane l reads float4s
 // l, l+64, ...), UNROLL loads in flight per lane, FP32 FMA accumulation,
 // then a butterfly sum across the wave.  Keys are max-reduced per wave and
-// across the 16 waves; each workgroup publishes its key and counts itself in.  The workgroup that arrives last (nobody waits: it is
+// across the 16 waves; each workgroup publishes its key and counts itself in
+// (publish_arrive).  The workgroup that arrives last (nobody waits: it is
 // simply the one that sees the count reach the grid size) takes the winning
 // key, updates x~ and r, computes ||r||^2 in FP64 and applies the stopping
 // test.
 constexpr int kCorrThreads = 1024;
-constexpr int kCorrUnroll = 16;
-
-// U loads of 16 bytes in flight per lane, then U x 4 FMAs against the LDS
-// copy of r; advances i by 64 * U float4s.
-template <int U>
-__device__ inline void dot_block(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
-                                 int& i, float& acc) {
-  v4f a[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(p + i + kWave * u);
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const v4f b = r_lds[i + kWave * u];
-    acc = __builtin_fmaf(a[u].x, b.x, acc);
-    acc = __builtin_fmaf(a[u].y, b.y, acc);
-    acc = __builtin_fmaf(a[u].z, b.z, acc);
-    acc = __builtin_fmaf(a[u].w, b.w, acc);
-  }
-  i += kWave * U;
-}
-
-// <r, psi_col> for one column by one wave: blocks of 16 loads per lane while
-// they fit, then at most one block each of 8, 4, 2 and 1 (so short columns
-// still have several loads in flight), then a butterfly sum.
-__device__ inline float dot_column_f32(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
-                                       int ld4, int lane) {
-  float acc = 0.0f;
-  int i = lane;
-  while (i + kWave * (kCorrUnroll - 1) < ld4) dot_block<kCorrUnroll>(p, r_lds, i, acc);
-  if (i + kWave * 7 < ld4) dot_block<8>(p, r_lds, i, acc);
-  if (i + kWave * 3 < ld4) dot_block<4>(p, r_lds, i, acc);
-  if (i + kWave * 1 < ld4) dot_block<2>(p, r_lds, i, acc);
-  if (i < ld4) dot_block<1>(p, r_lds, i, acc);
-  return wave_sum(acc);
-}
-
-// Selection and update, run by the last workgroup of a launch (NT threads).
-// `best` is the launch's winning key (largest |c|, smallest index).
-template <int NT>
-__device__ void select_update_tail(uint64_t best, const float* __restrict__ psi, int64_t ld,
-                                   int64_t n, int64_t m, float* __restrict__ x,
-                                   float* __restrict__ r, DevState* __restrict__ st,
-                                   const mp_trace& tr, double* dred) {
-  const int idx = key_index(best);
-  const float c = key_value(best);
-  if (idx < 0 || idx >= m) {  // cannot happen for a key a workgroup published
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = kStopInternal;
-    }
-    return;
-  }
-  if (c == 0.0f) {  // no atom correlates with r: MP cannot make progress
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = MP_STOP_STALLED;
-    }
-    return;
-  }
-  const float* col = psi + static_cast<int64_t>(idx) * ld;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) {
-    const float v = __builtin_fmaf(-c, col[i], r[i]);
-    r[i] = v;
-    s += static_cast<double>(v) * v;
-  }
-  const double rr = block_sum<NT>(s, dred);
-  if (threadIdx.x == 0) {
-    x[idx] += c;
-    const long long t = st->t;
-    if (t < tr.cap) {
-      if (tr.idx) tr.idx[t] = idx;
-      if (tr.coef) tr.coef[t] = c;
-      if (tr.rr) tr.rr[t] = rr;
-    }
-    st->t = t + 1;
-    st->rr = rr;
-    if (!(rr > st->thr)) {
-      st->done = 1;
-      st->reason = MP_STOP_CONVERGED;
-    } else if (t + 1 >= st->max_iters) {
-      st->done = 1;
-      st->reason = MP_STOP_MAX_ITERS;
-    }
-  }
-}
-
-// Publish a workgroup's key and count the workgroup in; returns true in the
-// workgroup that arrives last, together with the launch's winning key.
-//
-// The key slots and the arrival counter are only ever touched with atomic
-// read-modify-write operations at device scope.  Each one is performed at
-// the device's point of coherence for atomics and returns only once
-// performed, and every RMW returns the latest value of its word.  A
-// workgroup swaps its key into its own slot, waits for that swap to return,
-// then increments the counter; the workgroup whose increment returns grid-1
-// issues its reads after that, so each of its swaps-with-zero returns the
-// key stored in this launch (and leaves the slot cleared for the next one).
-// Plain or relaxed loads are not used for these words: a relaxed load is not
-// ordered after the other workgroups' RMWs and could return an older value.
-// No cache write-back or invalidate is needed; everything else the tail
-// reads was written by earlier launches.
-template <int NT>
-__device__ inline bool publish_and_arrive(uint64_t key, uint64_t* keys, DevState* st,
-                                          uint64_t* kred, uint64_t* winner) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    const uint64_t old =
-        __hip_atomic_exchange(keys + blockIdx.x, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // Keys never have bit 63 set, so inc is 1; computing it from `old` makes
-    // the increment wait for the exchange to have been performed.
-    const unsigned inc = 1u + static_cast<unsigned>(old >> 63);
-    const unsigned prev =
-        __hip_atomic_fetch_add(&st->arrive, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int last = prev == gridDim.x - 1;
-    if (last)
-      (void)__hip_atomic_exchange(&st->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = last;
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  uint64_t best = 0;
-  for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += NT) {
-    const uint64_t k =
-        __hip_atomic_exchange(keys + i, uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    best = k > best ? k : best;
-  }
-  *winner = block_max<NT>(best, kred);
-  return true;
-}
 
 __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
     const float* __restrict__ psi, int64_t ld, int64_t n, int64_t m, float* __restrict__ r,
@@ -264,8 +133,14 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
     best = k > best ? k : best;
   }
   best = block_max<kCorrThreads>(best, kred);
+  if (!publish_arrive<1>(best, keys, st)) return;
+  // last workgroup: the launch's winner is the largest published key
   uint64_t winner = 0;
-  if (!publish_and_arrive<kCorrThreads>(best, keys, st, kred, &winner)) return;
+  for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += kCorrThreads) {
+    const uint64_t k = take_slot(keys + i);
+    winner = k > winner ? k : winner;
+  }
+  winner = block_max<kCorrThreads>(winner, kred);
   select_update_tail<kCorrThreads>(winner, psi, ld, n, m, x, r, st, tr, dred);
 }
 

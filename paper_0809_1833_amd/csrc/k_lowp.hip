@@ -1,0 +1,311 @@
+// Reduced-precision dictionary forms of the MP iteration for gfx950.
+//
+// The correlation pass (eq. 9) streams a BF16 copy of the dictionary, or an
+// FP8 (OCP E4M3, "e4m3fn") copy with one FP32 scale per column, and
+// accumulates in FP32 against the FP32 residual.  Because the reduced
+// precision can reorder near-equal correlations, each pass keeps the 8 best
+// candidates rather than 1; the last workgroup re-scores up to 8 of them
+// against the FP32 columns (the same FP32 inner product the FP32 form
+// computes) and takes the best of those, smallest index on ties (eq. 16).
+// The coefficient and residual updates (eqs. 10-11) and the FP64 stopping
+// test then use the FP32 column and the re-scored FP32 coefficient.
+//
+// Set-up quantisers:
+//   BF16  round to nearest even of the FP32 value.
+//   FP8   s_m = fp32(max_n |psi_nm| / 448) (1 for an all-zero column);
+//         code = round-to-nearest-even of fp32(psi_nm / s_m), saturating at
+//         +-448 (the largest finite e4m3fn value).
+#include "k_common.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+constexpr int kLpThreads = 1024;
+constexpr int kLpWaves = kLpThreads / kWave;
+constexpr int kTopK = 8;
+
+// ---------------------------------------------------------------------------
+// Quantisers
+
+__device__ inline uint16_t bf16_rne(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// FP32 -> e4m3fn code, round to nearest even, saturating at 448.
+__device__ inline uint8_t fp8_e4m3_rne_sat(float v) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const float a = __builtin_fabsf(v);
+  uint32_t code;
+  if (!(a < 448.0f)) {
+    code = 0x7Eu;  // saturate (a value at or above the largest finite one)
+  } else if (a < 0.015625f) {
+    // below 2^-6 the representable values are the multiples of 2^-9 (the
+    // subnormals, then 2^-6 itself as code 8); a * 512 is exact
+    code = static_cast<uint32_t>(__builtin_rintf(a * 512.0f));
+  } else {
+    const uint32_t au = __builtin_bit_cast(uint32_t, a);
+    int e = static_cast<int>(au >> 23) - 127;  // -6 .. 8
+    const uint32_t mant = au & 0x7FFFFFu;
+    uint32_t m3 = mant >> 20;                   // 3 kept mantissa bits
+    const uint32_t rem = mant & 0xFFFFFu;       // 20 dropped bits
+    if (rem > 0x80000u || (rem == 0x80000u && (m3 & 1u))) ++m3;
+    if (m3 == 8u) {
+      m3 = 0u;
+      ++e;
+    }
+    code = (static_cast<uint32_t>(e + 7) << 3) | m3;  // a < 448 keeps this <= 0x7E
+  }
+  return static_cast<uint8_t>(code | sign);
+}
+
+__global__ __launch_bounds__(256) void k_quant_bf16(const float* __restrict__ psi, int64_t count,
+                                                    uint16_t* __restrict__ out) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += stride)
+    out[i] = bf16_rne(psi[i]);
+}
+
+// One wave per column: the column's largest |psi|, its scale, then the codes
+// (padding rows hold 0 and get code 0).
+__global__ __launch_bounds__(256) void k_quant_fp8(const float* __restrict__ psi, int64_t ld,
+                                                   int64_t m, uint8_t* __restrict__ out,
+                                                   float* __restrict__ scales) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t col = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / kWave;
+  if (col >= m) return;
+  const float* p = psi + col * ld;
+  float amax = 0.0f;
+  for (int64_t i = lane; i < ld; i += kWave) amax = __builtin_fmaxf(amax, __builtin_fabsf(p[i]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = __builtin_fmaxf(amax, __shfl_xor(amax, off, kWave));
+  const float s = amax == 0.0f ? 1.0f : amax / 448.0f;
+  if (lane == 0) scales[col] = s;
+  uint8_t* q = out + col * ld;
+  for (int64_t i = lane; i < ld; i += kWave) q[i] = fp8_e4m3_rne_sat(p[i] / s);
+}
+
+hipError_t launch_quant_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* out,
+                             hipStream_t s) {
+  const int64_t count = ld * m;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_quant_bf16<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(psi, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(const float* psi, int64_t ld, int64_t m, uint8_t* out,
+                            float* scales, hipStream_t s) {
+  const int64_t blocks = (m + 3) / 4;
+  k_quant_fp8<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(psi, ld, m, out, scales);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reduced-precision inner products.  S = bytes per element (2: BF16, 1: FP8);
+// one 16-byte load holds E = 16 / S elements, matched by E / 4 float4s of r.
+
+template <int S>
+__device__ inline void lp_fma(v4u q, const v4f* __restrict__ rv, float& acc) {
+  if constexpr (S == 2) {
+    const v4f b0 = rv[0], b1 = rv[1];
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.x << 16), b0.x, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.x & 0xFFFF0000u), b0.y, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.y << 16), b0.z, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.y & 0xFFFF0000u), b0.w, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.z << 16), b1.x, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.z & 0xFFFF0000u), b1.y, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.w << 16), b1.z, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.w & 0xFFFF0000u), b1.w, acc);
+  } else {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const v4f b = rv[w];
+      const unsigned word = q[w];
+      // gfx950 decodes OCP e4m3fn exactly: bytes 0,1 then bytes 2,3
+      const v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(word), false);
+      const v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(word), true);
+      acc = __builtin_fmaf(lo.x, b.x, acc);
+      acc = __builtin_fmaf(lo.y, b.y, acc);
+      acc = __builtin_fmaf(hi.x, b.z, acc);
+      acc = __builtin_fmaf(hi.y, b.w, acc);
+    }
+  }
+}
+
+template <int S, int U>
+__device__ inline void lp_block(const v4u* __restrict__ p, const v4f* __restrict__ r_lds,
+                                int& i, float& acc) {
+  constexpr int R = 16 / S / 4;  // float4s of r per 16-byte load
+  v4u a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+#pragma unroll
+  for (int u = 0; u < U; ++u) lp_fma<S>(a[u], r_lds + (i + kWave * u) * R, acc);
+  i += kWave * U;
+}
+
+// Reduced-precision <r, psi_col> (before the FP8 scale) by one wave; nq
+// 16-byte chunks per column.
+template <int S>
+__device__ inline float dot_column_lp(const v4u* __restrict__ p, const v4f* __restrict__ r_lds,
+                                      int nq, int lane) {
+  float acc = 0.0f;
+  int i = lane;
+  while (i + kWave * 7 < nq) lp_block<S, 8>(p, r_lds, i, acc);
+  if (i + kWave * 3 < nq) lp_block<S, 4>(p, r_lds, i, acc);
+  if (i + kWave * 1 < nq) lp_block<S, 2>(p, r_lds, i, acc);
+  if (i < nq) lp_block<S, 1>(p, r_lds, i, acc);
+  return wave_sum(acc);
+}
+
+// ---------------------------------------------------------------------------
+// Top-8 lists of packed keys (larger key = larger |c|, then smaller index;
+// 0 = empty).
+
+// Insert into a sorted (descending) list; the smallest entry falls out.
+__device__ inline void top8_insert(uint64_t (&L)[kTopK], uint64_t key) {
+  if (key <= L[kTopK - 1]) return;
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) {
+    if (key > L[j]) {
+      const uint64_t t = L[j];
+      L[j] = key;
+      key = t;
+    }
+  }
+}
+
+// The 8 largest of the 128 keys a wave holds (two per lane); lane j < 8
+// receives the j-th largest.  Keys are distinct apart from 0.
+__device__ inline uint64_t wave_top8(uint64_t a, uint64_t b, int lane) {
+  uint64_t out = 0;
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) {
+    const uint64_t w = wave_max(a > b ? a : b);
+    if (lane == j) out = w;
+    if (w != 0) {
+      if (a == w) a = 0;
+      else if (b == w) b = 0;
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// One MP iteration with a reduced-precision correlation pass (one launch).
+//
+// Same shape as the FP32 step: 16-wave workgroups, r staged in LDS, wave w
+// of workgroup b takes columns b*cpw + w, + 16, ...; each wave keeps a top-8
+// list of its columns' keys, the workgroup merges its 16 lists and publishes
+// 8 keys.  The last workgroup merges all published keys into the launch's
+// top 8, re-scores the first `rescore_k` of them in FP32 and finishes the
+// iteration with the best re-scored candidate.
+template <int S>
+__global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
+    const v4u* __restrict__ psiq, const float* __restrict__ scales,
+    const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m, float* __restrict__ r,
+    int cols_per_wg, int rescore_k, uint64_t* __restrict__ keys, float* __restrict__ x,
+    DevState* __restrict__ st, mp_trace tr) {
+  if (st->done) return;
+  extern __shared__ v4f r_lds[];
+  __shared__ uint64_t lists[kLpWaves * kTopK];
+  __shared__ uint64_t cand[kTopK];
+  __shared__ uint64_t rescored[kTopK];
+  __shared__ uint64_t kred[kLpWaves];
+  __shared__ double dred[kLpWaves];
+  const int ld4 = static_cast<int>(ld / 4);
+  const int nq = static_cast<int>(ld * S / 16);
+  const v4f* r4 = reinterpret_cast<const v4f*>(r);
+  for (int i = threadIdx.x; i < ld4; i += kLpThreads) r_lds[i] = r4[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
+  int64_t col1 = col0 + cols_per_wg;
+  if (col1 > m) col1 = m;
+  uint64_t L[kTopK];
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) L[j] = 0;
+  for (int64_t col = col0 + wave; col < col1; col += kLpWaves) {
+    float c = dot_column_lp<S>(psiq + col * nq, r_lds, nq, lane);
+    if constexpr (S == 1) c *= scales[col];
+    top8_insert(L, make_key(c, static_cast<int>(col)));
+  }
+  {
+    uint64_t v = 0;
+#pragma unroll
+    for (int j = 0; j < kTopK; ++j)
+      if (lane == j) v = L[j];
+    if (lane < kTopK) lists[wave * kTopK + lane] = v;
+  }
+  __syncthreads();
+  uint64_t mine = 0;
+  if (wave == 0) mine = wave_top8(lists[lane], lists[lane + kWave], lane);
+  if (!publish_arrive<kTopK>(mine, keys, st)) return;
+
+  // ---- last workgroup: the launch's top 8 ----
+  const int nslots = static_cast<int>(gridDim.x) * kTopK;  // <= 2 * kLpThreads (host-checked)
+  const uint64_t a = threadIdx.x < nslots ? take_slot(keys + threadIdx.x) : 0;
+  const uint64_t b =
+      threadIdx.x + kLpThreads < nslots ? take_slot(keys + threadIdx.x + kLpThreads) : 0;
+  const uint64_t wtop = wave_top8(a, b, lane);
+  __syncthreads();  // everyone is done with `lists`
+  if (lane < kTopK) lists[wave * kTopK + lane] = wtop;
+  __syncthreads();
+  if (wave == 0) {
+    const uint64_t t = wave_top8(lists[lane], lists[lane + kWave], lane);
+    if (lane < kTopK) cand[lane] = t;
+  }
+  __syncthreads();
+  // ---- re-score candidates against the FP32 columns, one wave each ----
+  if (wave < rescore_k) {
+    const uint64_t k = cand[wave];
+    uint64_t rk = 0;
+    if (k != 0) {
+      const int idx = key_index(k);
+      if (idx >= 0 && idx < m) {
+        const float c32 = dot_column_f32(
+            reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld), r_lds, ld4,
+            lane);
+        rk = make_key(c32, idx);
+      }
+    }
+    if (lane == 0) rescored[wave] = rk;
+  }
+  __syncthreads();
+  uint64_t best = 0;
+  for (int j = 0; j < rescore_k; ++j) best = rescored[j] > best ? rescored[j] : best;
+  select_update_tail<kLpThreads>(best, psi32, ld, n, m, x, r, st, tr, dred);
+}
+
+hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
+                             const float* psi32, int64_t ld, int64_t n, int64_t m, float* r,
+                             const CorrGeom& g, int rescore_k, uint64_t* keys, float* x,
+                             DevState* st, mp_trace tr, hipStream_t s) {
+  const size_t lds = static_cast<size_t>(ld) * sizeof(float);
+  const v4u* q = static_cast<const v4u*>(psiq);
+  static bool big_lds[2] = {false, false};
+  const void* fn = storage == MP_BF16 ? reinterpret_cast<const void*>(k_mp_step_lp<2>)
+                                      : reinterpret_cast<const void*>(k_mp_step_lp<1>);
+  const int which = storage == MP_BF16 ? 0 : 1;
+  if (!big_lds[which] && lds > 60 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+    big_lds[which] = true;
+  }
+  if (storage == MP_BF16)
+    k_mp_step_lp<2><<<dim3(g.grid), dim3(kLpThreads), lds, s>>>(
+        q, nullptr, psi32, ld, n, m, r, g.cols_per_wg, rescore_k, keys, x, st, tr);
+  else
+    k_mp_step_lp<1><<<dim3(g.grid), dim3(kLpThreads), lds, s>>>(
+        q, scales, psi32, ld, n, m, r, g.cols_per_wg, rescore_k, keys, x, st, tr);
+  return hipGetLastError();
+}
+
+}  // namespace mp

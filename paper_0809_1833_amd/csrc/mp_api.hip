@@ -51,8 +51,12 @@ hipError_t enqueue_iteration(mp_ctx* c, float* x, const mp_trace& tr, hipStream_
                              hipEvent_t e0, hipEvent_t e1) {
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-  e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials, x,
-                             c->st, tr, s);
+  if (c->storage == MP_F32)
+    e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials, x,
+                               c->st, tr, s);
+  else
+    e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
+                              c->r_work, c->geom, c->rescore_k, c->partials, x, c->st, tr, s);
   if (e != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
   return hipSuccess;
@@ -90,11 +94,8 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (n > kMaxN) return fail(nullptr, MP_EINVAL, "n exceeds 16384");
   if (m >= (int64_t{1} << 31)) return fail(nullptr, MP_EINVAL, "m must be < 2^31");
   if (flags & ~MP_SKIP_NORM_CHECK) return fail(nullptr, MP_EINVAL, "unknown flags");
-  if (storage != MP_F32) {
-    if (storage == MP_BF16 || storage == MP_FP8_E4M3)
-      return fail(nullptr, MP_EUNSUPPORTED, "reduced-precision storage is not built yet");
+  if (storage != MP_F32 && storage != MP_BF16 && storage != MP_FP8_E4M3)
     return fail(nullptr, MP_EINVAL, "unknown storage type");
-  }
   int dev = 0;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
@@ -124,7 +125,10 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (hipMalloc(&c->psi32, psi_bytes) != hipSuccess) return bail(MP_ENOMEM, "dictionary copy");
   if (hipMalloc(&c->r_work, c->ld * sizeof(float)) != hipSuccess) return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
-  if (hipMalloc(&c->partials, sizeof(uint64_t) * c->geom.grid) != hipSuccess)
+  if (c->geom.grid * mp::kLpTopK > 2 * 1024)
+    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
+  const size_t nkeys = static_cast<size_t>(c->geom.grid) * mp::kLpTopK;
+  if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
   if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
     return bail(MP_ENOMEM, "pinned state");
@@ -134,7 +138,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
     e = hipMemcpy2DAsync(c->psi32, c->ld * sizeof(float), psi, ld * sizeof(float),
                          n * sizeof(float), m, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
-  if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * c->geom.grid, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
 
   // Column norms in FP64 (eq. 4): finiteness always, unit norm unless skipped.
@@ -159,6 +163,21 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
                static_cast<long long>(j), sqrt(norm2[j]));
       return bail(MP_ENOTNORM, buf);
     }
+  }
+  // Reduced-precision copy the correlation pass streams (same padded layout).
+  if (storage == MP_BF16 || storage == MP_FP8_E4M3) {
+    const size_t esize = storage == MP_BF16 ? 2 : 1;
+    const size_t qbytes = static_cast<size_t>(c->ld) * static_cast<size_t>(m) * esize;
+    if (hipMalloc(&c->psiq, qbytes) != hipSuccess) return bail(MP_ENOMEM, "reduced copy");
+    if (storage == MP_BF16) {
+      e = mp::launch_quant_bf16(c->psi32, c->ld, m, static_cast<uint16_t*>(c->psiq), s);
+    } else {
+      if (hipMalloc(&c->scales, sizeof(float) * m) != hipSuccess)
+        return bail(MP_ENOMEM, "scales");
+      e = mp::launch_quant_fp8(c->psi32, c->ld, m, static_cast<uint8_t*>(c->psiq), c->scales, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(MP_EDEVICE, std::string("quantise: ") + hipGetErrorString(e));
   }
   *out = c;
   return MP_OK;
@@ -193,9 +212,13 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
     HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(float), c->psi32, c->ld * sizeof(float),
                                 c->n * sizeof(float), c->m, hipMemcpyDeviceToDevice, s));
   } else {
-    return fail(c, MP_EUNSUPPORTED, "storage not built");
+    const size_t esize = c->storage == MP_BF16 ? 2 : 1;
+    HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * esize, c->psiq, c->ld * esize, c->n * esize, c->m,
+                                hipMemcpyDeviceToDevice, s));
+    if (c->storage == MP_FP8_E4M3 && scales)
+      HIP_TRY(c, hipMemcpyAsync(scales, c->scales, sizeof(float) * c->m, hipMemcpyDeviceToDevice,
+                                s));
   }
-  (void)scales;
   HIP_TRY(c, hipStreamSynchronize(s));
   return MP_OK;
 }
@@ -219,6 +242,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_ctx* c = ctx;
+  c->rescore_k = opts->rescore_k == 0 ? mp::kLpTopK : opts->rescore_k;
   c->prof_ms = 0.0;
   c->prof_launches = 0;
 

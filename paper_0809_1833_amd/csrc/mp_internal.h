@@ -71,6 +71,17 @@ hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m
                               const CorrGeom& g, uint64_t* keys, float* x, DevState* st,
                               mp_trace tr, hipStream_t s);
 
+// ---- reduced-precision storage (k_lowp.hip) ---------------------------------
+constexpr int kLpTopK = 8;  // candidates kept per pass and re-scored in FP32
+hipError_t launch_quant_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* out,
+                             hipStream_t s);
+hipError_t launch_quant_fp8(const float* psi, int64_t ld, int64_t m, uint8_t* out,
+                            float* scales, hipStream_t s);
+hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
+                             const float* psi32, int64_t ld, int64_t n, int64_t m, float* r,
+                             const CorrGeom& g, int rescore_k, uint64_t* keys, float* x,
+                             DevState* st, mp_trace tr, hipStream_t s);
+
 }  // namespace mp
 
 // The context behind the opaque mp_ctx handle.
@@ -86,7 +97,7 @@ struct mp_ctx {
   float* r_work = nullptr;       // ld floats, rows n..ld-1 stay zero
   mp::DevState* st = nullptr;    // device state
   mp::DevState* h_st = nullptr;  // pinned host mirror
-  uint64_t* partials = nullptr;  // one key per correlation workgroup
+  uint64_t* partials = nullptr;  // key slots: kLpTopK per correlation workgroup
   mp::CorrGeom geom{};
   // profiling of the correlation kernel
   bool profiling = false;
@@ -94,5 +105,6 @@ struct mp_ctx {
   std::vector<hipEvent_t> ev;    // 2 slots x 2 events x max chunk
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
+  int rescore_k = mp::kLpTopK;   // for the current decode
   std::string err;
 };
