@@ -75,6 +75,65 @@ def cpu_baseline(p, budget_s=15.0):
                        f"{dt:.1f} s)")
 
 
+def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = True):
+    """Batched workload: 256 signals, K_b ~ U{16..256}, sharing one N=2048,
+    M=8192 dictionary.  signals/s of mp_solve_batched (BF16 matrix-core
+    correlations, FP32 re-scoring) and, for comparison, of FP32 mp_solve run
+    signal after signal on the same inputs; MFMA utilisation of the product
+    kernel = 2 N M (sum of per-signal iterations) / (its summed launch time)."""
+    import numpy as np
+    import torch
+
+    import mpgen
+    from paper_0809_1833_amd.mp import Decoder
+
+    bt = mpgen.make_batch(seed)
+    n, m, nb = bt.psi.shape[0], bt.psi.shape[1], bt.y.shape[1]
+    psi = torch.from_numpy(np.ascontiguousarray(bt.psi.T)).cuda().t()
+    Y = torch.from_numpy(np.ascontiguousarray(bt.y.T)).cuda().t()
+    caps = [int(v) for v in bt.max_iters]
+    out = {"workload": f"N={n}, M={m}, B={nb} signals, K_b ~ U{{16..256}}, eps={bt.eps}, "
+                       "T_b=20 K_b, shared dictionary"}
+    with Decoder(psi, storage="bf16") as dec:
+        for _ in range(warmup):
+            dec.solve_batched(Y, bt.eps, caps, want_r=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = dec.solve_batched(Y, bt.eps, caps, want_r=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        total_iters = sum(res["iters"])
+        out.update(signals_per_s_bf16_batched=round(nb / dt, 2), batch_ms=round(dt * 1e3, 3),
+                   total_iters=total_iters, max_iters=max(res["iters"]),
+                   stops=sorted(set(res["stop"])))
+        dec.set_profiling(1)
+        dec.solve_batched(Y, bt.eps, caps, want_r=False)
+        ms, cnt = dec.kernel_time()
+        dec.set_profiling(0)
+        flops = 2.0 * n * m * total_iters
+        gemm_s = ms * cnt * 1e-3
+        out["mfma"] = {"bound": "mfma", "kernel": "k_bcorr", "achieved": round(flops / gemm_s / 1e12, 2),
+                       "peak": 2500.0, "unit": "TFLOP/s",
+                       "frac": round(flops / gemm_s / 1e12 / 2500.0, 4),
+                       "rounds": cnt, "gemm_ms_per_batch": round(ms * cnt, 3)}
+    if sequential:
+        with Decoder(psi, storage="f32") as dec:
+            x = torch.empty(m, dtype=torch.float32, device="cuda")
+            r = torch.empty(n, dtype=torch.float32, device="cuda")
+            ys = [Y[:, b].contiguous() for b in range(nb)]
+            dec.solve(ys[0], bt.eps, caps[0], x=x, r=r)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for b in range(nb):
+                dec.solve(ys[b], bt.eps, caps[b], x=x, r=r)
+            torch.cuda.synchronize()
+            dts = time.perf_counter() - t0
+        out["signals_per_s_f32_sequential"] = round(nb / dts, 2)
+        out["batched_over_sequential"] = round(dts / dt, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +145,8 @@ def main():
                     help="dictionary copy the correlation pass streams")
     ap.add_argument("--dist", default="normal", choices=["normal", "loguniform"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form measurement added to the line")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every k-th iteration's kernel launch with HIP events")
     ap.add_argument("--max-iters", type=int, default=None,
@@ -183,10 +244,13 @@ def main():
             "launches": kt_n,
         },
     }
+    dec.close()
+    if not args.no_batched:
+        log("[bench] batched form (256 signals, shared dictionary)")
+        line["batched"] = bench_batched(args.seed)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p)
-    dec.close()
     print(json.dumps(line), flush=True)
 
 

@@ -154,6 +154,37 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
                    mp_result* res, const mp_trace* trace, void* stream);
 
 /*
+ * mp_solve_batched -- decode B signals that share the context's dictionary
+ * (the paper encodes and decodes every signal with one dictionary,
+ * Section 4).  Each signal runs its own Section 3 loop; the correlations of
+ * all still-active signals are computed together as one BF16 matrix product
+ * Psi^T R on the matrix cores (FP32 accumulate), the 8 best candidates of
+ * each signal are re-scored against the FP32 columns, and signals drop out
+ * of later products as soon as they stop.  A context created with MP_F32 or
+ * MP_FP8_E4M3 storage gets a BF16 copy of its dictionary on first use.
+ *
+ *   Y         device: N x B, column b = y of signal b, leading dimension ldy >= N
+ *   X         device: M x B, overwritten with the x~ columns, ldx >= M
+ *   R         device: N x B or NULL, receives the final residuals, ldr >= N
+ *   opts      host: eps and rescore_k apply to every signal; max_iters is the
+ *             cap unless max_iters_b is given
+ *   max_iters_b  host: B per-signal caps, or NULL
+ *   res       host: B results, or NULL
+ *   trace     host struct of device arrays of B * cap entries, or NULL; signal
+ *             b's step t goes to index b * cap + t
+ *
+ * Errors: MP_EINVAL (NULL ctx/Y/X/opts, B < 0 or >= 2^30, a leading
+ * dimension too small, eps/max_iters/rescore_k/flags as for mp_solve, a
+ * negative max_iters_b entry), MP_ENONFINITE (a column of Y holds NaN/Inf;
+ * the other signals are still decoded), MP_ENOMEM, MP_EDEVICE.  B = 0 is a
+ * no-op.
+ */
+mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, float* X,
+                           int64_t ldx, float* R, int64_t ldr, const mp_opts* opts,
+                           const int64_t* max_iters_b, mp_result* res, const mp_trace* trace,
+                           void* stream);
+
+/*
  * mp_destroy -- free everything the context owns.  NULL is a no-op.
  */
 void mp_destroy(mp_ctx* ctx);
@@ -182,7 +213,9 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
  * mp_set_profiling / mp_kernel_time -- per-launch timing of the kernel that
  * makes one MP iteration (the pass over the whole dictionary, eq. 9, with the
  * selection and update of eqs. 10-12 at its tail) during the last mp_solve,
- * measured with HIP events recorded around the launch on the decode stream.
+ * or of the matrix-product kernel (the correlations of all active signals)
+ * during the last mp_solve_batched, measured with HIP events recorded around
+ * the launch on the decode stream.
  *
  *   every     0: off.  k > 0: time every k-th iteration's launch (events
  *             around every launch add a little time between launches).

@@ -1,0 +1,496 @@
+// Batched Matching Pursuit: many signals against one shared dictionary.
+//
+// One round performs one MP iteration (Section 3, eqs. 9-12) for every
+// signal still active.  The correlations of all active signals with all
+// atoms are one matrix product C = Psi^T R (the residuals as columns), run
+// on the BF16 matrix cores with FP32 accumulation; its epilogue keeps, for
+// every signal, the 8 best atoms of each 64-atom tile.  A second kernel, one
+// workgroup per active signal, merges those into the signal's 8 best
+// candidates, re-scores them against the FP32 columns and the FP32 residual,
+// takes the best (smallest index on ties, eq. 16) and updates x~, r and the
+// FP64 stopping test for that signal.  Signals stop at their own iteration;
+// the last workgroup of each round compacts the list of active signals, so
+// the next round's product covers only those.
+#include "k_common.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8bf;
+
+constexpr int kBThreads = 256;              // 4 waves (init and compaction)
+constexpr int kBSelThreads = 512;           // 8 waves: one per re-scored candidate
+constexpr int kBTopK = 8;
+
+__device__ inline uint16_t bf16_rne_b(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// Sorted (descending) top-8 list of keys; 0 = empty.
+__device__ inline void topk_insert(uint64_t (&L)[kBTopK], uint64_t key) {
+  if (key <= L[kBTopK - 1]) return;
+#pragma unroll
+  for (int j = 0; j < kBTopK; ++j) {
+    if (key > L[j]) {
+      const uint64_t t = L[j];
+      L[j] = key;
+      key = t;
+    }
+  }
+}
+
+// The 8 largest keys over the lanes' sorted lists; lane j < 8 receives the
+// j-th largest.  Keys are distinct apart from 0.
+__device__ inline uint64_t wave_top8_lists(uint64_t (&L)[kBTopK], int lane) {
+  uint64_t out = 0;
+#pragma unroll
+  for (int j = 0; j < kBTopK; ++j) {
+    const uint64_t w = wave_max(L[0]);
+    if (lane == j) out = w;
+    if (w != 0 && L[0] == w) {  // pop the head of the list that held it
+#pragma unroll
+      for (int q = 0; q + 1 < kBTopK; ++q) L[q] = L[q + 1];
+      L[kBTopK - 1] = 0;
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Init: every signal slot b < B.  r = y (zero padded), its BF16 copy, x~ = 0,
+// ||y||^2 in FP64, the loop's pre-test.  One workgroup per slot.
+__global__ __launch_bounds__(kBThreads) void k_binit(
+    const float* __restrict__ Y, int64_t ldy, int64_t n, int64_t ld, float* __restrict__ X,
+    int64_t ldx, int64_t m, float* __restrict__ R32, uint16_t* __restrict__ Rq,
+    BSlot* __restrict__ slots, const long long* __restrict__ tcap, long long tcap_all,
+    double eps) {
+  __shared__ double red[kBThreads / kWave];
+  const int64_t b = blockIdx.x;
+  const float* y = Y + b * ldy;
+  float* r = R32 + b * ld;
+  uint16_t* rq = Rq + b * ld;
+  float* x = X + b * ldx;
+  for (int64_t j = threadIdx.x; j < m; j += kBThreads) x[j] = 0.0f;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < ld; i += kBThreads) {
+    const float v = i < n ? y[i] : 0.0f;
+    r[i] = v;
+    rq[i] = bf16_rne_b(v);
+    s += static_cast<double>(v) * v;
+  }
+  const double yy = block_sum<kBThreads>(s, red);
+  if (threadIdx.x == 0) {
+    BSlot d{};
+    d.yy = yy;
+    d.rr = yy;
+    d.thr = eps * eps * yy;
+    d.t = 0;
+    d.max_iters = tcap ? tcap[b] : tcap_all;
+    d.reason = MP_STOP_CONVERGED;
+    d.done = 0;
+    if (!__builtin_isfinite(yy)) {
+      d.done = 1;
+      d.reason = kStopNonFinite;
+    } else if (yy == 0.0) {
+      d.done = 1;
+      d.reason = MP_STOP_ZERO_INPUT;
+    } else if (!(yy > d.thr)) {
+      d.done = 1;
+      d.reason = MP_STOP_CONVERGED;
+    } else if (d.max_iters <= 0) {
+      d.done = 1;
+      d.reason = MP_STOP_MAX_ITERS;
+    }
+    slots[b] = d;
+  }
+}
+
+// Stable compaction of the slots that are still running into act[1 - cur]
+// (one workgroup; `alive(j)` tells whether position j of the current list
+// stays).  Used once after init (from all slots) and by the last workgroup
+// of every select round.
+template <int NT, typename Alive>
+__device__ void compact_active(const int* __restrict__ act_cur, int nact, bool from_all,
+                               int* __restrict__ act_next, BState* __restrict__ bs, int cur,
+                               Alive alive) {
+  __shared__ int wsum[NT / kWave];
+  __shared__ int base_s;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < nact; j0 += NT) {
+    const int j = j0 + threadIdx.x;
+    const int slot = j < nact ? (from_all ? j : act_cur[j]) : -1;
+    const bool keep = j < nact && alive(j, slot);
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int off = base_s;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    if (keep) act_next[off + before] = slot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < NT / kWave; ++w) tot += wsum[w];
+      base_s += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bs->n_active[1 - cur] = base_s;
+    bs->cur = 1 - cur;
+  }
+}
+
+__global__ __launch_bounds__(kBThreads) void k_bcompact_init(int nslots, const BSlot* slots,
+                                                             int* act0, int* act1, BState* bs) {
+  // initial list into act[1 - 0]; then cur flips to 1 ... keep the convention
+  // "current list = act[cur]" by compacting from "all slots" into act1.
+  (void)act0;
+  compact_active<kBThreads>(nullptr, nslots, true, act1, bs, 0,
+                 [&](int, int slot) { return slots[slot].done == 0; });
+  if (threadIdx.x == 0) bs->arrive = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Product tile: (16 TI) atoms x 64 signals per workgroup of 4 waves; TI = 4
+// when many signals are active, TI = 2 (twice the workgroups) when few are.
+// Every wave computes the whole tile as TI x 4 MFMA 16x16 blocks (K = 32 per
+// MFMA) over its share of K: wave w takes the K-steps w, w + 4, w + 8, ...
+// (neighbouring waves read neighbouring bytes of the same cache lines).
+// Operands come straight from global memory (the BF16 dictionary stays in
+// the last-level cache across rounds, the residuals in L2): lane l loads 16
+// contiguous bytes of atom row (l % 16) and of signal column (l % 16) at K
+// offset 8 * (l / 16).  The fragments of the wave's next kBPre K-steps stay
+// in flight in a register ring while the current step's MFMAs run.  The four
+// partial tiles are summed in LDS in a fixed order, ((w0 + w2) + (w1 + w3)),
+// and all 256 threads then find each signal's 8 best keys of the tile.
+constexpr int kBCorrThreads = 256;
+constexpr int kBCorrWaves = kBCorrThreads / kWave;   // K split
+constexpr int kBCorrTileB = 64;                      // signals per workgroup
+constexpr int kBPre = 4;                             // K-steps in flight per wave
+
+template <int TI>
+__global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restrict__ psib,
+                                                         int64_t ld, int64_t m,
+                                                         const uint16_t* __restrict__ Rq,
+                                                         const int* __restrict__ act0,
+                                                         const int* __restrict__ act1,
+                                                         const BState* __restrict__ bs,
+                                                         uint64_t* __restrict__ partials,
+                                                         int mtiles) {
+  constexpr int TM = 16 * TI;
+  const int cur = bs->cur;
+  const int nact = bs->n_active[cur];
+  const int j0 = blockIdx.y * kBCorrTileB;
+  if (j0 >= nact) return;  // workgroup-uniform
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int* act = cur ? act1 : act0;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * TM;
+  const int koff = 8 * (lane / 16);
+
+  const uint16_t* arow[TI];
+  bool aval[TI];
+#pragma unroll
+  for (int ti = 0; ti < TI; ++ti) {
+    const int64_t row = m0 + 16 * ti + (lane % 16);
+    aval[ti] = row < m;
+    arow[ti] = psib + (aval[ti] ? row : 0) * ld + koff;
+  }
+  const uint16_t* bcol[4];
+  bool bval[4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
+    const int j = j0 + 16 * tj + (lane % 16);
+    bval[tj] = j < nact;
+    bcol[tj] = Rq + static_cast<int64_t>(bval[tj] ? act[j] : 0) * ld + koff;
+  }
+  v4f acc[TI][4];
+#pragma unroll
+  for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const v8bf zero = {};
+  const int nsteps = static_cast<int>(ld / 32);
+  // this wave's K-steps: wave, wave + 4, ...; `q` counts them
+  const int nmine = nsteps > wave ? (nsteps - wave + kBCorrWaves - 1) / kBCorrWaves : 0;
+  v8bf ra[kBPre][TI], rb[kBPre][4];
+  auto load_step = [&](int slot, int q) {
+    const int64_t k = static_cast<int64_t>(wave + q * kBCorrWaves) * 32;
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+      ra[slot][ti] = aval[ti] ? *reinterpret_cast<const v8bf*>(arow[ti] + k) : zero;
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+      rb[slot][tj] = bval[tj] ? *reinterpret_cast<const v8bf*>(bcol[tj] + k) : zero;
+  };
+#pragma unroll
+  for (int p = 0; p < kBPre; ++p)
+    if (p < nmine) load_step(p, p);
+  for (int q0 = 0; q0 < nmine; q0 += kBPre) {
+#pragma unroll
+    for (int p = 0; p < kBPre; ++p) {
+      if (q0 + p < nmine) {
+#pragma unroll
+        for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < 4; ++tj)
+            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[p][ti], rb[p][tj],
+                                                                   acc[ti][tj], 0, 0, 0);
+        if (q0 + p + kBPre < nmine) load_step(p, q0 + p + kBPre);
+      }
+    }
+  }
+
+  // sum the four partial tiles: ((w0 + w2) + (w1 + w3)) into ctile[1]
+  __shared__ float ctile[2][TM][kBCorrTileB + 1];
+  __shared__ uint64_t lists[4][kBCorrTileB][kBTopK];
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          ctile[slot][16 * ti + 4 * (lane / 16) + i][16 * tj + (lane % 16)] = acc[ti][tj][i];
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[ti][tj][i] += ctile[slot][16 * ti + 4 * (lane / 16) + i][16 * tj + (lane % 16)];
+  };
+  if (wave >= 2) store(wave - 2);
+  __syncthreads();
+  if (wave < 2) add(wave);  // w0 + w2, w1 + w3
+  __syncthreads();
+  if (wave == 1) store(0);
+  __syncthreads();
+  if (wave == 0) {
+    add(0);
+    store(1);
+  }
+  __syncthreads();
+  // each signal's 8 best atoms: thread (part = wave, col = lane) scans TM/4
+  // rows, the four lists are merged by part 0
+  {
+    uint64_t L[kBTopK];
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) L[q] = 0;
+    constexpr int RP = TM / 4;
+    for (int rr = wave * RP; rr < wave * RP + RP; ++rr) {
+      const int64_t atom = m0 + rr;
+      if (atom < m) topk_insert(L, make_key(ctile[1][rr][lane], static_cast<int>(atom)));
+    }
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) lists[wave][lane][q] = L[q];
+    __syncthreads();
+    if (wave == 0 && j0 + lane < nact) {
+      for (int p = 1; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < kBTopK; ++q) topk_insert(L, lists[p][lane][q]);
+      uint64_t* out =
+          partials + (static_cast<int64_t>(j0 + lane) * mtiles + blockIdx.x) * kBTopK;
+#pragma unroll
+      for (int q = 0; q < kBTopK; ++q) out[q] = L[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-signal selection, FP32 re-scoring and update; one workgroup per active
+// signal (position j of the current list).  The workgroup that arrives last
+// compacts the list for the next round.
+__global__ __launch_bounds__(kBSelThreads) void k_bselect(
+    const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m,
+    float* __restrict__ R32, uint16_t* __restrict__ Rq, float* __restrict__ X, int64_t ldx,
+    BSlot* __restrict__ slots, int* __restrict__ act0, int* __restrict__ act1,
+    BState* __restrict__ bs, const uint64_t* __restrict__ partials, int mtiles,
+    uint64_t* __restrict__ alive, int rescore_k, mp_trace tr) {
+  const int cur = bs->cur;
+  const int nact = bs->n_active[cur];
+  const int j = blockIdx.x;
+  if (j >= nact) return;
+  const int* act = cur ? act1 : act0;
+  int* act_next = cur ? act0 : act1;
+  const int b = act[j];
+  extern __shared__ v4f r_lds[];
+  __shared__ uint64_t wl[kBSelThreads / kWave][kBTopK];
+  __shared__ uint64_t cand[kBTopK];
+  __shared__ uint64_t resc[kBTopK];
+  __shared__ double dred[kBSelThreads / kWave];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  float* r = R32 + static_cast<int64_t>(b) * ld;
+  const int ld4 = static_cast<int>(ld / 4);
+  for (int i = threadIdx.x; i < ld4; i += kBSelThreads) r_lds[i] = reinterpret_cast<const v4f*>(r)[i];
+
+  // the signal's 8 best candidates over all atom tiles
+  uint64_t L[kBTopK];
+#pragma unroll
+  for (int q = 0; q < kBTopK; ++q) L[q] = 0;
+  const uint64_t* pk = partials + static_cast<int64_t>(j) * mtiles * kBTopK;
+  for (int i = threadIdx.x; i < mtiles * kBTopK; i += kBSelThreads) topk_insert(L, pk[i]);
+  const uint64_t w8 = wave_top8_lists(L, lane);
+  if (lane < kBTopK) wl[wave][lane] = w8;
+  __syncthreads();
+  if (wave == 0) {
+    uint64_t M8[kBTopK];
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) M8[q] = 0;
+    if (lane < kBSelThreads / kWave)
+#pragma unroll
+      for (int q = 0; q < kBTopK; ++q) M8[q] = wl[lane][q];
+    const uint64_t t8 = wave_top8_lists(M8, lane);
+    if (lane < kBTopK) cand[lane] = t8;
+  }
+  __syncthreads();
+  // re-score in FP32, one candidate per wave
+  for (int q = wave; q < rescore_k; q += kBSelThreads / kWave) {
+    const uint64_t k = cand[q];
+    uint64_t rk = 0;
+    if (k != 0) {
+      const int idx = key_index(k);
+      if (idx >= 0 && idx < m) {
+        const float c32 = dot_column_f32(
+            reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld), r_lds, ld4,
+            lane);
+        rk = make_key(c32, idx);
+      }
+    }
+    if (lane == 0) resc[q] = rk;
+  }
+  __syncthreads();
+  uint64_t best = 0;
+  for (int q = 0; q < rescore_k; ++q) best = resc[q] > best ? resc[q] : best;
+  const int idx = key_index(best);
+  const float c = key_value(best);
+  BSlot* sl = slots + b;
+  bool stop_now = false;
+  if (best == 0 || idx < 0 || idx >= m) {
+    stop_now = true;
+    if (threadIdx.x == 0) {
+      sl->done = 1;
+      sl->reason = kStopInternal;
+    }
+  } else if (c == 0.0f) {
+    stop_now = true;
+    if (threadIdx.x == 0) {
+      sl->done = 1;
+      sl->reason = MP_STOP_STALLED;
+    }
+  }
+  if (!stop_now) {
+    const float* colp = psi32 + static_cast<int64_t>(idx) * ld;
+    uint16_t* rq = Rq + static_cast<int64_t>(b) * ld;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < ld; i += kBSelThreads) {
+      const float v = __builtin_fmaf(-c, colp[i], r[i]);  // padding rows stay 0
+      r[i] = v;
+      rq[i] = bf16_rne_b(v);
+      s += static_cast<double>(v) * v;
+    }
+    const double rr = block_sum<kBSelThreads>(s, dred);
+    if (threadIdx.x == 0) {
+      X[static_cast<int64_t>(b) * ldx + idx] += c;
+      const long long t = sl->t;
+      if (t < tr.cap) {
+        const int64_t o = static_cast<int64_t>(b) * tr.cap + t;
+        if (tr.idx) tr.idx[o] = idx;
+        if (tr.coef) tr.coef[o] = c;
+        if (tr.rr) tr.rr[o] = rr;
+      }
+      sl->t = t + 1;
+      sl->rr = rr;
+      if (!(rr > sl->thr)) {
+        sl->done = 1;
+        sl->reason = MP_STOP_CONVERGED;
+      } else if (t + 1 >= sl->max_iters) {
+        sl->done = 1;
+        sl->reason = MP_STOP_MAX_ITERS;
+      }
+    }
+  }
+  __syncthreads();
+  // publish whether this signal stays, count in; the last workgroup compacts
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    const uint64_t keep = sl->done ? 0ull : 1ull;
+    const uint64_t old = __hip_atomic_exchange(alive + j, keep + 2ull, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned inc = 1u + static_cast<unsigned>(old >> 63);
+    const unsigned prev =
+        __hip_atomic_fetch_add(&bs->arrive, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev == static_cast<unsigned>(nact - 1);
+    if (s_last)
+      (void)__hip_atomic_exchange(&bs->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // alive[j] = 2 + keep for every position of this round (set by the RMW
+  // above in each workgroup); read back with RMWs that also clear it
+  compact_active<kBSelThreads>(act, nact, false, act_next, bs, cur, [&](int jj, int) {
+    const uint64_t v = __hip_atomic_exchange(alive + jj, uint64_t{0}, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return v == 3ull;
+  });
+}
+
+// ---------------------------------------------------------------------------
+
+hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, float* X,
+                        int64_t ldx, int64_t m, float* R32, uint16_t* Rq, BSlot* slots,
+                        const long long* tcap, long long tcap_all, double eps, int nslots,
+                        int* act0, int* act1, BState* bs, hipStream_t s) {
+  k_binit<<<dim3(nslots), dim3(kBThreads), 0, s>>>(Y, ldy, n, ld, X, ldx, m, R32, Rq, slots,
+                                                   tcap, tcap_all, eps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_bcompact_init<<<dim3(1), dim3(kBThreads), 0, s>>>(nslots, slots, act0, act1, bs);
+  return hipGetLastError();
+}
+
+// Atoms per product tile for a round expected to have `nact_hint` active
+// signals: 64 when many are active, 32 (twice the workgroups) when few are.
+int bcorr_tile_m(int nact_hint) { return nact_hint > 96 ? 64 : 32; }
+int bcorr_mtiles(int64_t m, int tile_m) { return static_cast<int>((m + tile_m - 1) / tile_m); }
+
+hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, int64_t n,
+                         int64_t m, float* R32, uint16_t* Rq, float* X, int64_t ldx,
+                         BSlot* slots, int* act0, int* act1, BState* bs, uint64_t* partials,
+                         uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const int tile_m = bcorr_tile_m(nact_hint);
+  const int mtiles = bcorr_mtiles(m, tile_m);
+  const int btiles = (nact_hint + kBCorrTileB - 1) / kBCorrTileB;  // >= the round's tiles
+  hipError_t e;
+  if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+  if (tile_m == 64)
+    k_bcorr<4><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psib, ld, m, Rq, act0, act1,
+                                                                    bs, partials, mtiles);
+  else
+    k_bcorr<2><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psib, ld, m, Rq, act0, act1,
+                                                                    bs, partials, mtiles);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
+  const size_t lds = static_cast<size_t>(ld) * sizeof(float);
+  static bool big_lds = false;
+  if (!big_lds && lds > 60 * 1024) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bselect),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+    big_lds = true;
+  }
+  k_bselect<<<dim3(nact_hint), dim3(kBSelThreads), lds, s>>>(psi32, ld, n, m, R32, Rq, X, ldx,
+                                                             slots, act0, act1, bs, partials,
+                                                             mtiles, alive, rescore_k, tr);
+  return hipGetLastError();
+}
+
+}  // namespace mp

@@ -33,8 +33,34 @@ mp_status fail(mp_ctx* ctx, mp_status s, const std::string& msg) {
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+void free_batched(mp_ctx* c) {
+  (void)hipFree(c->b_r32);
+  (void)hipFree(c->b_rq);
+  (void)hipFree(c->b_slots);
+  (void)hipFree(c->b_act);
+  (void)hipFree(c->b_state);
+  (void)hipFree(c->b_partials);
+  (void)hipFree(c->b_alive);
+  (void)hipFree(c->b_tcap);
+  if (c->h_slots) (void)hipHostFree(c->h_slots);
+  if (c->h_bstate) (void)hipHostFree(c->h_bstate);
+  c->b_r32 = nullptr;
+  c->b_rq = nullptr;
+  c->b_slots = nullptr;
+  c->b_act = nullptr;
+  c->b_state = nullptr;
+  c->b_partials = nullptr;
+  c->b_alive = nullptr;
+  c->b_tcap = nullptr;
+  c->h_slots = nullptr;
+  c->h_bstate = nullptr;
+  c->bcap = 0;
+}
+
 void free_ctx(mp_ctx* c) {
   if (!c) return;
+  free_batched(c);
+  if (c->psib_owned) (void)hipFree(c->psib);
   (void)hipFree(c->psi32);
   (void)hipFree(c->psiq);
   (void)hipFree(c->scales);
@@ -353,6 +379,203 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     res->stop_reason = d.reason;
     res->reserved = 0;
   }
+  return MP_OK;
+}
+
+
+// Make sure the context has a BF16 copy for the batched product and buffers
+// for `B` signals.
+static mp_status ensure_batched(mp_ctx* c, int64_t B, hipStream_t s) {
+  if (!c->psib) {
+    if (c->storage == MP_BF16) {
+      c->psib = static_cast<uint16_t*>(c->psiq);
+    } else {
+      const size_t bytes = static_cast<size_t>(c->ld) * static_cast<size_t>(c->m) * 2;
+      if (hipMalloc(&c->psib, bytes) != hipSuccess) return fail(c, MP_ENOMEM, "BF16 copy");
+      c->psib_owned = true;
+      HIP_TRY(c, mp::launch_quant_bf16(c->psi32, c->ld, c->m, c->psib, s));
+    }
+  }
+  if (B <= c->bcap) return MP_OK;
+  free_batched(c);
+  const int64_t cap = B;
+  const int mtiles = mp::bcorr_mtiles(c->m, 32);  // the larger of the two tilings
+  const size_t ldb = static_cast<size_t>(c->ld);
+  bool ok = hipMalloc(&c->b_r32, sizeof(float) * ldb * cap) == hipSuccess &&
+            hipMalloc(&c->b_rq, sizeof(uint16_t) * ldb * cap) == hipSuccess &&
+            hipMalloc(&c->b_slots, sizeof(mp::BSlot) * cap) == hipSuccess &&
+            hipMalloc(&c->b_act, sizeof(int) * 2 * cap) == hipSuccess &&
+            hipMalloc(&c->b_state, sizeof(mp::BState)) == hipSuccess &&
+            hipMalloc(&c->b_partials, sizeof(uint64_t) * cap * mtiles * 8) == hipSuccess &&
+            hipMalloc(&c->b_alive, sizeof(uint64_t) * cap) == hipSuccess &&
+            hipMalloc(&c->b_tcap, sizeof(long long) * cap) == hipSuccess &&
+            hipHostMalloc(&c->h_slots, sizeof(mp::BSlot) * cap, hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc(&c->h_bstate, 2 * sizeof(mp::BState), hipHostMallocDefault) ==
+                hipSuccess;
+  if (!ok) {
+    free_batched(c);
+    return fail(c, MP_ENOMEM, "batched work buffers");
+  }
+  HIP_TRY(c, hipMemsetAsync(c->b_alive, 0, sizeof(uint64_t) * cap, s));
+  HIP_TRY(c, hipMemsetAsync(c->b_state, 0, sizeof(mp::BState), s));
+  c->bcap = cap;
+  return MP_OK;
+}
+
+mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, float* X,
+                           int64_t ldx, float* R, int64_t ldr, const mp_opts* opts,
+                           const int64_t* max_iters_b, mp_result* res, const mp_trace* trace,
+                           void* stream) {
+  if (!ctx) return MP_EINVAL;
+  ctx->err.clear();
+  mp_ctx* c = ctx;
+  if (B < 0) return fail(c, MP_EINVAL, "B must be >= 0");
+  if (B == 0) return MP_OK;
+  if (B >= (int64_t{1} << 31) / 2) return fail(c, MP_EINVAL, "B too large");
+  if (!Y || !X || !opts) return fail(c, MP_EINVAL, "Y, X and opts must not be NULL");
+  if (ldy < c->n || ldx < c->m || (R && ldr < c->n))
+    return fail(c, MP_EINVAL, "leading dimensions must be >= the column lengths");
+  if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
+    return fail(c, MP_EINVAL, "eps must be finite and >= 0");
+  if (opts->max_iters < 0) return fail(c, MP_EINVAL, "max_iters must be >= 0");
+  if (opts->flags != 0) return fail(c, MP_EINVAL, "opts.flags must be 0");
+  if (opts->rescore_k < 0 || opts->rescore_k > 8)
+    return fail(c, MP_EINVAL, "rescore_k must be in 0..8");
+  long long tmax = opts->max_iters;
+  if (max_iters_b) {
+    tmax = 0;
+    for (int64_t b = 0; b < B; ++b) {
+      if (max_iters_b[b] < 0) return fail(c, MP_EINVAL, "max_iters_b entries must be >= 0");
+      tmax = std::max<long long>(tmax, max_iters_b[b]);
+    }
+  }
+  mp_trace tr{};
+  if (trace) {
+    if (trace->cap < 0) return fail(c, MP_EINVAL, "trace cap must be >= 0");
+    tr = *trace;
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mp_status st = ensure_batched(c, B, s);
+  if (st != MP_OK) return st;
+  const int rk = opts->rescore_k == 0 ? mp::kLpTopK : opts->rescore_k;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  if (max_iters_b)
+    HIP_TRY(c, hipMemcpyAsync(c->b_tcap, max_iters_b, sizeof(long long) * B,
+                              hipMemcpyHostToDevice, s));
+  int* act0 = c->b_act;
+  int* act1 = c->b_act + c->bcap;
+  HIP_TRY(c, mp::launch_binit(Y, ldy, c->n, c->ld, X, ldx, c->m, c->b_r32, c->b_rq, c->b_slots,
+                              max_iters_b ? c->b_tcap : nullptr, opts->max_iters, opts->eps,
+                              static_cast<int>(B), act0, act1, c->b_state, s));
+
+  // Rounds in chunks, two chunks in flight; the kernels stop doing work once
+  // the active list is empty.  No signal runs more than tmax rounds.
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
+  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
+  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
+  long long issued = 0;
+  int chunk = 4, next = 0, inflight = 0;
+  long long slot_base[2] = {0, 0};
+  int slot_len[2] = {0, 0};
+  bool finished = false;
+  mp_status status = MP_OK;
+  // upper bound on the active count used to size each round's grids: all
+  // B at first, then the count read back after each completed chunk
+  int nact_hint = static_cast<int>(B);
+  auto account = [&](int k, int n_after) {
+    if (!c->profiling) return;
+    (void)n_after;
+    for (int j = 0; j < slot_len[k]; ++j) {
+      if ((slot_base[k] + j) % c->prof_every != 0) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
+                              c->ev[(k * kMaxChunk + j) * 2 + 1]) == hipSuccess) {
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+      }
+    }
+  };
+  while (!finished && status == MP_OK) {
+    while (inflight < 2 && issued < tmax && status == MP_OK) {
+      const int k = next;
+      const int len = static_cast<int>(std::min<long long>(chunk, tmax - issued));
+      for (int j = 0; j < len; ++j) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->profiling && (issued + j) % c->prof_every == 0) {
+          e0 = c->ev[(k * kMaxChunk + j) * 2];
+          e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
+        }
+        hipError_t e = mp::launch_bround(c->psib, c->psi32, c->ld, c->n, c->m, c->b_r32, c->b_rq,
+                                         X, ldx, c->b_slots, act0, act1, c->b_state,
+                                         c->b_partials, c->b_alive, static_cast<int>(B),
+                                         nact_hint, rk, tr, s, e0, e1);
+        if (e != hipSuccess) {
+          status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+          break;
+        }
+      }
+      if (status != MP_OK) break;
+      slot_base[k] = issued;
+      slot_len[k] = len;
+      issued += len;
+      hipError_t e = hipMemcpyAsync(&c->h_bstate[k], c->b_state, sizeof(mp::BState),
+                                    hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(done_ev[k], s);
+      if (e != hipSuccess) {
+        status = fail(c, MP_EDEVICE, std::string("state copy: ") + hipGetErrorString(e));
+        break;
+      }
+      ++inflight;
+      next ^= 1;
+      chunk = std::min(chunk * 2, kMaxChunk);
+    }
+    if (status != MP_OK || inflight == 0) break;
+    const int old = inflight == 2 ? next : (next ^ 1);
+    hipError_t e = hipEventSynchronize(done_ev[old]);
+    if (e != hipSuccess) {
+      status = fail(c, MP_EDEVICE, std::string("sync: ") + hipGetErrorString(e));
+      break;
+    }
+    --inflight;
+    const mp::BState& hb = c->h_bstate[old];
+    const int n_after = hb.n_active[hb.cur & 1];
+    account(old, n_after);
+    // rounds already in flight were sized with the older hint, which is also
+    // an upper bound; the count never increases
+    nact_hint = std::min(nact_hint, n_after);
+    if (n_after == 0) finished = true;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && status == MP_OK)
+    status = fail(c, MP_EDEVICE, "stream synchronize failed");
+  (void)hipEventDestroy(done_ev[0]);
+  (void)hipEventDestroy(done_ev[1]);
+  if (status != MP_OK) return status;
+
+  if (R)
+    HIP_TRY(c, hipMemcpy2DAsync(R, ldr * sizeof(float), c->b_r32, c->ld * sizeof(float),
+                                c->n * sizeof(float), B, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_slots, c->b_slots, sizeof(mp::BSlot) * B, hipMemcpyDeviceToHost,
+                            s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  bool nonfinite = false, internal = false;
+  for (int64_t b = 0; b < B; ++b) {
+    const mp::BSlot& d = c->h_slots[b];
+    nonfinite |= d.reason == mp::kStopNonFinite;
+    internal |= d.reason == mp::kStopInternal;
+    if (res) {
+      res[b].iters = d.t;
+      res[b].yy = d.yy;
+      res[b].rr = d.rr;
+      res[b].stop_reason = d.reason;
+      res[b].reserved = 0;
+    }
+  }
+  if (internal)
+    return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
+  if (nonfinite) return fail(c, MP_ENONFINITE, "a column of Y holds NaN or Inf");
   return MP_OK;
 }
 

@@ -71,6 +71,33 @@ hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m
                               const CorrGeom& g, uint64_t* keys, float* x, DevState* st,
                               mp_trace tr, hipStream_t s);
 
+// ---- batched decode against one dictionary (k_batched.hip) ------------------
+// Per-signal state; written only by the workgroup handling that signal.
+struct BSlot {
+  double yy, rr, thr;
+  long long t, max_iters;
+  int done, reason;
+};
+// Round state: the current active list is act[cur] with n_active[cur] entries.
+struct BState {
+  int cur;
+  int n_active[2];
+  unsigned arrive;  // workgroups of the current select launch that have counted in
+};
+hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, float* X,
+                        int64_t ldx, int64_t m, float* R32, uint16_t* Rq, BSlot* slots,
+                        const long long* tcap, long long tcap_all, double eps, int nslots,
+                        int* act0, int* act1, BState* bs, hipStream_t s);
+int bcorr_tile_m(int nact_hint);
+int bcorr_mtiles(int64_t m, int tile_m);
+// One round.  nact_hint >= the number of active signals (the host's last
+// reading; the count only decreases): it sizes the grids and picks the tile.
+hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, int64_t n,
+                         int64_t m, float* R32, uint16_t* Rq, float* X, int64_t ldx,
+                         BSlot* slots, int* act0, int* act1, BState* bs, uint64_t* partials,
+                         uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
+                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+
 // ---- reduced-precision storage (k_lowp.hip) ---------------------------------
 constexpr int kLpTopK = 8;  // candidates kept per pass and re-scored in FP32
 hipError_t launch_quant_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* out,
@@ -106,5 +133,19 @@ struct mp_ctx {
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
   int rescore_k = mp::kLpTopK;   // for the current decode
+  // batched decode: BF16 dictionary copy and per-signal buffers (grown on demand)
+  uint16_t* psib = nullptr;      // == psiq for MP_BF16 storage, else owned here
+  bool psib_owned = false;
+  int64_t bcap = 0;              // signal slots allocated
+  float* b_r32 = nullptr;        // bcap x ld
+  uint16_t* b_rq = nullptr;      // bcap x ld
+  mp::BSlot* b_slots = nullptr;
+  mp::BSlot* h_slots = nullptr;  // pinned
+  int* b_act = nullptr;          // 2 x bcap
+  mp::BState* b_state = nullptr;
+  mp::BState* h_bstate = nullptr;  // pinned, 2 entries
+  uint64_t* b_partials = nullptr;  // bcap x mtiles x 8
+  uint64_t* b_alive = nullptr;     // bcap
+  long long* b_tcap = nullptr;     // bcap
   std::string err;
 };

@@ -73,6 +73,9 @@ def _load():
     lib.mp_status_str.argtypes = [ctypes.c_int]
     lib.mp_last_error.restype = ctypes.c_char_p
     lib.mp_last_error.argtypes = [p]
+    lib.mp_solve_batched.restype = ctypes.c_int
+    lib.mp_solve_batched.argtypes = [p, p, i64, i64, p, i64, p, i64, ctypes.POINTER(Opts), p,
+                                     p, ctypes.POINTER(Trace), p]
     lib.mp_get_storage.restype = ctypes.c_int
     lib.mp_get_storage.argtypes = [p, p, p, p]
     lib.mp_set_profiling.restype = ctypes.c_int
@@ -133,6 +136,21 @@ def mp_solve(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
     st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
                           ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve", ctx)
+    return res
+
+
+def mp_solve_batched(ctx, y_ptr: int, ldy: int, nb: int, x_ptr: int, ldx: int,
+                     r_ptr: Optional[int], ldr: int, opts: Opts, max_iters_b=None,
+                     trace: Optional[Trace] = None, stream: Optional[int] = None):
+    """Returns a ctypes array of ``nb`` Result structures."""
+    res = (Result * max(nb, 1))()
+    caps = None
+    if max_iters_b is not None:
+        caps = (ctypes.c_int64 * max(nb, 1))(*[int(v) for v in max_iters_b])
+    st = _load().mp_solve_batched(ctx, y_ptr, ldy, nb, x_ptr, ldx, r_ptr, ldr, ctypes.byref(opts),
+                                  caps, res, ctypes.byref(trace) if trace is not None else None,
+                                  stream)
+    _check(st, "mp_solve_batched", ctx)
     return res
 
 
@@ -239,6 +257,49 @@ class Decoder:
         if tr is not None:
             k = min(res.iters, trace_cap)
             out.update(idx=tidx[:k], coef=tcoef[:k], rr_trace=trr[:k])
+        return out
+
+    def solve_batched(self, y: torch.Tensor, eps: float, max_iters, trace_cap: int = 0,
+                      rescore_k: int = 0, want_r: bool = True, stream=None):
+        """Decode the columns of ``y`` ((N, B) float32 CUDA, column-major).
+
+        ``max_iters``: one cap for all signals, or a sequence of B caps.
+        Returns dict(x (M, B), r (N, B) or None, iters, yy, rr, stop (lists), and
+        with ``trace_cap`` idx/coef/rr_trace of shape (B, trace_cap))."""
+        if not y.is_cuda or y.dtype != torch.float32 or y.dim() != 2 or y.shape[0] != self.n:
+            raise ValueError("y must be a (N, B) float32 CUDA tensor")
+        nb = y.shape[1]
+        if nb > 1 and y.stride(0) != 1:
+            raise ValueError("y must be column-major: stride(0) == 1")
+        ldy = max(y.stride(1) if nb > 1 else self.n, self.n)
+        dev = y.device
+        x = torch.empty((max(nb, 1), self.m), dtype=torch.float32, device=dev)
+        r = torch.empty((max(nb, 1), self.n), dtype=torch.float32, device=dev) if want_r else None
+        tr = None
+        tidx = tcoef = trr = None
+        if trace_cap > 0:
+            tidx = torch.full((max(nb, 1), trace_cap), -1, dtype=torch.int32, device=dev)
+            tcoef = torch.zeros((max(nb, 1), trace_cap), dtype=torch.float32, device=dev)
+            trr = torch.zeros((max(nb, 1), trace_cap), dtype=torch.float64, device=dev)
+            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+        per = None
+        if isinstance(max_iters, (list, tuple)) or hasattr(max_iters, "__len__"):
+            per = [int(v) for v in max_iters]
+            if len(per) != nb:
+                raise ValueError("need one cap per signal")
+            cap_all = max(per) if per else 0
+        else:
+            cap_all = int(max_iters)
+        opts = Opts(float(eps), cap_all, int(rescore_k), 0)
+        res = mp_solve_batched(self._ctx, y.data_ptr(), ldy, nb, x.data_ptr(), self.m,
+                               _ptr(r), self.n, opts, per, tr, _stream_ptr(stream))
+        out = dict(x=x[:nb].t(), r=None if r is None else r[:nb].t(),
+                   iters=[res[i].iters for i in range(nb)], yy=[res[i].yy for i in range(nb)],
+                   rr=[res[i].rr for i in range(nb)],
+                   stop=[STOP_NAMES.get(res[i].stop_reason, res[i].stop_reason)
+                         for i in range(nb)])
+        if tr is not None:
+            out.update(idx=tidx[:nb], coef=tcoef[:nb], rr_trace=trr[:nb])
         return out
 
     def storage_copy(self, stream=None):
