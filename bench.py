@@ -134,6 +134,53 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
     return out
 
 
+def bench_ragged(seed: int, storage: str = "f32", reps: int = 3, tune_reps: int = 1):
+    """Ragged workload: 512 independent problems, N_i ~ U{128,256,512,1024},
+    M_i = 4 N_i, K_i = N_i / 16, eps = 1e-5, T_i = 20 K_i, each with its own
+    dictionary, decoded in one persistent graph-replayed launch whose shape
+    the autotuner picks.  Reports problems/s and the aggregate algorithmic
+    dictionary bandwidth sum_i iters_i * bytes(Psi_i) / time."""
+    import numpy as np
+    import torch
+
+    import mpgen
+    from paper_0809_1833_amd import tune
+    from paper_0809_1833_amd.mp import RaggedDecoder
+
+    probs = mpgen.make_ragged(seed)
+    caps = [p.max_iters for p in probs]
+    psis = [torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t() for p in probs]
+    yp = torch.from_numpy(np.concatenate([p.y for p in probs]).astype(np.float32)).cuda()
+    esize = 4.0 if storage == "f32" else 2.0
+    out = {"workload": "512 instances, N_i ~ U{128,256,512,1024}, M_i = 4 N_i, K_i = N_i/16, "
+                       f"eps=1e-5, T_i = 20 K_i, own dictionary each, {storage} storage"}
+    with RaggedDecoder(psis, storage=storage) as dec:
+        del psis
+        tuned = tune.tune_ragged(dec, yp, 1e-5, caps, reps=tune_reps, log=log)
+        x = torch.empty(dec.x_off[-1], dtype=torch.float32, device="cuda")
+        dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        dec.set_profiling(1)
+        dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
+        kms, _ = dec.kernel_time()
+        dec.set_profiling(0)
+        nbytes = sum(it * esize * p.n * p.m for it, p in zip(res["iters"], probs))
+        achieved = nbytes / (kms * 1e-3) / 1e9
+        out.update(problems_per_s=round(len(probs) / dt, 2), solve_ms=round(dt * 1e3, 3),
+                   total_iters=sum(res["iters"]), stops=sorted(set(res["stop"])),
+                   config=tuned["config"], tuned_from_cache=tuned["cached"],
+                   roofline={"bound": "hbm", "kernel": "k_ragged", "achieved": round(achieved, 2),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "launch_ms": round(kms, 3)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +194,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form measurement added to the line")
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the ragged-instances measurement added to the line")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every k-th iteration's kernel launch with HIP events")
     ap.add_argument("--max-iters", type=int, default=None,
@@ -248,6 +297,9 @@ def main():
     if not args.no_batched:
         log("[bench] batched form (256 signals, shared dictionary)")
         line["batched"] = bench_batched(args.seed)
+    if not args.no_ragged:
+        log("[bench] ragged instances (512 problems of uneven size)")
+        line["ragged"] = bench_ragged(args.seed)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p)

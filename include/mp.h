@@ -184,6 +184,68 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
                            const int64_t* max_iters_b, mp_result* res, const mp_trace* trace,
                            void* stream);
 
+/* One problem of a ragged set: its own dictionary (device, FP32, column-major
+   N x M with leading dimension ld). */
+typedef struct mp_instance {
+    const float* psi;
+    int64_t n, m, ld;
+} mp_instance;
+
+/* Launch shape of the ragged decode (chosen by the autotuner). */
+typedef struct mp_ragged_config {
+    int32_t threads;        /* workgroup size: 256, 512 or 1024 */
+    int32_t cols_per_wave;  /* columns one wave streams at once: 1, 2 or 4 (MP_BF16: 1) */
+    int32_t wgs_per_cu;     /* persistent workgroups per compute unit: 1..8 */
+    int32_t reserved;
+} mp_ragged_config;
+
+/*
+ * mp_create_ragged -- take `count` independent problems of uneven size, each
+ * with its own dictionary (Section 2, eqs. 3-4, per instance), for decoding
+ * together with mp_solve_ragged.  Each dictionary is copied (padded leading
+ * dimension), checked for finite unit-norm columns like mp_create, and with
+ * MP_BF16 storage also kept as BF16 for the correlation pass (re-scored in
+ * FP32 as for mp_create).
+ *
+ *   inst     host: count descriptors; psi pointers are device memory, may be
+ *            freed after the call; 1 <= n <= 8192, ld >= n, 1 <= m < 2^31
+ *   count    1 <= count < 2^30
+ *   storage  MP_F32 or MP_BF16
+ * Errors: MP_EINVAL (bad arguments, naming the instance), MP_ENONFINITE,
+ * MP_ENOTNORM, MP_ENOMEM, MP_EDEVICE, MP_EUNSUPPORTED (MP_FP8_E4M3, or the
+ * device is not gfx950).
+ */
+mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count, mp_dtype storage,
+                           uint32_t flags, void* stream);
+
+/*
+ * mp_solve_ragged -- decode every instance of a ragged context (the
+ * Section 3 loop per instance) in one persistent launch, replayed from a
+ * captured HIP graph while the arguments stay the same.  Workgroups take
+ * instances largest first; each runs one instance's whole loop.
+ *
+ *   Y        device: the y of all instances packed in instance order
+ *            (instance i starts at n_0 + ... + n_{i-1})
+ *   X        device: the x~ packed the same way by m_i; overwritten
+ *   R        device or NULL: final residuals, packed like Y
+ *   opts     host: eps, max_iters (unless max_iters is given), rescore_k
+ *   max_iters host: count per-instance caps, or NULL
+ *   res      host: count results, or NULL
+ *   trace    host struct of device arrays of count * cap entries, or NULL;
+ *            instance i's step t goes to index i * cap + t
+ * Errors: MP_EINVAL (not a ragged context, NULL Y/X/opts, bad opts or caps),
+ * MP_ENONFINITE (some y holds NaN/Inf; the others are decoded), MP_EDEVICE.
+ */
+mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const mp_opts* opts,
+                          const int64_t* max_iters, mp_result* res, const mp_trace* trace,
+                          void* stream);
+
+/* mp_ragged_set_config / mp_ragged_get_config -- launch shape of
+   mp_solve_ragged (results do not depend on it).  Errors: MP_EINVAL (not a
+   ragged context, or a shape outside the listed values). */
+mp_status mp_ragged_set_config(mp_ctx* ctx, const mp_ragged_config* cfg);
+mp_status mp_ragged_get_config(const mp_ctx* ctx, mp_ragged_config* cfg);
+
 /*
  * mp_destroy -- free everything the context owns.  NULL is a no-op.
  */
@@ -214,8 +276,9 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
  * makes one MP iteration (the pass over the whole dictionary, eq. 9, with the
  * selection and update of eqs. 10-12 at its tail) during the last mp_solve,
  * or of the matrix-product kernel (the correlations of all active signals)
- * during the last mp_solve_batched, measured with HIP events recorded around
- * the launch on the decode stream.
+ * during the last mp_solve_batched, or of the whole persistent launch of the
+ * last mp_solve_ragged, measured with HIP events recorded around the launch
+ * on the decode stream.
  *
  *   every     0: off.  k > 0: time every k-th iteration's launch (events
  *             around every launch add a little time between launches).

@@ -12,6 +12,7 @@
 // the last workgroup of each round compacts the list of active signals, so
 // the next round's product covers only those.
 #include "k_common.h"
+#include "k_lowp.h"
 #include "mp_internal.h"
 
 namespace mp {
@@ -20,43 +21,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8bf;
 
 constexpr int kBThreads = 256;              // 4 waves (init and compaction)
 constexpr int kBSelThreads = 512;           // 8 waves: one per re-scored candidate
-constexpr int kBTopK = 8;
-
-__device__ inline uint16_t bf16_rne_b(float v) {
-  uint32_t u = __builtin_bit_cast(uint32_t, v);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-
-// Sorted (descending) top-8 list of keys; 0 = empty.
-__device__ inline void topk_insert(uint64_t (&L)[kBTopK], uint64_t key) {
-  if (key <= L[kBTopK - 1]) return;
-#pragma unroll
-  for (int j = 0; j < kBTopK; ++j) {
-    if (key > L[j]) {
-      const uint64_t t = L[j];
-      L[j] = key;
-      key = t;
-    }
-  }
-}
-
-// The 8 largest keys over the lanes' sorted lists; lane j < 8 receives the
-// j-th largest.  Keys are distinct apart from 0.
-__device__ inline uint64_t wave_top8_lists(uint64_t (&L)[kBTopK], int lane) {
-  uint64_t out = 0;
-#pragma unroll
-  for (int j = 0; j < kBTopK; ++j) {
-    const uint64_t w = wave_max(L[0]);
-    if (lane == j) out = w;
-    if (w != 0 && L[0] == w) {  // pop the head of the list that held it
-#pragma unroll
-      for (int q = 0; q + 1 < kBTopK; ++q) L[q] = L[q + 1];
-      L[kBTopK - 1] = 0;
-    }
-  }
-  return out;
-}
+constexpr int kBTopK = kTopK;
 
 // ---------------------------------------------------------------------------
 // Init: every signal slot b < B.  r = y (zero padded), its BF16 copy, x~ = 0,
@@ -77,7 +42,7 @@ __global__ __launch_bounds__(kBThreads) void k_binit(
   for (int64_t i = threadIdx.x; i < ld; i += kBThreads) {
     const float v = i < n ? y[i] : 0.0f;
     r[i] = v;
-    rq[i] = bf16_rne_b(v);
+    rq[i] = bf16_rne(v);
     s += static_cast<double>(v) * v;
   }
   const double yy = block_sum<kBThreads>(s, red);
@@ -287,7 +252,7 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
     constexpr int RP = TM / 4;
     for (int rr = wave * RP; rr < wave * RP + RP; ++rr) {
       const int64_t atom = m0 + rr;
-      if (atom < m) topk_insert(L, make_key(ctile[1][rr][lane], static_cast<int>(atom)));
+      if (atom < m) top8_insert(L, make_key(ctile[1][rr][lane], static_cast<int>(atom)));
     }
 #pragma unroll
     for (int q = 0; q < kBTopK; ++q) lists[wave][lane][q] = L[q];
@@ -295,7 +260,7 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
     if (wave == 0 && j0 + lane < nact) {
       for (int p = 1; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < kBTopK; ++q) topk_insert(L, lists[p][lane][q]);
+        for (int q = 0; q < kBTopK; ++q) top8_insert(L, lists[p][lane][q]);
       uint64_t* out =
           partials + (static_cast<int64_t>(j0 + lane) * mtiles + blockIdx.x) * kBTopK;
 #pragma unroll
@@ -336,7 +301,7 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
 #pragma unroll
   for (int q = 0; q < kBTopK; ++q) L[q] = 0;
   const uint64_t* pk = partials + static_cast<int64_t>(j) * mtiles * kBTopK;
-  for (int i = threadIdx.x; i < mtiles * kBTopK; i += kBSelThreads) topk_insert(L, pk[i]);
+  for (int i = threadIdx.x; i < mtiles * kBTopK; i += kBSelThreads) top8_insert(L, pk[i]);
   const uint64_t w8 = wave_top8_lists(L, lane);
   if (lane < kBTopK) wl[wave][lane] = w8;
   __syncthreads();
@@ -393,7 +358,7 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     for (int64_t i = threadIdx.x; i < ld; i += kBSelThreads) {
       const float v = __builtin_fmaf(-c, colp[i], r[i]);  // padding rows stay 0
       r[i] = v;
-      rq[i] = bf16_rne_b(v);
+      rq[i] = bf16_rne(v);
       s += static_cast<double>(v) * v;
     }
     const double rr = block_sum<kBSelThreads>(s, dred);

@@ -1,0 +1,128 @@
+// Shared pieces of the reduced-precision and multi-candidate kernels:
+// BF16 rounding, reduced-precision inner products against an FP32 residual
+// in LDS, and top-8 lists of packed candidate keys.
+#pragma once
+
+#include "k_common.h"
+
+namespace mp {
+
+typedef float v2f __attribute__((ext_vector_type(2)));
+constexpr int kTopK = 8;
+
+// FP32 -> BF16 bit pattern, round to nearest even (finite inputs).
+__device__ inline uint16_t bf16_rne(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Reduced-precision inner products.  S = bytes per element (2: BF16, 1: FP8);
+// one 16-byte load holds E = 16 / S elements, matched by E / 4 float4s of r.
+
+template <int S>
+__device__ inline void lp_fma(v4u q, const v4f* __restrict__ rv, float& acc) {
+  if constexpr (S == 2) {
+    const v4f b0 = rv[0], b1 = rv[1];
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.x << 16), b0.x, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.x & 0xFFFF0000u), b0.y, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.y << 16), b0.z, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.y & 0xFFFF0000u), b0.w, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.z << 16), b1.x, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.z & 0xFFFF0000u), b1.y, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.w << 16), b1.z, acc);
+    acc = __builtin_fmaf(__builtin_bit_cast(float, q.w & 0xFFFF0000u), b1.w, acc);
+  } else {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const v4f b = rv[w];
+      const unsigned word = q[w];
+      // gfx950 decodes OCP e4m3fn exactly: bytes 0,1 then bytes 2,3
+      const v2f lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(word), false);
+      const v2f hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(word), true);
+      acc = __builtin_fmaf(lo.x, b.x, acc);
+      acc = __builtin_fmaf(lo.y, b.y, acc);
+      acc = __builtin_fmaf(hi.x, b.z, acc);
+      acc = __builtin_fmaf(hi.y, b.w, acc);
+    }
+  }
+}
+
+template <int S, int U>
+__device__ inline void lp_block(const v4u* __restrict__ p, const v4f* __restrict__ r_lds,
+                                int& i, float& acc) {
+  constexpr int R = 16 / S / 4;  // float4s of r per 16-byte load
+  v4u a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+#pragma unroll
+  for (int u = 0; u < U; ++u) lp_fma<S>(a[u], r_lds + (i + kWave * u) * R, acc);
+  i += kWave * U;
+}
+
+// Reduced-precision <r, psi_col> (before the FP8 scale) by one wave; nq
+// 16-byte chunks per column.
+template <int S>
+__device__ inline float dot_column_lp(const v4u* __restrict__ p, const v4f* __restrict__ r_lds,
+                                      int nq, int lane) {
+  float acc = 0.0f;
+  int i = lane;
+  while (i + kWave * 7 < nq) lp_block<S, 8>(p, r_lds, i, acc);
+  if (i + kWave * 3 < nq) lp_block<S, 4>(p, r_lds, i, acc);
+  if (i + kWave * 1 < nq) lp_block<S, 2>(p, r_lds, i, acc);
+  if (i < nq) lp_block<S, 1>(p, r_lds, i, acc);
+  return wave_sum(acc);
+}
+
+// ---------------------------------------------------------------------------
+// Top-8 lists of packed keys (larger key = larger |c|, then smaller index;
+// 0 = empty).
+
+// Insert into a sorted (descending) list; the smallest entry falls out.
+__device__ inline void top8_insert(uint64_t (&L)[kTopK], uint64_t key) {
+  if (key <= L[kTopK - 1]) return;
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) {
+    if (key > L[j]) {
+      const uint64_t t = L[j];
+      L[j] = key;
+      key = t;
+    }
+  }
+}
+
+// The 8 largest of the 128 keys a wave holds (two per lane); lane j < 8
+// receives the j-th largest.  Keys are distinct apart from 0.
+__device__ inline uint64_t wave_top8(uint64_t a, uint64_t b, int lane) {
+  uint64_t out = 0;
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) {
+    const uint64_t w = wave_max(a > b ? a : b);
+    if (lane == j) out = w;
+    if (w != 0) {
+      if (a == w) a = 0;
+      else if (b == w) b = 0;
+    }
+  }
+  return out;
+}
+
+// The 8 largest keys over the lanes' sorted lists; lane j < 8 receives the
+// j-th largest.  Keys are distinct apart from 0.
+__device__ inline uint64_t wave_top8_lists(uint64_t (&L)[kTopK], int lane) {
+  uint64_t out = 0;
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) {
+    const uint64_t w = wave_max(L[0]);
+    if (lane == j) out = w;
+    if (w != 0 && L[0] == w) {  // pop the head of the list that held it
+#pragma unroll
+      for (int q = 0; q + 1 < kTopK; ++q) L[q] = L[q + 1];
+      L[kTopK - 1] = 0;
+    }
+  }
+  return out;
+}
+
+}  // namespace mp

@@ -1,0 +1,282 @@
+// Many independent Matching Pursuit problems of uneven size in one launch.
+//
+// Every instance has its own dictionary and signal.  A persistent grid of
+// workgroups takes instances from an on-device queue (largest first, as the
+// host ordered them) and each workgroup runs one instance's whole Section 3
+// loop (eqs. 8-12) by itself: the residual stays in LDS, the correlation
+// pass streams the instance's dictionary with every wave taking CC columns at
+// a time, and the argmax (smallest index on ties, eq. 16), the x~ and r
+// updates and the FP64 stopping test use only workgroup barriers.  No
+// workgroup ever waits for another one; each exits when the queue is empty.
+//
+// With BF16 storage each wave keeps the 8 best reduced-precision candidates
+// of its columns; the workgroup merges them, re-scores up to 8 against the
+// FP32 columns and takes the best re-scored one.
+#include "k_common.h"
+#include "k_lowp.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+// <r, psi_c> for CC columns at once by one wave (16-byte loads, 4 per column
+// in flight per lane, then singles), FP32 accumulation, butterfly sums.
+template <int CC>
+__device__ inline void dot_cols_f32(const v4f* const (&p)[CC], const v4f* __restrict__ r_lds,
+                                    int ld4, int lane, float (&acc)[CC]) {
+#pragma unroll
+  for (int c = 0; c < CC; ++c) acc[c] = 0.0f;
+  int i = lane;
+  for (; i + kWave * 3 < ld4; i += kWave * 4) {
+    v4f a[CC][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < CC; ++c) a[c][u] = __builtin_nontemporal_load(p[c] + i + kWave * u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const v4f b = r_lds[i + kWave * u];
+#pragma unroll
+      for (int c = 0; c < CC; ++c) {
+        acc[c] = __builtin_fmaf(a[c][u].x, b.x, acc[c]);
+        acc[c] = __builtin_fmaf(a[c][u].y, b.y, acc[c]);
+        acc[c] = __builtin_fmaf(a[c][u].z, b.z, acc[c]);
+        acc[c] = __builtin_fmaf(a[c][u].w, b.w, acc[c]);
+      }
+    }
+  }
+  for (; i < ld4; i += kWave) {
+    const v4f b = r_lds[i];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const v4f a = __builtin_nontemporal_load(p[c] + i);
+      acc[c] = __builtin_fmaf(a.x, b.x, acc[c]);
+      acc[c] = __builtin_fmaf(a.y, b.y, acc[c]);
+      acc[c] = __builtin_fmaf(a.z, b.z, acc[c]);
+      acc[c] = __builtin_fmaf(a.w, b.w, acc[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CC; ++c) acc[c] = wave_sum(acc[c]);
+}
+
+__global__ void k_ragged_reset(RQueue* q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) q->next = 0u;
+}
+
+template <int NT, int CC, bool LP>
+__global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
+                                               const int* __restrict__ order, int count,
+                                               const float* __restrict__ Y,
+                                               float* __restrict__ X, float* __restrict__ R,
+                                               const long long* __restrict__ caps,
+                                               long long cap_all, double eps, int rescore_k,
+                                               RResult* __restrict__ res,
+                                               RQueue* __restrict__ q, mp_trace tr) {
+  constexpr int W = NT / kWave;
+  extern __shared__ v4f r_lds[];
+  float* rf = reinterpret_cast<float*>(r_lds);
+  __shared__ uint64_t kred[W];
+  __shared__ double dred[W];
+  __shared__ uint64_t lists[16 * kTopK];  // LP: per-wave top-8 lists (zero padded)
+  __shared__ uint64_t cand[kTopK];
+  __shared__ uint64_t resc[kTopK];
+  __shared__ int s_item;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+
+  for (;;) {
+    if (threadIdx.x == 0)
+      s_item = static_cast<int>(
+          __hip_atomic_fetch_add(&q->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();  // s_item is rewritten next time round
+    if (item >= count) break;
+    const int id = order[item];
+    const RInst d = inst[id];
+    const int64_t n = d.n, m = d.m, ld = d.ld;
+    const int ld4 = static_cast<int>(ld / 4);
+    const float* y = Y + d.y_off;
+    float* x = X + d.x_off;
+
+    // ---- init (eq. 8) ----
+    for (int64_t j = threadIdx.x; j < m; j += NT) x[j] = 0.0f;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < ld; i += NT) {
+      const float v = i < n ? y[i] : 0.0f;
+      rf[i] = v;
+      s += static_cast<double>(v) * v;
+    }
+    const double yy = block_sum<NT>(s, dred);
+    const double thr = eps * eps * yy;
+    const long long T = caps ? caps[id] : cap_all;
+    double rr = yy;
+    long long t = 0;
+    int reason;
+    if (!__builtin_isfinite(yy)) {
+      reason = kStopNonFinite;
+    } else if (yy == 0.0) {
+      reason = MP_STOP_ZERO_INPUT;
+    } else {
+      for (;;) {
+        if (!(rr > thr)) {
+          reason = MP_STOP_CONVERGED;
+          break;
+        }
+        if (t >= T) {
+          reason = MP_STOP_MAX_ITERS;
+          break;
+        }
+        // ---- correlation pass (eq. 9) and argmax ----
+        uint64_t best = 0;
+        if constexpr (!LP) {
+          for (int64_t c0 = static_cast<int64_t>(wave) * CC; c0 < m; c0 += W * CC) {
+            const v4f* p[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c)
+              p[c] = reinterpret_cast<const v4f*>(d.psi32 + (c0 + c < m ? c0 + c : c0) * ld);
+            float acc[CC];
+            dot_cols_f32<CC>(p, r_lds, ld4, lane, acc);
+#pragma unroll
+            for (int c = 0; c < CC; ++c) {
+              if (c0 + c < m) {
+                const uint64_t k = make_key(acc[c], static_cast<int>(c0 + c));
+                best = k > best ? k : best;
+              }
+            }
+          }
+          best = block_max<NT>(best, kred);
+        } else {
+          const int nq = static_cast<int>(ld * 2 / 16);
+          const v4u* pq = reinterpret_cast<const v4u*>(d.psib);
+          uint64_t L[kTopK];
+#pragma unroll
+          for (int j = 0; j < kTopK; ++j) L[j] = 0;
+          for (int64_t col = wave; col < m; col += W)
+            top8_insert(L, make_key(dot_column_lp<2>(pq + col * nq, r_lds, nq, lane),
+                                    static_cast<int>(col)));
+          uint64_t v = 0;
+#pragma unroll
+          for (int j = 0; j < kTopK; ++j)
+            if (lane == j) v = L[j];
+          if (lane < kTopK) lists[wave * kTopK + lane] = v;
+          if (wave == 0)  // zero the unused list slots (W < 16)
+            for (int k = W * kTopK + lane; k < 16 * kTopK; k += kWave) lists[k] = 0;
+          __syncthreads();
+          if (wave == 0) {
+            const uint64_t c8 = wave_top8(lists[lane], lists[lane + kWave], lane);
+            if (lane < kTopK) cand[lane] = c8;
+          }
+          __syncthreads();
+          for (int qd = wave; qd < rescore_k; qd += W) {
+            const uint64_t k = cand[qd];
+            uint64_t rk = 0;
+            if (k != 0) {
+              const int idx = key_index(k);
+              if (idx >= 0 && idx < m) {
+                const float c32 = dot_column_f32(
+                    reinterpret_cast<const v4f*>(d.psi32 + static_cast<int64_t>(idx) * ld),
+                    r_lds, ld4, lane);
+                rk = make_key(c32, idx);
+              }
+            }
+            if (lane == 0) resc[qd] = rk;
+          }
+          __syncthreads();
+          for (int qd = 0; qd < rescore_k; ++qd) best = resc[qd] > best ? resc[qd] : best;
+        }
+        const int idx = key_index(best);
+        const float c = key_value(best);
+        if (best == 0 || idx < 0 || idx >= m) {
+          reason = kStopInternal;
+          break;
+        }
+        if (c == 0.0f) {
+          reason = MP_STOP_STALLED;
+          break;
+        }
+        // ---- update (eqs. 10-12); every wave is past the pass (barrier above) ----
+        const float* colp = d.psi32 + static_cast<int64_t>(idx) * ld;
+        s = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += NT) {
+          const float vv = __builtin_fmaf(-c, colp[i], rf[i]);
+          rf[i] = vv;
+          s += static_cast<double>(vv) * vv;
+        }
+        rr = block_sum<NT>(s, dred);  // its barriers publish the new r to all waves
+        if (threadIdx.x == 0) {
+          x[idx] += c;
+          if (t < tr.cap) {
+            const int64_t o = static_cast<int64_t>(id) * tr.cap + t;
+            if (tr.idx) tr.idx[o] = idx;
+            if (tr.coef) tr.coef[o] = c;
+            if (tr.rr) tr.rr[o] = rr;
+          }
+        }
+        ++t;
+      }
+    }
+    if (R)
+      for (int64_t i = threadIdx.x; i < n; i += NT) R[d.y_off + i] = rf[i];
+    if (threadIdx.x == 0) {
+      RResult o;
+      o.t = t;
+      o.yy = yy;
+      o.rr = rr;
+      o.reason = reason;
+      o.pad = 0;
+      res[id] = o;
+    }
+    __syncthreads();  // r_lds and the LDS lists are reused by the next instance
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+template <int NT, int CC, bool LP>
+static hipError_t launch_ragged_t(int grid, size_t lds, const RInst* inst, const int* order,
+                                  int count, const float* Y, float* X, float* R,
+                                  const long long* caps, long long cap_all, double eps,
+                                  int rescore_k, RResult* res, RQueue* q, mp_trace tr,
+                                  hipStream_t s) {
+  // instances have n <= 8192, so the residual needs at most 32 KB of LDS
+  k_ragged<NT, CC, LP><<<dim3(grid), dim3(NT), lds, s>>>(inst, order, count, Y, X, R, caps,
+                                                         cap_all, eps, rescore_k, res, q, tr);
+  return hipGetLastError();
+}
+
+bool ragged_config_valid(const RConfig& cf, bool lp) {
+  const bool nt_ok = cf.threads == 256 || cf.threads == 512 || cf.threads == 1024;
+  const bool cc_ok = lp ? cf.cols_per_wave == 1
+                        : (cf.cols_per_wave == 1 || cf.cols_per_wave == 2 ||
+                           cf.cols_per_wave == 4);
+  return nt_ok && cc_ok && cf.wgs_per_cu >= 1 && cf.wgs_per_cu <= 8;
+}
+
+hipError_t launch_ragged(const RConfig& cf, bool lp, int grid, size_t lds, const RInst* inst,
+                         const int* order, int count, const float* Y, float* X, float* R,
+                         const long long* caps, long long cap_all, double eps, int rescore_k,
+                         RResult* res, RQueue* q, mp_trace tr, hipStream_t s) {
+  k_ragged_reset<<<dim3(1), dim3(64), 0, s>>>(q);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+#define MP_RAGGED_CASE(NT, CC, LP)                                                          \
+  if (cf.threads == NT && cf.cols_per_wave == CC && lp == LP)                               \
+    return launch_ragged_t<NT, CC, LP>(grid, lds, inst, order, count, Y, X, R, caps,         \
+                                       cap_all, eps, rescore_k, res, q, tr, s);
+  MP_RAGGED_CASE(256, 1, false)
+  MP_RAGGED_CASE(256, 2, false)
+  MP_RAGGED_CASE(256, 4, false)
+  MP_RAGGED_CASE(512, 1, false)
+  MP_RAGGED_CASE(512, 2, false)
+  MP_RAGGED_CASE(512, 4, false)
+  MP_RAGGED_CASE(1024, 1, false)
+  MP_RAGGED_CASE(1024, 2, false)
+  MP_RAGGED_CASE(1024, 4, false)
+  MP_RAGGED_CASE(256, 1, true)
+  MP_RAGGED_CASE(512, 1, true)
+  MP_RAGGED_CASE(1024, 1, true)
+#undef MP_RAGGED_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mp

@@ -14,6 +14,7 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr int64_t kMaxN = 16384;          // the residual is staged whole in LDS
+constexpr int64_t kMaxRaggedN = 8192;     // per-instance residual in LDS, 32 KB
 constexpr int64_t kLdAlign = 64;          // padded column length (floats): 256 B aligned
 constexpr int kMaxChunk = 64;             // iterations enqueued per host check
 constexpr double kNormTol = 1e-4;
@@ -57,9 +58,23 @@ void free_batched(mp_ctx* c) {
   c->bcap = 0;
 }
 
+void free_ragged(mp_ctx* c) {
+  (void)hipFree(c->r_psi32);
+  (void)hipFree(c->r_psib);
+  (void)hipFree(c->r_inst);
+  (void)hipFree(c->r_order);
+  (void)hipFree(c->r_caps);
+  (void)hipFree(c->r_res);
+  (void)hipFree(c->r_queue);
+  if (c->h_rres) (void)hipHostFree(c->h_rres);
+  if (c->r_graph) (void)hipGraphExecDestroy(c->r_graph);
+  if (c->r_cap_stream) (void)hipStreamDestroy(c->r_cap_stream);
+}
+
 void free_ctx(mp_ctx* c) {
   if (!c) return;
   free_batched(c);
+  free_ragged(c);
   if (c->psib_owned) (void)hipFree(c->psib);
   (void)hipFree(c->psi32);
   (void)hipFree(c->psiq);
@@ -233,6 +248,7 @@ mp_status mp_kernel_time(const mp_ctx* ctx, double* avg_ms, int64_t* launches) {
 mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* stream) {
   if (!ctx || !codes) return MP_EINVAL;
   mp_ctx* c = const_cast<mp_ctx*>(ctx);
+  if (c->ragged) return fail(c, MP_EINVAL, "not available for a ragged context");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (c->storage == MP_F32) {
     HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(float), c->psi32, c->ld * sizeof(float),
@@ -253,6 +269,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
                    mp_result* res, const mp_trace* trace, void* stream) {
   if (!ctx) return MP_EINVAL;
   ctx->err.clear();
+  if (ctx->ragged) return fail(ctx, MP_EINVAL, "a ragged context is decoded with mp_solve_ragged");
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
   if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
     return fail(ctx, MP_EINVAL, "eps must be finite and >= 0");
@@ -430,6 +447,7 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
   if (!ctx) return MP_EINVAL;
   ctx->err.clear();
   mp_ctx* c = ctx;
+  if (c->ragged) return fail(c, MP_EINVAL, "a ragged context is decoded with mp_solve_ragged");
   if (B < 0) return fail(c, MP_EINVAL, "B must be >= 0");
   if (B == 0) return MP_OK;
   if (B >= (int64_t{1} << 31) / 2) return fail(c, MP_EINVAL, "B too large");
@@ -576,6 +594,284 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
   if (internal)
     return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
   if (nonfinite) return fail(c, MP_ENONFINITE, "a column of Y holds NaN or Inf");
+  return MP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Many independent instances
+
+mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count, mp_dtype storage,
+                           uint32_t flags, void* stream) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, MP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!inst) return fail(nullptr, MP_EINVAL, "inst is NULL");
+  if (count < 1 || count >= (int64_t{1} << 30)) return fail(nullptr, MP_EINVAL, "bad count");
+  if (flags & ~MP_SKIP_NORM_CHECK) return fail(nullptr, MP_EINVAL, "unknown flags");
+  if (storage != MP_F32 && storage != MP_BF16) {
+    if (storage == MP_FP8_E4M3)
+      return fail(nullptr, MP_EUNSUPPORTED, "ragged instances support MP_F32 and MP_BF16");
+    return fail(nullptr, MP_EINVAL, "unknown storage type");
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    const mp_instance& d = inst[i];
+    char buf[96];
+    snprintf(buf, sizeof buf, "instance %lld: ", static_cast<long long>(i));
+    if (!d.psi) return fail(nullptr, MP_EINVAL, std::string(buf) + "psi is NULL");
+    if (d.n < 1 || d.m < 1) return fail(nullptr, MP_EINVAL, std::string(buf) + "n, m must be >= 1");
+    if (d.ld < d.n) return fail(nullptr, MP_EINVAL, std::string(buf) + "ld must be >= n");
+    if (d.n > kMaxRaggedN) return fail(nullptr, MP_EINVAL, std::string(buf) + "n exceeds 8192");
+    if (d.m >= (int64_t{1} << 31)) return fail(nullptr, MP_EINVAL, std::string(buf) + "m too large");
+  }
+  int dev = 0, ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, MP_EDEVICE, "no HIP device");
+  HIP_TRY(nullptr, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(nullptr, hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, MP_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                              ", this library is built for gfx950");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mp_ctx* c = new mp_ctx();
+  c->device = dev;
+  c->num_cus = prop.multiProcessorCount;
+  c->storage = storage;
+  c->ragged = true;
+  c->r_count = count;
+  if (storage == MP_BF16) c->r_cfg.cols_per_wave = 1;  // the BF16 pass takes one column per wave
+  auto bail = [&](mp_status st, const std::string& msg) {
+    free_ctx(c);
+    return fail(nullptr, st, msg);
+  };
+  // packed layout of the copies, descriptors, and the work order
+  std::vector<mp::RInst> desc(static_cast<size_t>(count));
+  std::vector<int64_t> psi_off(static_cast<size_t>(count));
+  int64_t elems = 0, yo = 0, xo = 0, msum = 0;
+  c->r_n.resize(count);
+  c->r_m.resize(count);
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t ld = round_up(inst[i].n, kLdAlign);
+    psi_off[i] = elems;
+    desc[i].n = inst[i].n;
+    desc[i].m = inst[i].m;
+    desc[i].ld = ld;
+    desc[i].y_off = yo;
+    desc[i].x_off = xo;
+    elems += ld * inst[i].m;
+    yo += inst[i].n;
+    xo += inst[i].m;
+    msum += inst[i].m;
+    c->r_max_ld = std::max(c->r_max_ld, ld);
+    c->r_n[i] = inst[i].n;
+    c->r_m[i] = inst[i].m;
+  }
+  c->r_sum_n = yo;
+  c->r_sum_m = xo;
+  if (hipMalloc(&c->r_psi32, sizeof(float) * elems) != hipSuccess)
+    return bail(MP_ENOMEM, "dictionary copies");
+  if (storage == MP_BF16 && hipMalloc(&c->r_psib, sizeof(uint16_t) * elems) != hipSuccess)
+    return bail(MP_ENOMEM, "BF16 copies");
+  if (hipMalloc(&c->r_inst, sizeof(mp::RInst) * count) != hipSuccess ||
+      hipMalloc(&c->r_order, sizeof(int) * count) != hipSuccess ||
+      hipMalloc(&c->r_caps, sizeof(long long) * count) != hipSuccess ||
+      hipMalloc(&c->r_res, sizeof(mp::RResult) * count) != hipSuccess ||
+      hipMalloc(&c->r_queue, sizeof(mp::RQueue)) != hipSuccess ||
+      hipHostMalloc(&c->h_rres, sizeof(mp::RResult) * count, hipHostMallocDefault) != hipSuccess)
+    return bail(MP_ENOMEM, "ragged buffers");
+  if (hipStreamCreateWithFlags(&c->r_cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(MP_EDEVICE, "capture stream");
+  hipError_t e = hipMemsetAsync(c->r_psi32, 0, sizeof(float) * elems, s);
+  for (int64_t i = 0; i < count && e == hipSuccess; ++i)
+    e = hipMemcpy2DAsync(c->r_psi32 + psi_off[i], desc[i].ld * sizeof(float), inst[i].psi,
+                         inst[i].ld * sizeof(float), inst[i].n * sizeof(float), inst[i].m,
+                         hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
+  // column norms of every instance (eq. 4)
+  double* d_norm2 = nullptr;
+  if (hipMalloc(&d_norm2, sizeof(double) * msum) != hipSuccess) return bail(MP_ENOMEM, "norms");
+  std::vector<double> norm2(static_cast<size_t>(msum));
+  int64_t mo = 0;
+  for (int64_t i = 0; i < count && e == hipSuccess; ++i) {
+    e = mp::launch_norms(c->r_psi32 + psi_off[i], desc[i].ld, desc[i].n, desc[i].m,
+                         d_norm2 + mo, nullptr, s);
+    mo += desc[i].m;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(norm2.data(), d_norm2, sizeof(double) * msum, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_norm2);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("norms: ") + hipGetErrorString(e));
+  mo = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    for (int64_t j = 0; j < desc[i].m; ++j) {
+      const double v = norm2[mo + j];
+      char buf[128];
+      if (!isfinite(v)) {
+        snprintf(buf, sizeof buf, "instance %lld column %lld holds NaN or Inf",
+                 static_cast<long long>(i), static_cast<long long>(j));
+        return bail(MP_ENONFINITE, buf);
+      }
+      if (!(flags & MP_SKIP_NORM_CHECK) && fabs(sqrt(v) - 1.0) > kNormTol) {
+        snprintf(buf, sizeof buf, "instance %lld column %lld has norm %.9g",
+                 static_cast<long long>(i), static_cast<long long>(j), sqrt(v));
+        return bail(MP_ENOTNORM, buf);
+      }
+    }
+    mo += desc[i].m;
+  }
+  if (storage == MP_BF16) {
+    // padding rows are zero and quantise to zero: one pass over everything
+    e = mp::launch_quant_bf16(c->r_psi32, elems, 1, c->r_psib, s);
+    if (e != hipSuccess) return bail(MP_EDEVICE, "quantise");
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    desc[i].psi32 = c->r_psi32 + psi_off[i];
+    desc[i].psib = storage == MP_BF16 ? c->r_psib + psi_off[i] : nullptr;
+  }
+  // most work first (iterations grow with n, a pass costs n * m)
+  std::vector<int> order(static_cast<size_t>(count));
+  for (int64_t i = 0; i < count; ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a1, int b1) {
+    const double wa = static_cast<double>(desc[a1].n) * desc[a1].n * desc[a1].m;
+    const double wb = static_cast<double>(desc[b1].n) * desc[b1].n * desc[b1].m;
+    return wa > wb;
+  });
+  e = hipMemcpyAsync(c->r_inst, desc.data(), sizeof(mp::RInst) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->r_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+  *out = c;
+  return MP_OK;
+}
+
+mp_status mp_ragged_set_config(mp_ctx* ctx, const mp_ragged_config* cfg) {
+  if (!ctx || !cfg) return MP_EINVAL;
+  if (!ctx->ragged) return fail(ctx, MP_EINVAL, "not a ragged context");
+  mp::RConfig cf{cfg->threads, cfg->cols_per_wave, cfg->wgs_per_cu};
+  if (!mp::ragged_config_valid(cf, ctx->storage == MP_BF16))
+    return fail(ctx, MP_EINVAL, "threads must be 256/512/1024, cols_per_wave 1/2/4 (BF16: 1), "
+                                "wgs_per_cu 1..8");
+  ctx->r_cfg = cf;
+  return MP_OK;
+}
+
+mp_status mp_ragged_get_config(const mp_ctx* ctx, mp_ragged_config* cfg) {
+  if (!ctx || !cfg || !ctx->ragged) return MP_EINVAL;
+  cfg->threads = ctx->r_cfg.threads;
+  cfg->cols_per_wave = ctx->r_cfg.cols_per_wave;
+  cfg->wgs_per_cu = ctx->r_cfg.wgs_per_cu;
+  cfg->reserved = 0;
+  return MP_OK;
+}
+
+mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const mp_opts* opts,
+                          const int64_t* max_iters, mp_result* res, const mp_trace* trace,
+                          void* stream) {
+  if (!ctx) return MP_EINVAL;
+  ctx->err.clear();
+  mp_ctx* c = ctx;
+  if (!c->ragged) return fail(c, MP_EINVAL, "not a ragged context (use mp_create_ragged)");
+  if (!Y || !X || !opts) return fail(c, MP_EINVAL, "Y, X and opts must not be NULL");
+  if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
+    return fail(c, MP_EINVAL, "eps must be finite and >= 0");
+  if (opts->max_iters < 0) return fail(c, MP_EINVAL, "max_iters must be >= 0");
+  if (opts->flags != 0) return fail(c, MP_EINVAL, "opts.flags must be 0");
+  if (opts->rescore_k < 0 || opts->rescore_k > 8)
+    return fail(c, MP_EINVAL, "rescore_k must be in 0..8");
+  if (max_iters)
+    for (int64_t i = 0; i < c->r_count; ++i)
+      if (max_iters[i] < 0) return fail(c, MP_EINVAL, "max_iters entries must be >= 0");
+  mp_trace tr{};
+  if (trace) {
+    if (trace->cap < 0) return fail(c, MP_EINVAL, "trace cap must be >= 0");
+    tr = *trace;
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool lp = c->storage == MP_BF16;
+  const int rk = opts->rescore_k == 0 ? mp::kLpTopK : opts->rescore_k;
+  const long long* caps = max_iters ? c->r_caps : nullptr;
+  if (max_iters)
+    HIP_TRY(c, hipMemcpyAsync(c->r_caps, max_iters, sizeof(long long) * c->r_count,
+                              hipMemcpyHostToDevice, s));
+  int grid = c->num_cus * c->r_cfg.wgs_per_cu;
+  if (grid > c->r_count) grid = static_cast<int>(c->r_count);
+  const size_t lds = static_cast<size_t>(c->r_max_ld) * sizeof(float);
+
+  // (re)capture the solve as a graph when its arguments change
+  struct Key {
+    const void *y, *x, *r, *caps, *ti, *tc, *trr;
+    double eps;
+    long long cap_all, tcap;
+    int rk, threads, cc, grid;
+  } key{Y, X, R, caps, tr.idx, tr.coef, tr.rr, opts->eps, opts->max_iters, tr.cap, rk,
+        c->r_cfg.threads, c->r_cfg.cols_per_wave, grid};
+  const unsigned char* kb = reinterpret_cast<const unsigned char*>(&key);
+  std::vector<unsigned char> kv(kb, kb + sizeof key);
+  if (!c->r_graph || kv != c->r_graph_key) {
+    if (c->r_graph) {
+      (void)hipGraphExecDestroy(c->r_graph);
+      c->r_graph = nullptr;
+    }
+    HIP_TRY(c, hipStreamBeginCapture(c->r_cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = mp::launch_ragged(c->r_cfg, lp, grid, lds, c->r_inst, c->r_order,
+                                      static_cast<int>(c->r_count), Y, X, R, caps,
+                                      opts->max_iters, opts->eps, rk, c->r_res, c->r_queue, tr,
+                                      c->r_cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(c->r_cap_stream, &g);
+    if (le != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, MP_EDEVICE, std::string("capture: ") +
+                                     hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipError_t ie = hipGraphInstantiate(&c->r_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      c->r_graph = nullptr;
+      return fail(c, MP_EDEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
+    }
+    c->r_graph_key = kv;
+  }
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    e0 = c->ev[0];
+    e1 = c->ev[1];
+    HIP_TRY(c, hipEventRecord(e0, s));
+  }
+  HIP_TRY(c, hipGraphLaunch(c->r_graph, s));
+  if (e1) HIP_TRY(c, hipEventRecord(e1, s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_rres, c->r_res, sizeof(mp::RResult) * c->r_count,
+                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (e1) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+      c->prof_ms = ms;
+      c->prof_launches = 1;
+    }
+  }
+  bool nonfinite = false, internal = false;
+  for (int64_t i = 0; i < c->r_count; ++i) {
+    const mp::RResult& d = c->h_rres[i];
+    nonfinite |= d.reason == mp::kStopNonFinite;
+    internal |= d.reason == mp::kStopInternal;
+    if (res) {
+      res[i].iters = d.t;
+      res[i].yy = d.yy;
+      res[i].rr = d.rr;
+      res[i].stop_reason = d.reason;
+      res[i].reserved = 0;
+    }
+  }
+  if (internal)
+    return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
+  if (nonfinite) return fail(c, MP_ENONFINITE, "an instance's y holds NaN or Inf");
   return MP_OK;
 }
 

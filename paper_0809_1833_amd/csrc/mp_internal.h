@@ -98,6 +98,32 @@ hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, i
                          uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
                          hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
+// ---- many independent instances (k_ragged.hip) -------------------------------
+struct RInst {             // one instance, device-resident descriptor
+  const float* psi32;      // ld x m FP32 copy (zero padded rows)
+  const uint16_t* psib;    // ld x m BF16 copy, or null
+  int64_t n, m, ld;
+  int64_t y_off, x_off;    // offsets of the instance in the packed Y / R and X
+};
+struct RResult {
+  long long t;
+  double yy, rr;
+  int reason, pad;
+};
+struct RQueue {
+  unsigned next;           // next position of the instance order to take
+};
+struct RConfig {           // launch shape, chosen by the autotuner
+  int threads;             // workgroup size: 256, 512 or 1024
+  int cols_per_wave;       // columns a wave streams at once: 1, 2 or 4 (BF16: 1)
+  int wgs_per_cu;          // persistent workgroups per CU
+};
+bool ragged_config_valid(const RConfig& cf, bool lp);
+hipError_t launch_ragged(const RConfig& cf, bool lp, int grid, size_t lds, const RInst* inst,
+                         const int* order, int count, const float* Y, float* X, float* R,
+                         const long long* caps, long long cap_all, double eps, int rescore_k,
+                         RResult* res, RQueue* q, mp_trace tr, hipStream_t s);
+
 // ---- reduced-precision storage (k_lowp.hip) ---------------------------------
 constexpr int kLpTopK = 8;  // candidates kept per pass and re-scored in FP32
 hipError_t launch_quant_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* out,
@@ -147,5 +173,23 @@ struct mp_ctx {
   uint64_t* b_partials = nullptr;  // bcap x mtiles x 8
   uint64_t* b_alive = nullptr;     // bcap
   long long* b_tcap = nullptr;     // bcap
+  // ragged contexts (mp_create_ragged): many instances, each its own dictionary
+  bool ragged = false;
+  int64_t r_count = 0;
+  int64_t r_sum_n = 0, r_sum_m = 0, r_max_ld = 0;
+  float* r_psi32 = nullptr;        // all instances' FP32 copies, packed
+  uint16_t* r_psib = nullptr;      // all BF16 copies, packed (MP_BF16 storage)
+  mp::RInst* r_inst = nullptr;     // device descriptors
+  int* r_order = nullptr;          // device: instance ids, most work first
+  long long* r_caps = nullptr;     // device: per-instance caps
+  mp::RResult* r_res = nullptr;    // device results
+  mp::RResult* h_rres = nullptr;   // pinned host copy
+  mp::RQueue* r_queue = nullptr;
+  mp::RConfig r_cfg{1024, 2, 1};
+  std::vector<int64_t> r_n, r_m;   // host copies of the sizes
+  // the solve captured as a graph (replayed while its arguments are unchanged)
+  hipStream_t r_cap_stream = nullptr;
+  hipGraphExec_t r_graph = nullptr;
+  std::vector<unsigned char> r_graph_key;
   std::string err;
 };

@@ -44,6 +44,16 @@ class Trace(ctypes.Structure):
                 ("cap", ctypes.c_int64)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("psi", ctypes.c_void_p), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("ld", ctypes.c_int64)]
+
+
+class RaggedConfig(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("cols_per_wave", ctypes.c_int32),
+                ("wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class MPError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -76,6 +86,16 @@ def _load():
     lib.mp_solve_batched.restype = ctypes.c_int
     lib.mp_solve_batched.argtypes = [p, p, i64, i64, p, i64, p, i64, ctypes.POINTER(Opts), p,
                                      p, ctypes.POINTER(Trace), p]
+    lib.mp_create_ragged.restype = ctypes.c_int
+    lib.mp_create_ragged.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Instance),
+                                     i64, ctypes.c_int, u32, p]
+    lib.mp_solve_ragged.restype = ctypes.c_int
+    lib.mp_solve_ragged.argtypes = [p, p, p, p, ctypes.POINTER(Opts), p, p,
+                                    ctypes.POINTER(Trace), p]
+    lib.mp_ragged_set_config.restype = ctypes.c_int
+    lib.mp_ragged_set_config.argtypes = [p, ctypes.POINTER(RaggedConfig)]
+    lib.mp_ragged_get_config.restype = ctypes.c_int
+    lib.mp_ragged_get_config.argtypes = [p, ctypes.POINTER(RaggedConfig)]
     lib.mp_get_storage.restype = ctypes.c_int
     lib.mp_get_storage.argtypes = [p, p, p, p]
     lib.mp_set_profiling.restype = ctypes.c_int
@@ -152,6 +172,40 @@ def mp_solve_batched(ctx, y_ptr: int, ldy: int, nb: int, x_ptr: int, ldx: int,
                                   stream)
     _check(st, "mp_solve_batched", ctx)
     return res
+
+
+def mp_create_ragged(instances, storage: int = MP_F32, flags: int = 0,
+                     stream: Optional[int] = None) -> ctypes.c_void_p:
+    """``instances``: sequence of (psi_ptr, n, m, ld)."""
+    arr = (Instance * len(instances))(*[Instance(*t) for t in instances])
+    h = ctypes.c_void_p()
+    st = _load().mp_create_ragged(ctypes.byref(h), arr, len(instances), storage, flags, stream)
+    _check(st, "mp_create_ragged", None)
+    return h
+
+
+def mp_solve_ragged(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts, count: int,
+                    max_iters=None, trace: Optional[Trace] = None,
+                    stream: Optional[int] = None):
+    res = (Result * count)()
+    caps = None
+    if max_iters is not None:
+        caps = (ctypes.c_int64 * count)(*[int(v) for v in max_iters])
+    st = _load().mp_solve_ragged(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), caps, res,
+                                 ctypes.byref(trace) if trace is not None else None, stream)
+    _check(st, "mp_solve_ragged", ctx)
+    return res
+
+
+def mp_ragged_set_config(ctx, threads: int, cols_per_wave: int, wgs_per_cu: int) -> None:
+    cfg = RaggedConfig(threads, cols_per_wave, wgs_per_cu, 0)
+    _check(_load().mp_ragged_set_config(ctx, ctypes.byref(cfg)), "mp_ragged_set_config", ctx)
+
+
+def mp_ragged_get_config(ctx):
+    cfg = RaggedConfig()
+    _check(_load().mp_ragged_get_config(ctx, ctypes.byref(cfg)), "mp_ragged_get_config", ctx)
+    return dict(threads=cfg.threads, cols_per_wave=cfg.cols_per_wave, wgs_per_cu=cfg.wgs_per_cu)
 
 
 def mp_destroy(ctx) -> None:
@@ -318,4 +372,107 @@ class Decoder:
 
     def kernel_time(self):
         """(mean correlation-kernel launch time in ms, launches counted)."""
+        return mp_kernel_time(self._ctx)
+
+
+class RaggedDecoder:
+    """Independent problems of uneven size (``mp_create_ragged``).
+
+    ``psis``: list of (N_i, M_i) float32 CUDA tensors, column-major.
+    """
+
+    def __init__(self, psis, storage: str = "f32", check_norms: bool = True, stream=None):
+        descs = []
+        self.ns, self.ms = [], []
+        for psi in psis:
+            n, m, ld = _check_psi(psi)
+            descs.append((psi.data_ptr(), n, m, ld))
+            self.ns.append(n)
+            self.ms.append(m)
+        self.count = len(descs)
+        self.storage = storage
+        flags = 0 if check_norms else MP_SKIP_NORM_CHECK
+        self._ctx = mp_create_ragged(descs, DTYPES[storage], flags, _stream_ptr(stream))
+        self.y_off = [0]
+        self.x_off = [0]
+        for n, m in zip(self.ns, self.ms):
+            self.y_off.append(self.y_off[-1] + n)
+            self.x_off.append(self.x_off[-1] + m)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            mp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def set_config(self, threads: int, cols_per_wave: int, wgs_per_cu: int):
+        mp_ragged_set_config(self._ctx, threads, cols_per_wave, wgs_per_cu)
+
+    def get_config(self):
+        return mp_ragged_get_config(self._ctx)
+
+    def pack(self, ys):
+        """Concatenate per-instance y tensors into the packed layout."""
+        return torch.cat([y.reshape(-1) for y in ys]).contiguous()
+
+    def solve(self, y_packed: torch.Tensor, eps: float, max_iters, trace_cap: int = 0,
+              rescore_k: int = 0, want_r: bool = True, x_out=None, stream=None):
+        """Decode every instance.  ``y_packed``: float32 CUDA vector of sum(N_i).
+        ``max_iters``: one cap, or one per instance.  Returns dict with packed
+        ``x``/``r`` and per-instance ``iters``/``stop``/``yy``/``rr`` lists,
+        plus ``idx``/``coef``/``rr_trace`` (count, trace_cap) with a trace."""
+        if (not y_packed.is_cuda or y_packed.dtype != torch.float32
+                or y_packed.numel() != self.y_off[-1]):
+            raise ValueError("y_packed must be a float32 CUDA vector of sum(N_i) entries")
+        y_packed = y_packed.contiguous()
+        dev = y_packed.device
+        x = x_out if x_out is not None else torch.empty(self.x_off[-1], dtype=torch.float32,
+                                                         device=dev)
+        r = torch.empty(self.y_off[-1], dtype=torch.float32, device=dev) if want_r else None
+        tr = None
+        tidx = tcoef = trr = None
+        if trace_cap > 0:
+            tidx = torch.full((self.count, trace_cap), -1, dtype=torch.int32, device=dev)
+            tcoef = torch.zeros((self.count, trace_cap), dtype=torch.float32, device=dev)
+            trr = torch.zeros((self.count, trace_cap), dtype=torch.float64, device=dev)
+            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+        per = None
+        if hasattr(max_iters, "__len__"):
+            per = [int(v) for v in max_iters]
+            if len(per) != self.count:
+                raise ValueError("need one cap per instance")
+            cap_all = max(per)
+        else:
+            cap_all = int(max_iters)
+        opts = Opts(float(eps), cap_all, int(rescore_k), 0)
+        res = mp_solve_ragged(self._ctx, y_packed.data_ptr(), x.data_ptr(), _ptr(r), opts,
+                              self.count, per, tr, _stream_ptr(stream))
+        out = dict(x=x, r=r, iters=[res[i].iters for i in range(self.count)],
+                   yy=[res[i].yy for i in range(self.count)],
+                   rr=[res[i].rr for i in range(self.count)],
+                   stop=[STOP_NAMES.get(res[i].stop_reason, res[i].stop_reason)
+                         for i in range(self.count)])
+        if tr is not None:
+            out.update(idx=tidx, coef=tcoef, rr_trace=trr)
+        return out
+
+    def set_profiling(self, every: int = 1):
+        mp_set_profiling(self._ctx, int(every))
+
+    def kernel_time(self):
         return mp_kernel_time(self._ctx)

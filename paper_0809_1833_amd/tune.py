@@ -1,0 +1,96 @@
+"""Autotuner for the ragged decode's launch shape.
+
+The ragged decode (``mp_solve_ragged``) runs one persistent launch whose
+shape -- workgroup size, columns streamed per wave, workgroups per CU --
+changes speed but never results.  ``tune_ragged`` times every valid shape on
+the actual instances and keeps the fastest; the choice is cached in a JSON
+file keyed by the GPU architecture, the storage type and the multiset of
+instance sizes, so later runs with the same shape of work reuse it.
+
+Cache file: ``$MP_TUNE_CACHE`` if set, else ``~/.cache/mp_mi355x_tune.json``.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from collections import Counter
+from typing import Iterable, Optional
+
+import torch
+
+FP32_SHAPES = [(t, c, w) for t in (256, 512, 1024) for c in (1, 2, 4) for w in (1, 2)]
+BF16_SHAPES = [(t, 1, w) for t in (256, 512, 1024) for w in (1, 2)]
+
+
+def cache_path() -> str:
+    return os.environ.get("MP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "mp_mi355x_tune.json"))
+
+
+def workload_key(dec, arch: Optional[str] = None) -> str:
+    if arch is None:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    sizes = sorted(Counter(zip(dec.ns, dec.ms)).items())
+    digest = hashlib.sha256(json.dumps(sizes).encode()).hexdigest()[:16]
+    return f"{arch}|{dec.storage}|{dec.count}|{digest}"
+
+
+def _load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(cache: dict) -> None:
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only costs a re-tune next time
+
+
+def tune_ragged(dec, y_packed: torch.Tensor, eps: float, max_iters, reps: int = 2,
+                shapes: Optional[Iterable] = None, use_cache: bool = True, log=None) -> dict:
+    """Time each launch shape on this workload, apply and return the fastest.
+
+    Returns dict(config=..., ms=..., timings=[...], cached=bool)."""
+    key = workload_key(dec)
+    cache = _load_cache() if use_cache else {}
+    if use_cache and key in cache:
+        cfg = cache[key]["config"]
+        dec.set_config(cfg["threads"], cfg["cols_per_wave"], cfg["wgs_per_cu"])
+        return dict(cache[key], cached=True)
+    if shapes is None:
+        shapes = BF16_SHAPES if dec.storage == "bf16" else FP32_SHAPES
+    timings = []
+    x = torch.empty(dec.x_off[-1], dtype=torch.float32, device=y_packed.device)
+    for (t, c, w) in shapes:
+        dec.set_config(t, c, w)
+        dec.solve(y_packed, eps, max_iters, want_r=False, x_out=x)  # capture + warm-up
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            dec.solve(y_packed, eps, max_iters, want_r=False, x_out=x)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        timings.append(dict(threads=t, cols_per_wave=c, wgs_per_cu=w, ms=round(best * 1e3, 3)))
+        if log:
+            log(f"[tune] threads={t} cols/wave={c} wgs/cu={w}: {best * 1e3:.2f} ms")
+    win = min(timings, key=lambda d: d["ms"])
+    cfg = dict(threads=win["threads"], cols_per_wave=win["cols_per_wave"],
+               wgs_per_cu=win["wgs_per_cu"])
+    dec.set_config(**cfg)
+    entry = dict(config=cfg, ms=win["ms"], timings=timings)
+    if use_cache:
+        cache[key] = entry
+        _store_cache(cache)
+    return dict(entry, cached=False)
