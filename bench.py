@@ -26,8 +26,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MP iters/s & achieved HBM GB/s (1 signal); signals/s batched BF16 vs FP32"
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "mp_step_f32_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_0809_1833_amd", "csrc", "k_f32.hip")
+# counter-derived HBM traffic of each single-signal step kernel, and every
+# source file that kernel is compiled from (the record is used only while
+# those sources are unchanged)
+_CSRC = os.path.join(ROOT, "paper_0809_1833_amd", "csrc")
+TRAFFIC = {
+    "f32": (os.path.join(ROOT, "profiles", "mp_step_f32_traffic.json"),
+            [os.path.join(_CSRC, f) for f in ("k_f32.hip", "k_common.h", "mp_internal.h")]),
+    "bf16": (os.path.join(ROOT, "profiles", "mp_step_lp_bf16_traffic.json"),
+             [os.path.join(_CSRC, f) for f in ("k_lowp.hip", "k_lowp.h", "k_common.h",
+                                               "mp_internal.h")]),
+    "fp8": (os.path.join(ROOT, "profiles", "mp_step_lp_fp8_traffic.json"),
+            [os.path.join(_CSRC, f) for f in ("k_lowp.hip", "k_lowp.h", "k_common.h",
+                                              "mp_internal.h")]),
+}
 
 WORKLOADS = {
     "c1b": "N=8192, M=32768 (FP32 dictionary 1 GiB), K=512, eps=1e-5, T=10240, single signal",
@@ -42,20 +54,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_hash(storage="f32"):
+    h = hashlib.sha256()
+    for path in TRAFFIC[storage][1]:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def traffic_from_counters(n, m):
-    """HBM bytes per correlation launch from committed rocprofv3 counter runs,
-    or None when absent or taken on a different kernel source."""
+def traffic_from_counters(n, m, storage="f32"):
+    """HBM bytes per step launch from committed rocprofv3 counter runs, or
+    None when absent, for another size, or taken on a different kernel source."""
     try:
-        with open(PMC_FILE) as f:
+        with open(TRAFFIC[storage][0]) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha") != kernel_hash() or d.get("n") != n or d.get("m") != m:
+    if d.get("kernel_sha") != kernel_hash(storage) or d.get("n") != n or d.get("m") != m:
         return None
     return d.get("bytes_per_launch")
 
@@ -259,7 +274,7 @@ def main():
     bytes_per_iter = bytes_per_launch + 8.0 * n       # + residual read and written by the update
     avg_ms = kt_ms / max(kt_n, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kt_n else None
-    traffic = traffic_from_counters(n, m) if args.storage == "f32" else None
+    traffic = traffic_from_counters(n, m, args.storage)
     line = {
         "metric": METRIC,
         "value": round(iters / dt, 3),

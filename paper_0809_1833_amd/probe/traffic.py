@@ -4,13 +4,15 @@ Each counter is read in KiB per dispatch.  The scale factor of each counter
 comes from the probe's copy kernel, whose bytes read and written are known
 exactly: factor = known bytes / (counter KiB * 1024).  The result is written
 as JSON (by default ``profiles/<kernel>_traffic.json``) together with the
-SHA-256 prefix of the kernel's source file, so a benchmark can tell when the
+SHA-256 prefix of the kernel's source files, so a benchmark can tell when the
 kernel has changed since the counters were taken.
 
 Usage (after the four counter runs described in the profile summaries):
 
     python -m paper_0809_1833_amd.probe.traffic --kernel k_mp_step_f32 \\
-        --source paper_0809_1833_amd/csrc/k_f32.hip --n 8192 --m 32768 \\
+        --source paper_0809_1833_amd/csrc/k_f32.hip \\
+        --source paper_0809_1833_amd/csrc/k_common.h \\
+        --source paper_0809_1833_amd/csrc/mp_internal.h --n 8192 --m 32768 \\
         --fetch gpurun_out/pmc_FETCH_SIZE --write gpurun_out/pmc_WRITE_SIZE \\
         --copy-bytes 1073741824 --out profiles/mp_step_f32_traffic.json
 """
@@ -34,15 +36,20 @@ def _mean_counter(path: str, kernel_substr: str) -> tuple:
     return sum(vals) / len(vals), len(vals)
 
 
-def source_sha(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(paths) -> str:
+    """SHA-256 prefix over the kernel's source files, in the order given."""
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--kernel", required=True)
-    ap.add_argument("--source", required=True)
+    ap.add_argument("--source", required=True, action="append",
+                    help="a source file the kernel is built from (repeat for each)")
     ap.add_argument("--n", type=int, required=True)
     ap.add_argument("--m", type=int, required=True)
     ap.add_argument("--fetch", required=True, help="directory of the FETCH_SIZE runs")
