@@ -1,8 +1,8 @@
 // Wave64 / workgroup reductions used by the decoder's kernels (gfx950).
 //
-// All reductions combine values in a fixed pattern (xor butterflies inside a
-// wave, then the per-wave results in wave order), so a given launch shape
-// always produces bit-identical results.
+// All reductions combine values in a fixed pattern (DPP steps inside each
+// 16-lane row, the rows in lane order, then the per-wave results in wave
+// order), so a given launch shape always produces bit-identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,25 +16,92 @@ constexpr int kWave = 64;
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
+// ---- cross-lane reductions ---------------------------------------------------
+//
+// Inside each row of 16 lanes the reductions use DPP lane moves, which run on
+// the vector ALU instead of the LDS crossbar.
+//
+// Sums of floats (the inner products) keep every lane's result identical, as
+// the per-lane candidate lists that follow require: quad_perm [1,0,3,2] and
+// [2,3,0,1], row_mirror (lane i <-> 15-i) and row_half_mirror (i <-> 7-i)
+// are all symmetric exchanges, so after the four steps all 16 lanes of a row
+// hold the same row sum (addition is commutative), and two xor shuffles
+// across rows (16, then 32) finish it the same way.
+//
+// The 64-bit maximum and the FP64 sum return a wave-uniform value: after
+// quad_perm [1,0,3,2], [2,3,0,1], row_ror:4 and row_ror:8, lane 16k holds a
+// fixed combination of row k's values, and lanes 0, 16, 32 and 48 are then
+// read and combined in a fixed order.
+//
+// Every pattern depends only on the lane, so results are bit-reproducible.
+// Callers run these with every lane of the wave active.
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppRowRor4 = 0x124;       // row_ror:4
+constexpr int kDppRowRor8 = 0x128;       // row_ror:8
+constexpr int kDppRowMirror = 0x140;     // row_mirror
+constexpr int kDppRowHalfMirror = 0x141; // row_half_mirror
+
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(v), static_cast<int>(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ inline float dpp_f32(float v) {
+  return __builtin_bit_cast(float, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+}
+
+template <int CTRL>
+__device__ inline uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = dpp_u32<CTRL>(static_cast<uint32_t>(v));
+  const uint32_t hi = dpp_u32<CTRL>(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  return __builtin_bit_cast(double, dpp_u64<CTRL>(__builtin_bit_cast(uint64_t, v)));
+}
+
+__device__ inline uint64_t lane_u64(uint64_t v, int l) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+  const uint32_t hi =
+      static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v >> 32), l));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ inline double lane_f64(double v, int l) {
+  return __builtin_bit_cast(double, lane_u64(__builtin_bit_cast(uint64_t, v), l));
+}
+
+__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  v += dpp_f32<kDppQuadSwap1>(v);
+  v += dpp_f32<kDppQuadSwap2>(v);
+  v += dpp_f32<kDppRowMirror>(v);
+  v += dpp_f32<kDppRowHalfMirror>(v);
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
   return v;
 }
 
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_f64<kDppQuadSwap1>(v);
+  v += dpp_f64<kDppQuadSwap2>(v);
+  v += dpp_f64<kDppRowRor4>(v);
+  v += dpp_f64<kDppRowRor8>(v);
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 __device__ inline uint64_t wave_max(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    uint64_t o = __shfl_xor(static_cast<unsigned long long>(v), off, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
+  v = umax64(v, dpp_u64<kDppQuadSwap1>(v));
+  v = umax64(v, dpp_u64<kDppQuadSwap2>(v));
+  v = umax64(v, dpp_u64<kDppRowRor4>(v));
+  v = umax64(v, dpp_u64<kDppRowRor8>(v));
+  return umax64(umax64(lane_u64(v, 0), lane_u64(v, 16)), umax64(lane_u64(v, 32), lane_u64(v, 48)));
 }
 
 // Workgroup-wide sum of a double; every thread receives the result.
@@ -155,12 +222,16 @@ __device__ inline uint64_t take_slot(uint64_t* slot) {
 }
 
 // Selection and update, run by the last workgroup of a launch (NT threads).
-// `best` is the launch's winning key (largest |c|, smallest index).
+// `best` is the launch's winning key (largest |c|, smallest index); `r_lds`
+// holds this launch's r (ld floats, zero padded), which the update reads
+// instead of the global copy.  Column and r padding rows are zero, so the
+// update keeps the padding at +0 and the FP64 norm over ld equals the norm
+// over n.
 template <int NT>
 __device__ void select_update_tail(uint64_t best, const float* __restrict__ psi, int64_t ld,
                                    int64_t n, int64_t m, float* __restrict__ x,
-                                   float* __restrict__ r, DevState* __restrict__ st,
-                                   const mp_trace& tr, double* dred) {
+                                   float* __restrict__ r, const v4f* __restrict__ r_lds,
+                                   DevState* __restrict__ st, const mp_trace& tr, double* dred) {
   const int idx = key_index(best);
   const float c = key_value(best);
   if (idx < 0 || idx >= m) {  // cannot happen for a key a workgroup published
@@ -177,12 +248,44 @@ __device__ void select_update_tail(uint64_t best, const float* __restrict__ psi,
     }
     return;
   }
-  const float* col = psi + static_cast<int64_t>(idx) * ld;
+  // r <- r - c psi_idx: all of this thread's column loads are issued first
+  // (ld <= 16384 gives at most P float4s per thread), then the updates.
+  constexpr int P = 16384 / 4 / NT > 0 ? 16384 / 4 / NT : 1;
+  const v4f* col = reinterpret_cast<const v4f*>(psi + static_cast<int64_t>(idx) * ld);
+  v4f* r4 = reinterpret_cast<v4f*>(r);
+  const int ld4 = static_cast<int>(ld / 4);
+  v4f a[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < ld4) a[u] = col[i];
+  }
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) {
-    const float v = __builtin_fmaf(-c, col[i], r[i]);
-    r[i] = v;
-    s += static_cast<double>(v) * v;
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (i < ld4) {
+      const v4f rv = r_lds[i];
+      v4f o;
+      o.x = __builtin_fmaf(-c, a[u].x, rv.x);
+      o.y = __builtin_fmaf(-c, a[u].y, rv.y);
+      o.z = __builtin_fmaf(-c, a[u].z, rv.z);
+      o.w = __builtin_fmaf(-c, a[u].w, rv.w);
+      r4[i] = o;
+      s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
+           (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
+    }
+  }
+  for (int i = threadIdx.x + P * NT; i < ld4; i += NT) {  // only if ld exceeds the bound
+    const v4f av = col[i], rv = r_lds[i];
+    v4f o;
+    o.x = __builtin_fmaf(-c, av.x, rv.x);
+    o.y = __builtin_fmaf(-c, av.y, rv.y);
+    o.z = __builtin_fmaf(-c, av.z, rv.z);
+    o.w = __builtin_fmaf(-c, av.w, rv.w);
+    r4[i] = o;
+    s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
+         (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
   }
   const double rr = block_sum<NT>(s, dred);
   if (threadIdx.x == 0) {

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
     winner = k > winner ? k : winner;
   }
   winner = block_max<kCorrThreads>(winner, kred);
-  select_update_tail<kCorrThreads>(winner, psi, ld, n, m, x, r, st, tr, dred);
+  select_update_tail<kCorrThreads>(winner, psi, ld, n, m, x, r, r_lds, st, tr, dred);
 }
 
 CorrGeom corr_f32_geometry(int64_t m, int num_cus) {

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   __syncthreads();
   uint64_t best = 0;
   for (int j = 0; j < rescore_k; ++j) best = rescored[j] > best ? rescored[j] : best;
-  select_update_tail<kLpThreads>(best, psi32, ld, n, m, x, r, st, tr, dred);
+  select_update_tail<kLpThreads>(best, psi32, ld, n, m, x, r, r_lds, st, tr, dred);
 }
 
 hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
