@@ -41,6 +41,8 @@ constexpr int kDppRowRor4 = 0x124;       // row_ror:4
 constexpr int kDppRowRor8 = 0x128;       // row_ror:8
 constexpr int kDppRowMirror = 0x140;     // row_mirror
 constexpr int kDppRowHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppRowShl4 = 0x104;       // row_shl:4 (lane i reads lane i+4 of its row)
+constexpr int kDppRowShr4 = 0x114;       // row_shr:4 (lane i reads lane i-4 of its row)
 
 template <int CTRL>
 __device__ inline uint32_t dpp_u32(uint32_t v) {
@@ -134,6 +136,15 @@ __device__ inline uint64_t block_max(uint64_t v, uint64_t* red) {
 }
 
 // ---- FP32 inner product of one column with the LDS copy of r ----------------
+//
+// The inner product is defined as two per-lane chains over the two halves of
+// the column's float4s (ld4 is even: ld is a multiple of 64): lane l sums
+// float4s l, l+64, ... below h0 = ld4/2 into one FP32 accumulator and
+// h0+l, h0+l+64, ... into another, each in increasing order with FMAs; the
+// two are added per lane and the wave sums the lanes.  A single wave runs both
+// chains in lockstep; the re-scoring in the reduced-precision kernel gives
+// each chain to its own wave and combines them per lane through LDS, with the
+// same result bit for bit.
 
 // U loads of 16 bytes in flight per lane, then U x 4 FMAs against the LDS
 // copy of r; advances i by 64 * U float4s.
@@ -154,19 +165,61 @@ __device__ inline void dot_block(const v4f* __restrict__ p, const v4f* __restric
   i += kWave * U;
 }
 
-// <r, psi_col> for one column by one wave: blocks of 16 loads per lane while
-// they fit, then at most one block each of 8, 4, 2 and 1 (so short columns
-// still have several loads in flight), then a butterfly sum.
+// Both chains at once: U loads from each half (2U in flight per lane).
+template <int U>
+__device__ inline void dot_block2(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
+                                  int h0, int& i, float& acc_a, float& acc_b) {
+  v4f a[U], b[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+    b[u] = __builtin_nontemporal_load(p + h0 + i + kWave * u);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const v4f ra = r_lds[i + kWave * u];
+    acc_a = __builtin_fmaf(a[u].x, ra.x, acc_a);
+    acc_a = __builtin_fmaf(a[u].y, ra.y, acc_a);
+    acc_a = __builtin_fmaf(a[u].z, ra.z, acc_a);
+    acc_a = __builtin_fmaf(a[u].w, ra.w, acc_a);
+    const v4f rb = r_lds[h0 + i + kWave * u];
+    acc_b = __builtin_fmaf(b[u].x, rb.x, acc_b);
+    acc_b = __builtin_fmaf(b[u].y, rb.y, acc_b);
+    acc_b = __builtin_fmaf(b[u].z, rb.z, acc_b);
+    acc_b = __builtin_fmaf(b[u].w, rb.w, acc_b);
+  }
+  i += kWave * U;
+}
+
+// <r, psi_col> for one column by one wave: both chains in blocks of 8 loads
+// each while they fit, then at most one block each of 4, 2 and 1 (so short
+// columns still have several loads in flight), then the lane sum.
 __device__ inline float dot_column_f32(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
                                        int ld4, int lane) {
+  const int h0 = ld4 / 2;
+  float acc_a = 0.0f, acc_b = 0.0f;
+  int i = lane;
+  while (i + kWave * 7 < h0) dot_block2<8>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i + kWave * 3 < h0) dot_block2<4>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i + kWave * 1 < h0) dot_block2<2>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i < h0) dot_block2<1>(p, r_lds, h0, i, acc_a, acc_b);
+  return wave_sum(acc_a + acc_b);
+}
+
+// One chain of the inner product (float4s base+l, base+l+64, ... below
+// base+len) as this lane's partial sum, without the lane sum.
+__device__ inline float dot_chain_f32(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
+                                      int base, int len, int lane) {
+  p += base;
+  r_lds += base;
   float acc = 0.0f;
   int i = lane;
-  while (i + kWave * 15 < ld4) dot_block<16>(p, r_lds, i, acc);
-  if (i + kWave * 7 < ld4) dot_block<8>(p, r_lds, i, acc);
-  if (i + kWave * 3 < ld4) dot_block<4>(p, r_lds, i, acc);
-  if (i + kWave * 1 < ld4) dot_block<2>(p, r_lds, i, acc);
-  if (i < ld4) dot_block<1>(p, r_lds, i, acc);
-  return wave_sum(acc);
+  while (i + kWave * 15 < len) dot_block<16>(p, r_lds, i, acc);
+  if (i + kWave * 7 < len) dot_block<8>(p, r_lds, i, acc);
+  if (i + kWave * 3 < len) dot_block<4>(p, r_lds, i, acc);
+  if (i + kWave * 1 < len) dot_block<2>(p, r_lds, i, acc);
+  if (i < len) dot_block<1>(p, r_lds, i, acc);
+  return acc;
 }
 
 // ---- hand-off from all workgroups of a launch to the last one ---------------

@@ -92,20 +92,51 @@ __device__ inline void top8_insert(uint64_t (&L)[kTopK], uint64_t key) {
   }
 }
 
-// The 8 largest of the 128 keys a wave holds (two per lane); lane j < 8
-// receives the j-th largest.  Keys are distinct apart from 0.
-__device__ inline uint64_t wave_top8(uint64_t a, uint64_t b, int lane) {
-  uint64_t out = 0;
-#pragma unroll
-  for (int j = 0; j < kTopK; ++j) {
-    const uint64_t w = wave_max(a > b ? a : b);
-    if (lane == j) out = w;
-    if (w != 0) {
-      if (a == w) a = 0;
-      else if (b == w) b = 0;
-    }
-  }
-  return out;
+// ---- bitonic merge of sorted 8-key lists across the lanes of a wave ----------
+
+// Lane i receives lane (i ^ 4)'s key (groups of 8 lanes inside a row of 16).
+__device__ inline uint64_t xor4_u64(uint64_t v, int lane) {
+  const uint64_t up = dpp_u64<kDppRowShl4>(v);
+  const uint64_t dn = dpp_u64<kDppRowShr4>(v);
+  return (lane & 4) ? dn : up;
+}
+
+// Compare-exchange for descending order: the lower lane of a pair keeps the
+// larger key.
+__device__ inline uint64_t cx_desc(uint64_t v, uint64_t partner, bool upper) {
+  return upper ? (v < partner ? v : partner) : (v > partner ? v : partner);
+}
+
+// Sorts, descending, the bitonic sequence of 8 keys each group of 8 lanes
+// holds (compare-exchange at distances 4, 2, 1).
+__device__ inline uint64_t bitonic_sort8(uint64_t v, int lane) {
+  v = cx_desc(v, xor4_u64(v, lane), (lane & 4) != 0);
+  v = cx_desc(v, dpp_u64<kDppQuadSwap2>(v), (lane & 2) != 0);
+  v = cx_desc(v, dpp_u64<kDppQuadSwap1>(v), (lane & 1) != 0);
+  return v;
+}
+
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+  return __shfl(static_cast<unsigned long long>(v), src, kWave);
+}
+
+// The 8 largest keys of 16 lists of 8, each sorted in descending order: list
+// g < 8 sits in lanes 8g..8g+7 of `a` (its rank-j key in lane 8g+j), list
+// 8+g likewise in `b`.  The element-wise maximum of one sorted list and the
+// reverse of another is a bitonic sequence holding the 8 largest keys of
+// both, so four such merges (partner list reversed by row_half_mirror, then
+// row_mirror, then lane ^ 23 and lane ^ 39) each followed by bitonic_sort8
+// leave the 8 largest of all 128 keys, sorted, in every group of 8 lanes;
+// lane j < 8 returns the j-th largest.  0 (an empty entry) sorts last.
+__device__ inline uint64_t top8_of_lists16(uint64_t a, uint64_t b, int lane) {
+  uint64_t v = umax64(a, dpp_u64<kDppRowHalfMirror>(b));
+  v = bitonic_sort8(v, lane);
+  v = umax64(v, dpp_u64<kDppRowMirror>(v));
+  v = bitonic_sort8(v, lane);
+  v = umax64(v, shfl_u64(v, lane ^ 23));
+  v = bitonic_sort8(v, lane);
+  v = umax64(v, shfl_u64(v, lane ^ 39));
+  return bitonic_sort8(v, lane);
 }
 
 // The 8 largest keys over the lanes' sorted lists; lane j < 8 receives the

@@ -6,7 +6,8 @@
 // precision can reorder near-equal correlations, each pass keeps the 8 best
 // candidates rather than 1; the last workgroup re-scores up to 8 of them
 // against the FP32 columns (the same FP32 inner product the FP32 form
-// computes) and takes the best of those, smallest index on ties (eq. 16).
+// computes, each column's two chains on two waves) and takes the best of
+// those, smallest index on ties (eq. 16).
 // The coefficient and residual updates (eqs. 10-11) and the FP64 stopping
 // test then use the FP32 column and the re-scored FP32 coefficient.
 //
@@ -118,6 +119,7 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   __shared__ uint64_t lists[kLpWaves * kTopK];
   __shared__ uint64_t cand[kTopK];
   __shared__ uint64_t rescored[kTopK];
+  __shared__ float chain_b[kTopK][kWave];
   __shared__ uint64_t kred[kLpWaves];
   __shared__ double dred[kLpWaves];
   const int ld4 = static_cast<int>(ld / 4);
@@ -147,37 +149,49 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   }
   __syncthreads();
   uint64_t mine = 0;
-  if (wave == 0) mine = wave_top8(lists[lane], lists[lane + kWave], lane);
+  if (wave == 0) mine = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
   if (!publish_arrive<kTopK>(mine, keys, st)) return;
 
-  // ---- last workgroup: the launch's top 8 ----
+  // ---- last workgroup: the launch's top 8.  Slot 8g + j holds workgroup
+  // g's rank-j key, so every group of 8 lanes below holds one sorted list ----
   const int nslots = static_cast<int>(gridDim.x) * kTopK;  // <= 2 * kLpThreads (host-checked)
   const uint64_t a = threadIdx.x < nslots ? take_slot(keys + threadIdx.x) : 0;
   const uint64_t b =
       threadIdx.x + kLpThreads < nslots ? take_slot(keys + threadIdx.x + kLpThreads) : 0;
-  const uint64_t wtop = wave_top8(a, b, lane);
+  const uint64_t wtop = top8_of_lists16(a, b, lane);
   __syncthreads();  // everyone is done with `lists`
   if (lane < kTopK) lists[wave * kTopK + lane] = wtop;
   __syncthreads();
   if (wave == 0) {
-    const uint64_t t = wave_top8(lists[lane], lists[lane + kWave], lane);
+    const uint64_t t = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
     if (lane < kTopK) cand[lane] = t;
   }
   __syncthreads();
-  // ---- re-score candidates against the FP32 columns, one wave each ----
-  if (wave < rescore_k) {
-    const uint64_t k = cand[wave];
-    uint64_t rk = 0;
-    if (k != 0) {
-      const int idx = key_index(k);
-      if (idx >= 0 && idx < m) {
-        const float c32 = dot_column_f32(
-            reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld), r_lds, ld4,
-            lane);
-        rk = make_key(c32, idx);
-      }
+  // ---- re-score candidates against the FP32 columns: waves 2q and 2q+1 run
+  // the two chains of candidate q's inner product, which meet per lane in
+  // LDS (the same arithmetic as the FP32 form's inner product) ----
+  static_assert(kLpWaves >= 2 * kTopK, "two waves per candidate");
+  {
+    const int q = wave / 2;
+    const bool second = (wave % 2) != 0;
+    const int h0 = ld4 / 2;
+    int idx = -1;
+    if (q < rescore_k && cand[q] != 0) {
+      idx = key_index(cand[q]);
+      if (idx >= m) idx = -1;
     }
-    if (lane == 0) rescored[wave] = rk;
+    float acc = 0.0f;
+    if (idx >= 0) {
+      acc = dot_chain_f32(reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld),
+                          r_lds, second ? h0 : 0, h0, lane);
+      if (second) chain_b[q][lane] = acc;
+    }
+    __syncthreads();
+    if (!second && q < rescore_k) {
+      uint64_t rk = 0;
+      if (idx >= 0) rk = make_key(wave_sum(acc + chain_b[q][lane]), idx);
+      if (lane == 0) rescored[q] = rk;
+    }
   }
   __syncthreads();
   uint64_t best = 0;

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
             for (int k = W * kTopK + lane; k < 16 * kTopK; k += kWave) lists[k] = 0;
           __syncthreads();
           if (wave == 0) {
-            const uint64_t c8 = wave_top8(lists[lane], lists[lane + kWave], lane);
+            const uint64_t c8 = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
             if (lane < kTopK) cand[lane] = c8;
           }
           __syncthreads();
