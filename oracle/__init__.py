@@ -5,8 +5,10 @@ the CPU-baseline leg of ``bench.py`` may import anything from this package.
 The GPU library never calls it and shares no code with it.
 
 Contents
-* :func:`solve` / :func:`correlate` -- the plain FP64 MP of Section 3
-  (eqs. 8-12, argmax tie rule of eq. 16), in C (``mp_oracle.c``).
+* :func:`solve` / :func:`solve64` / :func:`correlate` -- the plain FP64 MP of
+  Section 3 (eqs. 8-12, argmax tie rule of eq. 16), in C (``mp_oracle.c``);
+  ``solve`` takes y as FP32 (the FP32 decoder's input), ``solve64`` an FP64
+  dictionary and an FP64 y (the FP64 decoder's inputs).
 * :mod:`oracle.exact` -- exact rational MP and brute-force pins.
 * :mod:`oracle.quant` -- reference BF16 / FP8-e4m3fn quantisers.
 """
@@ -33,10 +35,11 @@ def load_library(path: str):
     """Open a compiled oracle (the default one, or a test-built variant)."""
     lib = ctypes.CDLL(path)
     p, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
-    for suf in ("f32", "f64"):
-        f = getattr(lib, "mpo_solve_" + suf)
+    for name in ("f32", "f64", "f64_y64"):
+        f = getattr(lib, "mpo_solve_" + name)
         f.restype = ctypes.c_int
         f.argtypes = [p, i64, i64, i64, p, dbl, i64, p, p, p, p, p, p, p, p, p, p, i64]
+    for suf in ("f32", "f64"):
         g = getattr(lib, "mpo_correlate_" + suf)
         g.restype = None
         g.argtypes = [p, i64, i64, i64, p, p]
@@ -102,12 +105,31 @@ class Result:
 
 def solve(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
           trace: bool = True, lib=None) -> Result:
-    """FP64 Matching Pursuit on the given dictionary (FP32 or FP64 storage)."""
+    """FP64 Matching Pursuit on the given dictionary (FP32 or FP64 storage) and
+    an FP32 y (y is rounded to FP32 first, as the FP32 decoder receives it)."""
     lib = _load() if lib is None else lib
     base, suf, n, m, ld = _psi_view(psi)
     y32 = np.ascontiguousarray(y, dtype=np.float32)
     if y32.shape != (n,):
         raise ValueError("y must have shape (N,)")
+    return _run(lib, "mpo_solve_" + suf, base, n, m, ld, y32, eps, max_iters, trace)
+
+
+def solve64(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
+            trace: bool = True, lib=None) -> Result:
+    """The same FP64 Matching Pursuit on an FP64 dictionary and an FP64 y (the
+    inputs of the FP64 decoder), with no rounding of either."""
+    lib = _load() if lib is None else lib
+    if psi.dtype != np.float64:
+        raise TypeError("solve64 needs a float64 dictionary")
+    base, _, n, m, ld = _psi_view(psi)
+    y64 = np.ascontiguousarray(y, dtype=np.float64)
+    if y64.shape != (n,):
+        raise ValueError("y must have shape (N,)")
+    return _run(lib, "mpo_solve_f64_y64", base, n, m, ld, y64, eps, max_iters, trace)
+
+
+def _run(lib, fname, base, n, m, ld, yv, eps, max_iters, trace):
     x = np.zeros(m, dtype=np.float64)
     r = np.zeros(n, dtype=np.float64)
     iters = np.zeros(1, dtype=np.int64)
@@ -119,8 +141,8 @@ def solve(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
     tc = np.zeros(max(cap, 1), dtype=np.float64)
     tr = np.zeros(max(cap, 1), dtype=np.float64)
     tg = np.zeros(max(cap, 1), dtype=np.float64)
-    rc = getattr(lib, "mpo_solve_" + suf)(
-        _ptr(base), n, m, ld, _ptr(y32), float(eps), int(max_iters),
+    rc = getattr(lib, fname)(
+        _ptr(base), n, m, ld, _ptr(yv), float(eps), int(max_iters),
         _ptr(x), _ptr(r), _ptr(iters), _ptr(reason), _ptr(yy), _ptr(rr),
         _ptr(ti), _ptr(tc), _ptr(tr), _ptr(tg), cap)
     if rc != 0:

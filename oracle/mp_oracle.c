@@ -96,7 +96,7 @@ static int64_t argmax_abs(const double* c, int64_t m, double* best, double* seco
  *   selected index, the coefficient <r, psi_i>, sum r^2 after the update,
  *   and the gap between the largest and second-largest |<r, psi_m>|.
  */
-#define MPO_DEFINE(SUFFIX, T)                                                            \
+#define MPO_DEFINE_CORRELATE(SUFFIX, T)                                                   \
     void mpo_correlate_##SUFFIX(const T* psi, int64_t n, int64_t m, int64_t ld,          \
                                 const double* r, double* c) {                            \
         _Pragma("omp parallel for schedule(static)")                                      \
@@ -106,14 +106,17 @@ static int64_t argmax_abs(const double* c, int64_t m, double* best, double* seco
             for (int64_t i = 0; i < n; ++i) s += (double)col[i] * r[i];                   \
             c[j] = s;                                                                     \
         }                                                                                 \
-    }                                                                                     \
-                                                                                          \
-    int mpo_solve_##SUFFIX(const T* psi, int64_t n, int64_t m, int64_t ld,               \
-                           const float* y, double eps, int64_t max_iters,                 \
-                           double* x_out, double* r_out, int64_t* iters_out,              \
-                           int32_t* reason_out, double* yy_out, double* rr_out,           \
-                           int32_t* tr_idx, double* tr_coef, double* tr_rr,               \
-                           double* tr_gap, int64_t tr_cap) {                              \
+    }
+
+/* The solver for dictionary element type T and y element type YT, whose
+   correlation pass is mpo_correlate_SUFFIX; y is promoted exactly to FP64. */
+#define MPO_DEFINE_SOLVE(NAME, SUFFIX, T, YT)                                             \
+    int NAME(const T* psi, int64_t n, int64_t m, int64_t ld,                              \
+             const YT* y, double eps, int64_t max_iters,                                  \
+             double* x_out, double* r_out, int64_t* iters_out,                            \
+             int32_t* reason_out, double* yy_out, double* rr_out,                         \
+             int32_t* tr_idx, double* tr_coef, double* tr_rr,                             \
+             double* tr_gap, int64_t tr_cap) {                                            \
         if (!psi || !y || !x_out || !r_out || n < 1 || m < 1 || ld < n || max_iters < 0 \
             || !(eps >= 0.0))                                                             \
             return MPO_BAD_ARGS;                                                          \
@@ -158,5 +161,9 @@ static int64_t argmax_abs(const double* c, int64_t m, double* best, double* seco
         return MPO_OK;                                                                    \
     }
 
-MPO_DEFINE(f32, float)
-MPO_DEFINE(f64, double)
+MPO_DEFINE_CORRELATE(f32, float)
+MPO_DEFINE_CORRELATE(f64, double)
+MPO_DEFINE_SOLVE(mpo_solve_f32, f32, float, float)
+MPO_DEFINE_SOLVE(mpo_solve_f64, f64, double, float)
+/* FP64 dictionary and FP64 y (the inputs of an FP64 decode) */
+MPO_DEFINE_SOLVE(mpo_solve_f64_y64, f64, double, double)

@@ -101,6 +101,13 @@ def _run_battery(lib):
     res = oracle.solve(psi, y, 0.25, 20, lib=lib)
     if res.iters != 5:
         failed.append("eps_stop_count")
+    # 5. the FP64-y entry: exact dyadic recovery with more than 24 bits
+    x64 = np.zeros(16)
+    x64[[1, 4, 9]] = [0.5 + 2.0 ** -30, -(0.25 + 2.0 ** -40), 0.125 + 2.0 ** -35]
+    psi64h = psi.astype(np.float64)
+    res = oracle.solve64(psi64h, psi64h @ x64, 0.0, 10, lib=lib)
+    if res.idx.tolist() != [1, 4, 9] or not np.array_equal(res.x, x64) or res.rr != 0.0:
+        failed.append("fp64_dyadic")
     return failed
 
 

@@ -187,6 +187,53 @@ def test_orthonormal_hadamard_exact():
     assert res.idx.tolist() == order.tolist()
 
 
+# --- the FP64-y entry point (inputs of the FP64 decode) ----------------------
+
+def test_solve64_equals_solve_when_y_is_fp32():
+    """With y exactly representable in FP32 both entry points run the same
+    FP64 arithmetic (the FP64 entry only skips the rounding of y)."""
+    psi = _unit_gaussian_f64(5, 48, 96)
+    _, _, y = _sparse_y(psi, 6, 5)
+    a = oracle.solve(psi, y, 1e-9, 60)
+    b = oracle.solve64(psi, y.astype(np.float64), 1e-9, 60)
+    assert a.iters == b.iters and a.reason == b.reason
+    assert np.array_equal(a.idx, b.idx) and np.array_equal(a.coef, b.coef)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.r, b.r)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_solve64_orthonormal_keeps_fp64_y(seed):
+    """N = M orthonormal FP64 dictionary and FP64 nonzeros: MP is the sort of
+    |x| and recovers x to FP64 rounding in exactly K steps (textbook
+    reduction).  Rounding y to FP32 would leave errors of order 1e-8."""
+    n, k = 64, 8
+    rng = np.random.default_rng(300 + seed)
+    q = mpgen.qr_orthonormal_dictionary(rng, n)
+    sup = np.sort(rng.choice(n, size=k, replace=False))
+    x = np.zeros(n)
+    x[sup] = rng.standard_normal(k)
+    y = q @ x
+    res = oracle.solve64(q, y, 1e-12, 100)
+    c0 = q.T @ y
+    order = sup[np.argsort(-np.abs(c0[sup]), kind="stable")]
+    assert res.iters == k and res.reason == oracle.CONVERGED
+    assert res.idx.tolist() == order.tolist()
+    assert np.linalg.norm(res.x - x) <= 1e-14 * np.linalg.norm(x)
+
+
+def test_solve64_dyadic_exact():
+    """Hadamard columns (entries +-1/4) and dyadic nonzeros that need more
+    than FP32's 24 significant bits: every step is exact in FP64, so x~ = x
+    and r = 0 exactly after K steps, largest |x| first."""
+    psi = mpgen.hadamard_dictionary(16).astype(np.float64)
+    x = np.zeros(16)
+    x[[1, 4, 9]] = [0.5 + 2.0 ** -30, -(0.25 + 2.0 ** -40), 0.125 + 2.0 ** -35]
+    y = psi @ x
+    res = oracle.solve64(psi, y, 0.0, 10)
+    assert res.idx.tolist() == [1, 4, 9] and res.reason == oracle.CONVERGED
+    assert np.array_equal(res.x, x) and res.rr == 0.0 and not np.any(res.r)
+
+
 # --- invariants --------------------------------------------------------------
 
 @pytest.mark.parametrize("seed", [0, 1])
