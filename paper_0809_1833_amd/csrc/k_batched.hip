@@ -21,6 +21,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8bf;
 
 constexpr int kBThreads = 256;              // 4 waves (init and compaction)
 constexpr int kBSelThreads = 512;           // 8 waves: one per re-scored candidate
+constexpr int kBSelWaves = kBSelThreads / kWave;
 constexpr int kBTopK = kTopK;
 
 // ---------------------------------------------------------------------------
@@ -129,17 +130,24 @@ __global__ __launch_bounds__(kBThreads) void k_bcompact_init(int nslots, const B
 // Operands come straight from global memory (the BF16 dictionary stays in
 // the last-level cache across rounds, the residuals in L2): lane l loads 16
 // contiguous bytes of atom row (l % 16) and of signal column (l % 16) at K
-// offset 8 * (l / 16).  The fragments of the wave's next kBPre K-steps stay
-// in flight in a register ring while the current step's MFMAs run.  The four
-// partial tiles are summed in LDS in a fixed order, ((w0 + w2) + (w1 + w3)),
-// and all 256 threads then find each signal's 8 best keys of the tile.
+// offset 8 * (l / 16).  Rows past the last atom and columns past the last
+// active signal load the last valid row or column instead: an operand row
+// only reaches its own row (column) of the product, which the epilogue
+// skips, so no load needs a predicate and the loads of the next kBPre
+// K-steps stay in flight in a register ring while the current step's MFMAs
+// run (scheduling barriers keep each step's loads behind its MFMAs, so the
+// oldest slot is the only one waited for; two waves per SIMD fit).  The four partial tiles are summed in LDS in a fixed order,
+// ((w0 + w2) + (w1 + w3)); then thread (wave, lane) sorts the keys of rows
+// [wave * TM/4, (wave + 1) * TM/4) of signal column `lane` with sorting
+// networks, and the four sorted lists are merged pairwise into the signal's
+// 8 best atoms of the tile (descending), written to `partials`.
 constexpr int kBCorrThreads = 256;
 constexpr int kBCorrWaves = kBCorrThreads / kWave;   // K split
 constexpr int kBCorrTileB = 64;                      // signals per workgroup
 constexpr int kBPre = 4;                             // K-steps in flight per wave
 
 template <int TI>
-__global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restrict__ psib,
+__global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr(const uint16_t* __restrict__ psib,
                                                          int64_t ld, int64_t m,
                                                          const uint16_t* __restrict__ Rq,
                                                          const int* __restrict__ act0,
@@ -152,26 +160,25 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
   const int nact = bs->n_active[cur];
   const int j0 = blockIdx.y * kBCorrTileB;
   if (j0 >= nact) return;  // workgroup-uniform
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int* act = cur ? act1 : act0;
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * TM;
   const int koff = 8 * (lane / 16);
 
   const uint16_t* arow[TI];
-  bool aval[TI];
 #pragma unroll
   for (int ti = 0; ti < TI; ++ti) {
-    const int64_t row = m0 + 16 * ti + (lane % 16);
-    aval[ti] = row < m;
-    arow[ti] = psib + (aval[ti] ? row : 0) * ld + koff;
+    int64_t row = m0 + 16 * ti + (lane % 16);
+    if (row > m - 1) row = m - 1;
+    arow[ti] = psib + row * ld + koff;
   }
   const uint16_t* bcol[4];
-  bool bval[4];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj) {
-    const int j = j0 + 16 * tj + (lane % 16);
-    bval[tj] = j < nact;
-    bcol[tj] = Rq + static_cast<int64_t>(bval[tj] ? act[j] : 0) * ld + koff;
+    int j = j0 + 16 * tj + (lane % 16);
+    if (j > nact - 1) j = nact - 1;
+    bcol[tj] = Rq + static_cast<int64_t>(act[j]) * ld + koff;
   }
   v4f acc[TI][4];
 #pragma unroll
@@ -179,7 +186,6 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  const v8bf zero = {};
   const int nsteps = static_cast<int>(ld / 32);
   // this wave's K-steps: wave, wave + 4, ...; `q` counts them
   const int nmine = nsteps > wave ? (nsteps - wave + kBCorrWaves - 1) / kBCorrWaves : 0;
@@ -187,25 +193,39 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
   auto load_step = [&](int slot, int q) {
     const int64_t k = static_cast<int64_t>(wave + q * kBCorrWaves) * 32;
 #pragma unroll
-    for (int ti = 0; ti < TI; ++ti)
-      ra[slot][ti] = aval[ti] ? *reinterpret_cast<const v8bf*>(arow[ti] + k) : zero;
+    for (int ti = 0; ti < TI; ++ti) ra[slot][ti] = *reinterpret_cast<const v8bf*>(arow[ti] + k);
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj)
-      rb[slot][tj] = bval[tj] ? *reinterpret_cast<const v8bf*>(bcol[tj] + k) : zero;
+    for (int tj = 0; tj < 4; ++tj) rb[slot][tj] = *reinterpret_cast<const v8bf*>(bcol[tj] + k);
   };
+  auto mma_step = [&](int slot) {
 #pragma unroll
-  for (int p = 0; p < kBPre; ++p)
-    if (p < nmine) load_step(p, p);
-  for (int q0 = 0; q0 < nmine; q0 += kBPre) {
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+        acc[ti][tj] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[slot][ti], rb[slot][tj], acc[ti][tj], 0, 0, 0);
+  };
+  // the first kBPre steps (a step past the wave's last loads step 0 again,
+  // which is valid memory and never used)
+#pragma unroll
+  for (int p = 0; p < kBPre; ++p) load_step(p, p < nmine ? p : 0);
+  __builtin_amdgcn_sched_barrier(0);
+  int q0 = 0;
+  // steady state: every slot consumed is reloaded kBPre steps ahead
+  for (; q0 + 2 * kBPre <= nmine; q0 += kBPre) {
+#pragma unroll
+    for (int p = 0; p < kBPre; ++p) {
+      mma_step(p);
+      load_step(p, q0 + p + kBPre);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // the last (fewer than 2 kBPre) steps
+  for (; q0 < nmine; q0 += kBPre) {
 #pragma unroll
     for (int p = 0; p < kBPre; ++p) {
       if (q0 + p < nmine) {
-#pragma unroll
-        for (int ti = 0; ti < TI; ++ti)
-#pragma unroll
-          for (int tj = 0; tj < 4; ++tj)
-            acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[p][ti], rb[p][tj],
-                                                                   acc[ti][tj], 0, 0, 0);
+        mma_step(p);
         if (q0 + p + kBPre < nmine) load_step(p, q0 + p + kBPre);
       }
     }
@@ -213,7 +233,7 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
 
   // sum the four partial tiles: ((w0 + w2) + (w1 + w3)) into ctile[1]
   __shared__ float ctile[2][TM][kBCorrTileB + 1];
-  __shared__ uint64_t lists[4][kBCorrTileB][kBTopK];
+  __shared__ uint64_t lists[2][kBTopK][kBCorrTileB];
   auto store = [&](int slot) {
 #pragma unroll
     for (int ti = 0; ti < TI; ++ti)
@@ -243,29 +263,54 @@ __global__ __launch_bounds__(kBCorrThreads) void k_bcorr(const uint16_t* __restr
     store(1);
   }
   __syncthreads();
-  // each signal's 8 best atoms: thread (part = wave, col = lane) scans TM/4
-  // rows, the four lists are merged by part 0
+
+  // each signal's 8 best atoms of the tile
+  constexpr int RP = TM / 4;  // rows per thread: 16 or 8
+  static_assert(RP == 16 || RP == 8, "tile height");
+  uint64_t L[kBTopK];
   {
-    uint64_t L[kBTopK];
+    uint64_t v[RP];
 #pragma unroll
-    for (int q = 0; q < kBTopK; ++q) L[q] = 0;
-    constexpr int RP = TM / 4;
-    for (int rr = wave * RP; rr < wave * RP + RP; ++rr) {
+    for (int i = 0; i < RP; ++i) {
+      const int rr = wave * RP + i;
       const int64_t atom = m0 + rr;
-      if (atom < m) top8_insert(L, make_key(ctile[1][rr][lane], static_cast<int>(atom)));
+      v[i] = atom < m ? make_key(ctile[1][rr][lane], static_cast<int>(atom)) : 0ull;
     }
 #pragma unroll
-    for (int q = 0; q < kBTopK; ++q) lists[wave][lane][q] = L[q];
-    __syncthreads();
-    if (wave == 0 && j0 + lane < nact) {
-      for (int p = 1; p < 4; ++p)
+    for (int q = 0; q < kBTopK; ++q) L[q] = v[q];
+    sort8_keys(L);
+    if constexpr (RP == 16) {
+      uint64_t h[kBTopK];
 #pragma unroll
-        for (int q = 0; q < kBTopK; ++q) top8_insert(L, lists[p][lane][q]);
-      uint64_t* out =
-          partials + (static_cast<int64_t>(j0 + lane) * mtiles + blockIdx.x) * kBTopK;
-#pragma unroll
-      for (int q = 0; q < kBTopK; ++q) out[q] = L[q];
+      for (int q = 0; q < kBTopK; ++q) h[q] = v[kBTopK + q];
+      sort8_keys(h);
+      merge8_keys(L, h);
     }
+  }
+  // waves 2, 3 hand their lists to waves 0, 1; then wave 1 to wave 0
+  if (wave >= 2)
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) lists[wave - 2][q][lane] = L[q];
+  __syncthreads();
+  if (wave < 2) {
+    uint64_t o[kBTopK];
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) o[q] = lists[wave][q][lane];
+    merge8_keys(L, o);
+  }
+  __syncthreads();
+  if (wave == 1)
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) lists[1][q][lane] = L[q];
+  __syncthreads();
+  if (wave == 0 && j0 + lane < nact) {
+    uint64_t o[kBTopK];
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) o[q] = lists[1][q][lane];
+    merge8_keys(L, o);
+    uint64_t* out = partials + (static_cast<int64_t>(j0 + lane) * mtiles + blockIdx.x) * kBTopK;
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) out[q] = L[q];
   }
 }
 
@@ -287,37 +332,39 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
   int* act_next = cur ? act0 : act1;
   const int b = act[j];
   extern __shared__ v4f r_lds[];
-  __shared__ uint64_t wl[kBSelThreads / kWave][kBTopK];
+  __shared__ uint64_t wl[kBSelWaves][kBTopK];
   __shared__ uint64_t cand[kBTopK];
   __shared__ uint64_t resc[kBTopK];
-  __shared__ double dred[kBSelThreads / kWave];
+  __shared__ double dred[kBSelWaves];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   float* r = R32 + static_cast<int64_t>(b) * ld;
   const int ld4 = static_cast<int>(ld / 4);
   for (int i = threadIdx.x; i < ld4; i += kBSelThreads) r_lds[i] = reinterpret_cast<const v4f*>(r)[i];
 
-  // the signal's 8 best candidates over all atom tiles
-  uint64_t L[kBTopK];
-#pragma unroll
-  for (int q = 0; q < kBTopK; ++q) L[q] = 0;
-  const uint64_t* pk = partials + static_cast<int64_t>(j) * mtiles * kBTopK;
-  for (int i = threadIdx.x; i < mtiles * kBTopK; i += kBSelThreads) top8_insert(L, pk[i]);
-  const uint64_t w8 = wave_top8_lists(L, lane);
-  if (lane < kBTopK) wl[wave][lane] = w8;
+  // the signal's 8 best candidates: the product wrote one descending list of
+  // 8 keys per atom tile; each wave merges 16 lists at a time across its
+  // lanes and keeps a running top 8, then wave 0 merges the 8 waves' lists
+  {
+    const uint64_t* pk = partials + static_cast<int64_t>(j) * mtiles * kBTopK;
+    const int nkeys = mtiles * kBTopK;
+    uint64_t top = 0;
+    for (int g = wave; g * 2 * kWave < nkeys; g += kBSelWaves) {
+      const int i = g * 2 * kWave + lane;
+      const uint64_t a = i < nkeys ? pk[i] : 0ull;
+      const uint64_t c = i + kWave < nkeys ? pk[i + kWave] : 0ull;
+      top = merge_lane_lists8(top, top8_of_lists16(a, c, lane), lane);
+    }
+    if (lane < kBTopK) wl[wave][lane] = top;
+  }
   __syncthreads();
   if (wave == 0) {
-    uint64_t M8[kBTopK];
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) M8[q] = 0;
-    if (lane < kBSelThreads / kWave)
-#pragma unroll
-      for (int q = 0; q < kBTopK; ++q) M8[q] = wl[lane][q];
-    const uint64_t t8 = wave_top8_lists(M8, lane);
+    static_assert(kBSelWaves * kBTopK == kWave, "one list per group of 8 lanes");
+    const uint64_t t8 = top8_of_lists16(wl[lane / kBTopK][lane % kBTopK], 0ull, lane);
     if (lane < kBTopK) cand[lane] = t8;
   }
   __syncthreads();
   // re-score in FP32, one candidate per wave
-  for (int q = wave; q < rescore_k; q += kBSelThreads / kWave) {
+  for (int q = wave; q < rescore_k; q += kBSelWaves) {
     const uint64_t k = cand[q];
     uint64_t rk = 0;
     if (k != 0) {
@@ -352,14 +399,24 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     }
   }
   if (!stop_now) {
-    const float* colp = psi32 + static_cast<int64_t>(idx) * ld;
-    uint16_t* rq = Rq + static_cast<int64_t>(b) * ld;
+    // r -= c psi_idx from the LDS copy of r (padding rows stay 0), with its
+    // BF16 copy, four elements per thread and step
+    const v4f* colp = reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld);
+    v4f* r4 = reinterpret_cast<v4f*>(r);
+    uint2* rq4 = reinterpret_cast<uint2*>(Rq + static_cast<int64_t>(b) * ld);
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < ld; i += kBSelThreads) {
-      const float v = __builtin_fmaf(-c, colp[i], r[i]);  // padding rows stay 0
-      r[i] = v;
-      rq[i] = bf16_rne(v);
-      s += static_cast<double>(v) * v;
+    for (int i = threadIdx.x; i < ld4; i += kBSelThreads) {
+      const v4f a = colp[i], rv = r_lds[i];
+      v4f o;
+      o.x = __builtin_fmaf(-c, a.x, rv.x);
+      o.y = __builtin_fmaf(-c, a.y, rv.y);
+      o.z = __builtin_fmaf(-c, a.z, rv.z);
+      o.w = __builtin_fmaf(-c, a.w, rv.w);
+      r4[i] = o;
+      rq4[i] = uint2{static_cast<uint32_t>(bf16_rne(o.x)) | (static_cast<uint32_t>(bf16_rne(o.y)) << 16),
+                     static_cast<uint32_t>(bf16_rne(o.z)) | (static_cast<uint32_t>(bf16_rne(o.w)) << 16)};
+      s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
+           (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
     }
     const double rr = block_sum<kBSelThreads>(s, dred);
     if (threadIdx.x == 0) {

@@ -92,6 +92,37 @@ __device__ inline void top8_insert(uint64_t (&L)[kTopK], uint64_t key) {
   }
 }
 
+// ---- sorting networks on keys held in one thread's registers ----------------
+
+// Compare-exchange for descending order: a keeps the larger key.
+__device__ inline void cx_keys(uint64_t& a, uint64_t& b) {
+  const uint64_t hi = a > b ? a : b;
+  b = a > b ? b : a;
+  a = hi;
+}
+
+// Sorts 8 keys in descending order: a 19 compare-exchange network (checked
+// on all 256 inputs of 0s and 1s, which suffices for a sorting network).
+__device__ inline void sort8_keys(uint64_t (&v)[8]) {
+  cx_keys(v[0], v[2]); cx_keys(v[1], v[3]); cx_keys(v[4], v[6]); cx_keys(v[5], v[7]);
+  cx_keys(v[0], v[4]); cx_keys(v[1], v[5]); cx_keys(v[2], v[6]); cx_keys(v[3], v[7]);
+  cx_keys(v[0], v[1]); cx_keys(v[2], v[3]); cx_keys(v[4], v[5]); cx_keys(v[6], v[7]);
+  cx_keys(v[2], v[4]); cx_keys(v[3], v[5]);
+  cx_keys(v[1], v[4]); cx_keys(v[3], v[6]);
+  cx_keys(v[1], v[2]); cx_keys(v[3], v[4]); cx_keys(v[5], v[6]);
+}
+
+// a <- the 8 largest of two descending lists a and b, descending: the
+// element-wise maximum of a and reversed b is bitonic and holds them; the
+// bitonic merge (distances 4, 2, 1) sorts it.
+__device__ inline void merge8_keys(uint64_t (&a)[8], const uint64_t (&b)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = a[i] > b[7 - i] ? a[i] : b[7 - i];
+  cx_keys(a[0], a[4]); cx_keys(a[1], a[5]); cx_keys(a[2], a[6]); cx_keys(a[3], a[7]);
+  cx_keys(a[0], a[2]); cx_keys(a[1], a[3]); cx_keys(a[4], a[6]); cx_keys(a[5], a[7]);
+  cx_keys(a[0], a[1]); cx_keys(a[2], a[3]); cx_keys(a[4], a[5]); cx_keys(a[6], a[7]);
+}
+
 // ---- bitonic merge of sorted 8-key lists across the lanes of a wave ----------
 
 // Lane i receives lane (i ^ 4)'s key (groups of 8 lanes inside a row of 16).
@@ -139,21 +170,10 @@ __device__ inline uint64_t top8_of_lists16(uint64_t a, uint64_t b, int lane) {
   return bitonic_sort8(v, lane);
 }
 
-// The 8 largest keys over the lanes' sorted lists; lane j < 8 receives the
-// j-th largest.  Keys are distinct apart from 0.
-__device__ inline uint64_t wave_top8_lists(uint64_t (&L)[kTopK], int lane) {
-  uint64_t out = 0;
-#pragma unroll
-  for (int j = 0; j < kTopK; ++j) {
-    const uint64_t w = wave_max(L[0]);
-    if (lane == j) out = w;
-    if (w != 0 && L[0] == w) {  // pop the head of the list that held it
-#pragma unroll
-      for (int q = 0; q + 1 < kTopK; ++q) L[q] = L[q + 1];
-      L[kTopK - 1] = 0;
-    }
-  }
-  return out;
+// The 8 largest of two descending lists held in every group of 8 lanes (rank
+// j in lane 8g + j), sorted the same way.
+__device__ inline uint64_t merge_lane_lists8(uint64_t a, uint64_t b, int lane) {
+  return bitonic_sort8(umax64(a, dpp_u64<kDppRowHalfMirror>(b)), lane);
 }
 
 }  // namespace mp
