@@ -10,7 +10,10 @@ Prints ONE JSON line.  `value` is MP iterations per second over the timed
 steps; `roofline` is the correlation kernel's algorithmic HBM bandwidth
 (dictionary + residual bytes per launch / mean launch time from HIP events on
 the decode stream) against the 8 TB/s peak; `cpu_baseline` is the FP64
-oracle timed on a bounded sample of the same decode on this host.
+oracle timed on a bounded sample of the same decode on this host.  The line
+also carries the batched form, the ragged instances and the FP64 decode of
+the same workload (each skippable with --no-batched / --no-ragged /
+--no-f64).
 """
 from __future__ import annotations
 
@@ -39,7 +42,12 @@ TRAFFIC = {
     "fp8": (os.path.join(ROOT, "profiles", "mp_step_lp_fp8_traffic.json"),
             [os.path.join(_CSRC, f) for f in ("k_lowp.hip", "k_lowp.h", "k_common.h",
                                               "mp_internal.h")]),
+    "f64": (os.path.join(ROOT, "profiles", "mp_step_f64_traffic.json"),
+            [os.path.join(_CSRC, f) for f in ("k_f64.hip", "k_common.h", "mp_internal.h")]),
 }
+ESIZE = {"f64": 8.0, "f32": 4.0, "bf16": 2.0, "fp8": 1.0}
+KERNEL = {"f64": "k_mp_step_f64", "f32": "k_mp_step_f32", "bf16": "k_mp_step_lp",
+          "fp8": "k_mp_step_lp"}
 
 WORKLOADS = {
     "c1b": "N=8192, M=32768 (FP32 dictionary 1 GiB), K=512, eps=1e-5, T=10240, single signal",
@@ -75,14 +83,86 @@ def traffic_from_counters(n, m, storage="f32"):
     return d.get("bytes_per_launch")
 
 
+def step_bytes(n, m, storage):
+    """Algorithmic bytes of one iteration's launch: the dictionary copy once,
+    r once, and for the reduced-precision forms the FP8 scales and the 8 FP32
+    candidate columns re-scored."""
+    rsize = 8.0 if storage == "f64" else 4.0
+    b = ESIZE[storage] * n * m + rsize * n
+    if storage == "fp8":
+        b += 4.0 * m
+    if storage in ("bf16", "fp8"):
+        b += 8 * 4.0 * n
+    return b
+
+
+def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None):
+    """Warm up, then time `steps` whole decodes; the step kernel's launches are
+    timed with HIP events on the decode stream (every profile_every-th)."""
+    import torch
+    for _ in range(warmup):
+        dec.solve(y, p.eps, p.max_iters, x=x, r=r)
+    dec.set_profiling(profile_every)
+    torch.cuda.synchronize()
+    iters, kt_ms, kt_n, stops = 0, 0.0, 0, set()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream)
+        iters += out["iters"]
+        ms, cnt = dec.kernel_time()
+        kt_ms += ms * cnt
+        kt_n += cnt
+        stops.add(out["stop"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dec.set_profiling(0)
+    return iters, dt, kt_ms / max(kt_n, 1), kt_n, stops
+
+
+def bench_f64(seed: int, steps: int = 2, warmup: int = 1, profile_every: int = 16):
+    """FP64 decode of the same N=8192, M=32768 workload (2 GiB FP64
+    dictionary): iters/s and the step kernel's algorithmic HBM bandwidth."""
+    import numpy as np
+    import torch
+
+    import mpgen
+    from paper_0809_1833_amd.mp import Decoder
+
+    p = mpgen.make_problem("c1b", seed, precision="f64")
+    n, m = p.n, p.m
+    psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
+    y = torch.from_numpy(p.y).cuda()
+    del p.psi
+    with Decoder(psi, storage="f64") as dec:
+        del psi
+        x = torch.empty(m, dtype=torch.float64, device="cuda")
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
+                                                      x, r)
+    b = step_bytes(n, m, "f64")
+    achieved = b / (avg_ms * 1e-3) / 1e9 if kt_n else None
+    return {"workload": f"N={n}, M={m} (FP64 dictionary 2 GiB), K=512, eps=1e-5, T=10240, "
+                        "single signal, FP64 throughout",
+            "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
+            "iters_per_decode": iters // max(steps, 1), "stop": sorted(stops),
+            "roofline": {"bound": "hbm", "kernel": KERNEL["f64"],
+                         "achieved": round(achieved, 2) if achieved else None,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                         "traffic": traffic_from_counters(n, m, "f64"),
+                         "bytes_per_launch": b, "avg_launch_us": round(avg_ms * 1e3, 3),
+                         "launches": kt_n}}
+
+
 def cpu_baseline(p, budget_s=15.0):
     import oracle
+    solve = oracle.solve64 if p.psi.dtype.itemsize == 8 else oracle.solve
     t0 = time.perf_counter()
-    oracle.solve(p.psi, p.y, p.eps, 2, trace=False)
+    solve(p.psi, p.y, p.eps, 2, trace=False)
     per = max((time.perf_counter() - t0) / 2.0, 1e-6)
     iters = int(max(3, min(p.max_iters, budget_s / per)))
     t0 = time.perf_counter()
-    res = oracle.solve(p.psi, p.y, p.eps, iters, trace=False)
+    res = solve(p.psi, p.y, p.eps, iters, trace=False)
     dt = time.perf_counter() - t0
     return dict(value=round(res.iters / dt, 3), unit="iters/s", cores=oracle.num_threads(),
                 kind="oracle",
@@ -203,14 +283,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1b", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8"],
-                    help="dictionary copy the correlation pass streams")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8", "f64"],
+                    help="dictionary copy the correlation pass streams (f64: the FP64 "
+                         "decode, FP64 inputs)")
     ap.add_argument("--dist", default="normal", choices=["normal", "loguniform"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form measurement added to the line")
     ap.add_argument("--no-ragged", action="store_true",
                     help="skip the ragged-instances measurement added to the line")
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the FP64-decode measurement added to the line")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every k-th iteration's kernel launch with HIP events")
     ap.add_argument("--max-iters", type=int, default=None,
@@ -229,50 +312,27 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"[bench] generating {args.workload} seed {args.seed}")
-    p = mpgen.make_problem(args.workload, args.seed, dist=args.dist)
+    prec = "f64" if args.storage == "f64" else "f32"
+    p = mpgen.make_problem(args.workload, args.seed, dist=args.dist, precision=prec)
     if args.max_iters is not None:
         p.max_iters = min(p.max_iters, args.max_iters)
     n, m = p.n, p.m
+    tdt = torch.float64 if prec == "f64" else torch.float32
     psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
     y = torch.from_numpy(p.y).cuda()
     stream = torch.cuda.current_stream()
     dec = Decoder(psi, storage=args.storage)
     del psi
-    x = torch.empty(m, dtype=torch.float32, device="cuda")
-    r = torch.empty(n, dtype=torch.float32, device="cuda")
-    log("[bench] warmup")
-    for _ in range(args.warmup):
-        dec.solve(y, p.eps, p.max_iters, x=x, r=r)
-    dec.set_profiling(args.profile_every)
-    torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} decodes")
-    iters = 0
-    kt_ms, kt_n = 0.0, 0
-    stops = set()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream)
-        iters += out["iters"]
-        ms, cnt = dec.kernel_time()
-        kt_ms += ms * cnt
-        kt_n += cnt
-        stops.add(out["stop"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    dec.set_profiling(0)
+    x = torch.empty(m, dtype=tdt, device="cuda")
+    r = torch.empty(n, dtype=tdt, device="cuda")
+    log(f"[bench] warmup, then timing {args.steps} decodes")
+    iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, args.steps, args.warmup,
+                                                  args.profile_every, x, r, stream)
     log(f"[bench] {iters} iterations in {dt:.3f} s")
 
-    # algorithmic bytes of one iteration's launch: the dictionary copy once,
-    # r once, and for the reduced-precision forms the FP8 scales and the 8
-    # FP32 candidate columns re-scored
-    esize = {"f32": 4.0, "bf16": 2.0, "fp8": 1.0}[args.storage]
-    bytes_per_launch = esize * n * m + 4.0 * n
-    if args.storage == "fp8":
-        bytes_per_launch += 4.0 * m
-    if args.storage != "f32":
-        bytes_per_launch += 8 * 4.0 * n
-    bytes_per_iter = bytes_per_launch + 8.0 * n       # + residual read and written by the update
-    avg_ms = kt_ms / max(kt_n, 1)
+    bytes_per_launch = step_bytes(n, m, args.storage)
+    rsize = 8.0 if prec == "f64" else 4.0
+    bytes_per_iter = bytes_per_launch + 2 * rsize * n  # + residual read and written by the update
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kt_n else None
     traffic = traffic_from_counters(n, m, args.storage)
     line = {
@@ -287,7 +347,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16": "bf16 storage, f32 accumulate",
-                  "fp8": "fp8-e4m3 storage, f32 accumulate"}[args.storage],
+                  "fp8": "fp8-e4m3 storage, f32 accumulate", "f64": "f64"}[args.storage],
         "data": "synthetic (seeded Gaussian unit-column dictionary, K-sparse N(0,1) signal)",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "storage": args.storage, "dist": args.dist,
@@ -297,7 +357,7 @@ def main():
         "effective_gbps_whole_step": round(iters * bytes_per_iter / dt / 1e9, 2),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_mp_step_f32" if args.storage == "f32" else "k_mp_step_lp",
+            "kernel": KERNEL[args.storage],
             "achieved": round(achieved, 2) if achieved else None,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -315,6 +375,9 @@ def main():
     if not args.no_ragged:
         log("[bench] ragged instances (512 problems of uneven size)")
         line["ragged"] = bench_ragged(args.seed)
+    if not args.no_f64 and args.storage != "f64":
+        log("[bench] FP64 decode of the same workload")
+        line["f64"] = bench_f64(args.seed)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p)

@@ -59,9 +59,11 @@ typedef enum mp_status {
 typedef enum mp_dtype {
     MP_F32 = 0,           /* FP32, as given */
     MP_BF16 = 1,          /* BF16, round to nearest even from FP32 */
-    MP_FP8_E4M3 = 2       /* OCP FP8 E4M3 (e4m3fn) with one FP32 scale per column:
+    MP_FP8_E4M3 = 2,      /* OCP FP8 E4M3 (e4m3fn) with one FP32 scale per column:
                              s_m = fp32(max_n |psi_nm| / 448) (1 for a zero column),
                              code = RNE-saturate(fp32(psi_nm / s_m)) */
+    MP_F64 = 3            /* FP64 dictionary and FP64 decode (mp_create_f64 /
+                             mp_solve_f64 only) */
 } mp_dtype;
 
 /* Why a decode stopped (mp_result.stop_reason). */
@@ -104,6 +106,14 @@ typedef struct mp_trace {
     double* rr;
     int64_t cap;
 } mp_trace;
+
+/* The same record for an FP64 decode: coef[t] is the FP64 coefficient. */
+typedef struct mp_trace_f64 {
+    int32_t* idx;
+    double* coef;
+    double* rr;
+    int64_t cap;
+} mp_trace_f64;
 
 /*
  * mp_create -- take the dictionary Psi (Section 2, eqs. 3-4) and prepare it
@@ -184,6 +194,45 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
                            const int64_t* max_iters_b, mp_result* res, const mp_trace* trace,
                            void* stream);
 
+/*
+ * mp_create_f64 -- mp_create for an FP64 dictionary: the double-precision
+ * configuration of the decoder (the paper times single- and double-precision
+ * builds of the same loop, Section 4).  The correlation pass streams the FP64
+ * copy (8 bytes per element) and every inner product, coefficient, residual
+ * and norm is FP64.  The context has storage MP_F64 and is decoded only with
+ * mp_solve_f64 (mp_solve and mp_solve_batched return MP_EINVAL for it).
+ *
+ *   out      host: receives the new context (set to NULL on failure)
+ *   psi      device: FP64 N x M column-major dictionary, leading dimension ld
+ *   n, m     1 <= N <= 16384, 1 <= M < 2^31
+ *   ld       leading dimension, ld >= n
+ *   flags    MP_SKIP_NORM_CHECK or 0
+ *   stream   hipStream_t as void*
+ *
+ * The context copies psi (padded leading dimension); the caller may free it
+ * when the call returns.  Errors: as mp_create.
+ */
+mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, int64_t ld,
+                        uint32_t flags, void* stream);
+
+/*
+ * mp_solve_f64 -- decode one signal on an MP_F64 context: the Section 3 loop
+ * in FP64 on the device, as mp_solve.
+ *
+ *   y        device: N doubles, not modified
+ *   x        device: M doubles, overwritten with x~
+ *   r        device: N doubles or NULL; receives the final residual
+ *   opts     host: eps, max_iters (rescore_k is ignored), flags 0
+ *   res      host or NULL (rr is the FP64 norm of the FP64 residual)
+ *   trace    host struct of device arrays, or NULL (see mp_trace_f64)
+ *
+ * y, x and r must not overlap.  Errors: MP_EINVAL (not an MP_F64 context,
+ * NULL ctx/y/x/opts, bad opts), MP_ENONFINITE (y holds NaN/Inf),
+ * MP_EDEVICE.
+ */
+mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const mp_opts* opts,
+                       mp_result* res, const mp_trace_f64* trace, void* stream);
+
 /* One problem of a ragged set: its own dictionary (device, FP32, column-major
    N x M with leading dimension ld). */
 typedef struct mp_instance {
@@ -261,9 +310,9 @@ const char* mp_last_error(const mp_ctx* ctx);
 
 /*
  * mp_get_storage -- copy out the dictionary copy the correlation pass reads,
- * without its padding: FP32 (4-byte), BF16 (2-byte) or FP8 (1-byte) codes,
- * column-major N x M with leading dimension N, and for MP_FP8_E4M3 the M
- * per-column FP32 scales (scales may be NULL otherwise).
+ * without its padding: FP64 (8-byte), FP32 (4-byte), BF16 (2-byte) or FP8
+ * (1-byte) codes, column-major N x M with leading dimension N, and for
+ * MP_FP8_E4M3 the M per-column FP32 scales (scales may be NULL otherwise).
  *
  *   codes    device: N*M elements of the storage type's size
  *   scales   device: M floats, or NULL

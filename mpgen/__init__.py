@@ -23,6 +23,8 @@ Workloads (all synthetic; the paper measures on no dataset):
 Dictionaries are Gaussian N(0,1) with every column divided by its FP64 L2 norm
 and then rounded to FP32; supports are uniform without replacement; y is
 computed in FP64 from the FP32 dictionary and FP32 x, then rounded to FP32.
+The FP64 variants of the single-signal workloads (``precision='f64'``) use
+the same draws and keep the dictionary, x and y in FP64.
 Seeds go through ``numpy.random.SeedSequence([workload_id, seed])``.
 """
 from __future__ import annotations
@@ -83,18 +85,20 @@ def rng_streams(wid: int, seed: int, count: int) -> List[np.random.Generator]:
 
 
 def gaussian_unit_dictionary(rng: np.random.Generator, n: int, m: int,
-                             chunk: int = 2048) -> np.ndarray:
-    """N x M Gaussian dictionary, columns normalised in FP64, stored as FP32.
+                             chunk: int = 2048, dtype=np.float32) -> np.ndarray:
+    """N x M Gaussian dictionary, columns normalised in FP64, stored as FP32
+    (or kept in FP64 with ``dtype=np.float64``; the same draws, so the FP32
+    dictionary is the FP64 one rounded).
 
     Columns are drawn one after another (column m's N entries are consecutive
-    draws), normalised to unit L2 norm (eq. 4) and rounded to FP32.
+    draws), normalised to unit L2 norm (eq. 4) and rounded to ``dtype``.
     """
-    cols = np.empty((m, n), dtype=np.float32)
+    cols = np.empty((m, n), dtype=dtype)
     for j0 in range(0, m, chunk):
         j1 = min(m, j0 + chunk)
         g = rng.standard_normal((j1 - j0, n))
         nrm = np.sqrt(np.einsum("ij,ij->i", g, g))
-        cols[j0:j1] = (g / nrm[:, None]).astype(np.float32)
+        cols[j0:j1] = (g / nrm[:, None]).astype(dtype)
     return cols.T  # (n, m) view in Fortran order
 
 
@@ -128,12 +132,12 @@ def qr_orthonormal_dictionary(rng: np.random.Generator, n: int,
 
 
 def sparse_signal(rng_support: np.random.Generator, rng_values: np.random.Generator,
-                  m: int, k: int, dist: str = "normal"):
+                  m: int, k: int, dist: str = "normal", dtype=np.float32):
     """K-sparse x (eq. 1): support uniform without replacement.
 
     ``dist='normal'``: nonzeros i.i.d. N(0,1).  ``dist='loguniform'``:
     magnitudes 10^U(-3,0) with an independent random sign (p = 1/2).
-    Returns (x float32 (M,), support int64 sorted).
+    Returns (x (M,) of ``dtype``, support int64 sorted).
     """
     support = np.sort(rng_support.choice(m, size=k, replace=False)).astype(np.int64)
     if dist == "normal":
@@ -146,29 +150,37 @@ def sparse_signal(rng_support: np.random.Generator, rng_values: np.random.Genera
         raise ValueError(dist)
     x = np.zeros(m, dtype=np.float64)
     x[support] = vals
-    return x.astype(np.float32), support
+    return x.astype(dtype), support
 
 
-def encode(psi: np.ndarray, x: np.ndarray, support: Optional[np.ndarray] = None) -> np.ndarray:
-    """y = Psi x (eq. 2) in FP64 from the FP32 inputs, rounded to FP32."""
+def encode(psi: np.ndarray, x: np.ndarray, support: Optional[np.ndarray] = None,
+           dtype=np.float32) -> np.ndarray:
+    """y = Psi x (eq. 2) in FP64 from the given inputs, rounded to ``dtype``."""
     if support is None:
         support = np.flatnonzero(x)
     cols = np.asarray(psi[:, support], dtype=np.float64)
     y = cols @ np.asarray(x[support], dtype=np.float64)
-    return y.astype(np.float32)
+    return y.astype(dtype)
 
 
-def make_problem(name: str, seed: int, dist: str = "normal") -> Problem:
-    """A single-signal workload (``c0``, ``c1a``, ``c1b`` or ``c2``)."""
+def make_problem(name: str, seed: int, dist: str = "normal", precision: str = "f32") -> Problem:
+    """A single-signal workload (``c0``, ``c1a``, ``c1b`` or ``c2``).
+
+    ``precision='f64'`` draws the same problem for the FP64 decoder: the
+    dictionary, x and y stay FP64 (no rounding to FP32 anywhere)."""
+    if precision not in ("f32", "f64"):
+        raise ValueError(precision)
+    dt = np.float64 if precision == "f64" else np.float32
     w = workload(name)
     r_psi, r_sup, r_val = rng_streams(w["wid"], seed, 3)
     if dist == "loguniform":  # a separate value stream for the second distribution
         r_val = rng_streams(w["wid"] + 100, seed, 1)[0]
-    psi = gaussian_unit_dictionary(r_psi, w["n"], w["m"])
-    x, support = sparse_signal(r_sup, r_val, w["m"], w["k"], dist)
-    y = encode(psi, x, support)
+    psi = gaussian_unit_dictionary(r_psi, w["n"], w["m"], dtype=dt)
+    x, support = sparse_signal(r_sup, r_val, w["m"], w["k"], dist, dtype=dt)
+    y = encode(psi, x, support, dtype=dt)
     return Problem(psi, x, y, support, w["eps"], w["max_iters"],
-                   meta=dict(workload=name, seed=seed, dist=dist, k=w["k"]))
+                   meta=dict(workload=name, seed=seed, dist=dist, k=w["k"],
+                             precision=precision))
 
 
 @dataclass

@@ -1,0 +1,320 @@
+// FP64 single-signal Matching Pursuit for gfx950 (Section 3, eqs. 8-12): the
+// double-precision configuration the paper times beside the single-precision
+// one (Section 4).  Dictionary, y, x~, r and every inner product are FP64.
+//
+// The launch structure is the FP32 form's: one MP iteration per launch, one
+// 16-wave workgroup per CU, r staged whole in LDS (N <= 16384 doubles =
+// 128 KB), each column streamed with 16-byte non-temporal loads (two doubles)
+// and summed with FP64 FMAs in two per-lane chains over the column halves,
+// then across the wave.  A candidate is a pair of 64-bit words so that the
+// exact FP64 coefficient survives the argmax: the |c| bits (a non-negative
+// double orders like its bit pattern), then (0x7FFFFFFF - index) and the
+// sign; the pair order is "larger |c|, then smaller index" (eq. 16).  Each
+// workgroup hands its pair to the last workgroup to arrive through the same
+// RMW-only protocol as the FP32 form, and that workgroup updates x~ and r and
+// applies the FP64 stopping test.
+#include "k_common.h"
+#include "mp_internal.h"
+
+namespace mp {
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+constexpr int kF64Threads = 1024;
+constexpr int kF64Waves = kF64Threads / kWave;
+
+// ---- candidate pairs ----------------------------------------------------------
+
+struct Key2 {
+  uint64_t hi;  // |c| bits, sign cleared (NaN mapped to 0)
+  uint64_t lo;  // (0x7FFFFFFF - index) << 1 | sign of c; 0 = empty
+};
+
+__device__ inline Key2 make_key2(double c, int idx) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, c);
+  uint64_t ab = u & 0x7FFFFFFFFFFFFFFFull;
+  if (ab > 0x7FF0000000000000ull) ab = 0;
+  return Key2{ab, (static_cast<uint64_t>(0x7FFFFFFFu - static_cast<uint32_t>(idx)) << 1) |
+                      (u >> 63)};
+}
+__device__ inline int key2_index(const Key2& k) {
+  return static_cast<int>(0x7FFFFFFFu - (static_cast<uint32_t>(k.lo) >> 1));
+}
+__device__ inline double key2_value(const Key2& k) {
+  return __builtin_bit_cast(double, k.hi | ((k.lo & 1ull) << 63));
+}
+__device__ inline bool key2_greater(const Key2& a, const Key2& b) {
+  return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
+}
+__device__ inline Key2 key2_max(const Key2& a, const Key2& b) {
+  return key2_greater(b, a) ? b : a;
+}
+
+template <int CTRL>
+__device__ inline Key2 dpp_key2(const Key2& k) {
+  return Key2{dpp_u64<CTRL>(k.hi), dpp_u64<CTRL>(k.lo)};
+}
+__device__ inline Key2 lane_key2(const Key2& k, int l) {
+  return Key2{lane_u64(k.hi, l), lane_u64(k.lo, l)};
+}
+
+// Wave-uniform maximum pair (the DPP pattern of wave_max).
+__device__ inline Key2 wave_max_key2(Key2 k) {
+  k = key2_max(k, dpp_key2<kDppQuadSwap1>(k));
+  k = key2_max(k, dpp_key2<kDppQuadSwap2>(k));
+  k = key2_max(k, dpp_key2<kDppRowRor4>(k));
+  k = key2_max(k, dpp_key2<kDppRowRor8>(k));
+  return key2_max(key2_max(lane_key2(k, 0), lane_key2(k, 16)),
+                  key2_max(lane_key2(k, 32), lane_key2(k, 48)));
+}
+
+// Workgroup-wide maximum pair; every thread receives it.  `red` holds
+// kF64Waves pairs of LDS.
+__device__ inline Key2 block_max_key2(Key2 k, Key2* red) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  k = wave_max_key2(k);
+  if (lane == 0) red[wave] = k;
+  __syncthreads();
+  Key2 s = lane < kF64Waves ? red[lane] : Key2{0, 0};
+  s = wave_max_key2(s);
+  __syncthreads();
+  return s;
+}
+
+// ---- FP64 inner product of one column with the LDS copy of r -----------------
+//
+// Lane l sums the 16-byte chunks (two doubles) l, l+64, ... below h0 = ld2/2
+// into one FP64 accumulator and h0+l, h0+l+64, ... into another, each in
+// increasing order with FMAs; the two are added per lane and the wave sums
+// the lanes.
+
+template <int U>
+__device__ inline void dot_block2_f64(const v2d* __restrict__ p, const v2d* __restrict__ r_lds,
+                                      int h0, int& i, double& acc_a, double& acc_b) {
+  v2d a[U], b[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+    b[u] = __builtin_nontemporal_load(p + h0 + i + kWave * u);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const v2d ra = r_lds[i + kWave * u];
+    acc_a = __builtin_fma(a[u].x, ra.x, acc_a);
+    acc_a = __builtin_fma(a[u].y, ra.y, acc_a);
+    const v2d rb = r_lds[h0 + i + kWave * u];
+    acc_b = __builtin_fma(b[u].x, rb.x, acc_b);
+    acc_b = __builtin_fma(b[u].y, rb.y, acc_b);
+  }
+  i += kWave * U;
+}
+
+__device__ inline double dot_column_f64(const v2d* __restrict__ p, const v2d* __restrict__ r_lds,
+                                        int ld2, int lane) {
+  const int h0 = ld2 / 2;
+  double acc_a = 0.0, acc_b = 0.0;
+  int i = lane;
+  while (i + kWave * 7 < h0) dot_block2_f64<8>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i + kWave * 3 < h0) dot_block2_f64<4>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i + kWave * 1 < h0) dot_block2_f64<2>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i < h0) dot_block2_f64<1>(p, r_lds, h0, i, acc_a, acc_b);
+  return wave_sum(acc_a + acc_b);
+}
+
+// ---------------------------------------------------------------------------
+// Set-up check of eq. 4: norm2[m] = sum_n psi_nm^2 in FP64, one wave per column.
+__global__ __launch_bounds__(256) void k_norms_f64(const double* __restrict__ psi, int64_t ld,
+                                                   int64_t n, int64_t m,
+                                                   double* __restrict__ norm2) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t col = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / kWave;
+  if (col >= m) return;
+  const double* p = psi + col * ld;
+  double s = 0.0;
+  for (int64_t i = lane; i < n; i += kWave) s = __builtin_fma(p[i], p[i], s);
+  s = wave_sum(s);
+  if (lane == 0) norm2[col] = s;
+}
+
+// Init (eq. 8): r = y (zero padded to ld), x~ = 0, t = 0, ||y||^2, pre-test.
+__global__ __launch_bounds__(256) void k_init_f64(const double* __restrict__ y, int64_t n,
+                                                  int64_t ld, double* __restrict__ x, int64_t m,
+                                                  double* __restrict__ r,
+                                                  DevState* __restrict__ st, double eps,
+                                                  long long max_iters) {
+  __shared__ double red[4];
+  const int64_t gtid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t gstride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t j = gtid; j < m; j += gstride) x[j] = 0.0;
+  if (blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < ld; i += 256) {
+    const double v = i < n ? y[i] : 0.0;
+    r[i] = v;
+    s = __builtin_fma(v, v, s);
+  }
+  const double yy = block_sum<256>(s, red);
+  if (threadIdx.x == 0) {
+    DevState d{};
+    d.yy = yy;
+    d.rr = yy;
+    d.thr = eps * eps * yy;
+    d.t = 0;
+    d.max_iters = max_iters;
+    d.done = 0;
+    d.reason = MP_STOP_CONVERGED;
+    if (!__builtin_isfinite(yy)) {
+      d.done = 1;
+      d.reason = kStopNonFinite;
+    } else if (yy == 0.0) {
+      d.done = 1;
+      d.reason = MP_STOP_ZERO_INPUT;
+    } else if (!(yy > d.thr)) {
+      d.done = 1;
+      d.reason = MP_STOP_CONVERGED;
+    } else if (max_iters <= 0) {
+      d.done = 1;
+      d.reason = MP_STOP_MAX_ITERS;
+    }
+    *st = d;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One MP iteration in one launch (eqs. 9-12).  Wave w of workgroup b takes
+// columns b*cpw + w, + 16, ...; the workgroup's best pair is handed to the
+// last workgroup, which selects, updates and tests.
+__global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
+    const double* __restrict__ psi, int64_t ld, int64_t n, int64_t m, double* __restrict__ r,
+    int cols_per_wg, uint64_t* __restrict__ keys, double* __restrict__ x,
+    DevState* __restrict__ st, mp_trace_f64 tr) {
+  if (st->done) return;
+  extern __shared__ v2d r2_lds[];
+  __shared__ Key2 kred[kF64Waves];
+  __shared__ double dred[kF64Waves];
+  const int ld2 = static_cast<int>(ld / 2);
+  const v2d* r2 = reinterpret_cast<const v2d*>(r);
+  for (int i = threadIdx.x; i < ld2; i += kF64Threads) r2_lds[i] = r2[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
+  int64_t col1 = col0 + cols_per_wg;
+  if (col1 > m) col1 = m;
+  Key2 best{0, 0};
+  for (int64_t col = col0 + wave; col < col1; col += kF64Waves) {
+    const double c =
+        dot_column_f64(reinterpret_cast<const v2d*>(psi + col * ld), r2_lds, ld2, lane);
+    best = key2_max(best, make_key2(c, static_cast<int>(col)));
+  }
+  best = block_max_key2(best, kred);
+  // lane 0 of wave 0 publishes the |c| word, lane 1 the index word
+  if (!publish_arrive<2>(lane == 0 ? best.hi : best.lo, keys, st)) return;
+
+  // ---- last workgroup: the launch's winner ----
+  Key2 w{0, 0};
+  for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += kF64Threads) {
+    const Key2 k{take_slot(keys + 2 * i), take_slot(keys + 2 * i + 1)};
+    w = key2_max(w, k);
+  }
+  w = block_max_key2(w, kred);
+  const int idx = key2_index(w);
+  const double c = key2_value(w);
+  if (w.lo == 0 || idx < 0 || idx >= m) {  // cannot happen for a published pair
+    if (threadIdx.x == 0) {
+      st->done = 1;
+      st->reason = kStopInternal;
+    }
+    return;
+  }
+  if (c == 0.0) {  // no atom correlates with r
+    if (threadIdx.x == 0) {
+      st->done = 1;
+      st->reason = MP_STOP_STALLED;
+    }
+    return;
+  }
+  // r <- r - c psi_idx from the LDS copy of r; all column loads first (ld <=
+  // 16384 gives at most P chunks per thread), padding rows stay +0
+  constexpr int P = 16384 / 2 / kF64Threads;
+  const v2d* colp = reinterpret_cast<const v2d*>(psi + static_cast<int64_t>(idx) * ld);
+  v2d* rw = reinterpret_cast<v2d*>(r);
+  v2d a[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int i = threadIdx.x + u * kF64Threads;
+    if (i < ld2) a[u] = colp[i];
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int i = threadIdx.x + u * kF64Threads;
+    if (i < ld2) {
+      const v2d rv = r2_lds[i];
+      v2d o;
+      o.x = __builtin_fma(-c, a[u].x, rv.x);
+      o.y = __builtin_fma(-c, a[u].y, rv.y);
+      rw[i] = o;
+      s = __builtin_fma(o.x, o.x, s);
+      s = __builtin_fma(o.y, o.y, s);
+    }
+  }
+  const double rr = block_sum<kF64Threads>(s, dred);
+  if (threadIdx.x == 0) {
+    x[idx] += c;
+    const long long t = st->t;
+    if (t < tr.cap) {
+      if (tr.idx) tr.idx[t] = idx;
+      if (tr.coef) tr.coef[t] = c;
+      if (tr.rr) tr.rr[t] = rr;
+    }
+    st->t = t + 1;
+    st->rr = rr;
+    if (!(rr > st->thr)) {
+      st->done = 1;
+      st->reason = MP_STOP_CONVERGED;
+    } else if (t + 1 >= st->max_iters) {
+      st->done = 1;
+      st->reason = MP_STOP_MAX_ITERS;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+hipError_t launch_norms_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* norm2,
+                            hipStream_t s) {
+  const int64_t blocks = (m + 3) / 4;
+  k_norms_f64<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(psi, ld, n, m, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_f64(const double* y, int64_t n, int64_t ld, double* x, int64_t m,
+                           double* r, DevState* st, double eps, long long max_iters,
+                           hipStream_t s) {
+  int64_t blocks = (m + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  k_init_f64<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(y, n, ld, x, m, r, st,
+                                                                        eps, max_iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* r,
+                              const CorrGeom& g, uint64_t* keys, double* x, DevState* st,
+                              mp_trace_f64 tr, hipStream_t s) {
+  const size_t lds = static_cast<size_t>(ld) * sizeof(double);
+  static size_t lds_set = 60 * 1024;  // above the default limit the opt-in is raised
+  if (lds > lds_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mp_step_f64),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    lds_set = lds;
+  }
+  k_mp_step_f64<<<dim3(g.grid), dim3(kF64Threads), lds, s>>>(psi, ld, n, m, r, g.cols_per_wg,
+                                                              keys, x, st, tr);
+  return hipGetLastError();
+}
+
+}  // namespace mp

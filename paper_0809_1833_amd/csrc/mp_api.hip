@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "mp_internal.h"
 
@@ -77,6 +78,8 @@ void free_ctx(mp_ctx* c) {
   free_ragged(c);
   if (c->psib_owned) (void)hipFree(c->psib);
   (void)hipFree(c->psi32);
+  (void)hipFree(c->psi64);
+  (void)hipFree(c->r64_work);
   (void)hipFree(c->psiq);
   (void)hipFree(c->scales);
   (void)hipFree(c->r_work);
@@ -101,6 +104,160 @@ hipError_t enqueue_iteration(mp_ctx* c, float* x, const mp_trace& tr, hipStream_
   if (e != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
   return hipSuccess;
+}
+
+// The current device, if it is a gfx950 this library was built for.
+mp_status open_device(int& dev, hipDeviceProp_t& prop) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return fail(nullptr, MP_EDEVICE, "no HIP device");
+  HIP_TRY(nullptr, hipGetDevice(&dev));
+  HIP_TRY(nullptr, hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, MP_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                              ", this library is built for gfx950");
+  return MP_OK;
+}
+
+// Eq. 4 on the FP64 squared column norms: finite always, 1 within kNormTol
+// unless MP_SKIP_NORM_CHECK.  Returns MP_OK or the status with `msg` set.
+mp_status check_norms(const std::vector<double>& norm2, uint32_t flags, std::string& msg) {
+  for (size_t j = 0; j < norm2.size(); ++j) {
+    if (!isfinite(norm2[j])) {
+      char buf[96];
+      snprintf(buf, sizeof buf, "column %lld holds NaN or Inf", static_cast<long long>(j));
+      msg = buf;
+      return MP_ENONFINITE;
+    }
+    if (!(flags & MP_SKIP_NORM_CHECK) && fabs(sqrt(norm2[j]) - 1.0) > kNormTol) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "column %lld has norm %.9g (must be 1 within 1e-4)",
+               static_cast<long long>(j), sqrt(norm2[j]));
+      msg = buf;
+      return MP_ENOTNORM;
+    }
+  }
+  return MP_OK;
+}
+
+mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
+  if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
+    return fail(c, MP_EINVAL, "eps must be finite and >= 0");
+  if (opts->max_iters < 0) return fail(c, MP_EINVAL, "max_iters must be >= 0");
+  if (opts->flags != 0) return fail(c, MP_EINVAL, "opts.flags must be 0");
+  if (opts->rescore_k < 0 || opts->rescore_k > 8)
+    return fail(c, MP_EINVAL, "rescore_k must be in 0..8");
+  return MP_OK;
+}
+
+// The single-signal iteration driver: after init (state already copied to
+// c->h_st), enqueue chunks of iterations with `enqueue(e0, e1)`; the kernels
+// stop doing work once the device state says the run is over.  Two chunks
+// stay in flight: after enqueuing chunk k the host waits for the state copy
+// that follows chunk k-1.  With profiling on, the launches of every
+// prof_every-th iteration are timed (only those that performed an iteration
+// are counted).
+template <typename Enqueue>
+mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, Enqueue enqueue) {
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  long long issued = 0;
+  int chunk = 4;
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
+  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
+  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
+  mp::DevState* h_slot = nullptr;
+  if (hipHostMalloc(&h_slot, 2 * sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess) {
+    (void)hipEventDestroy(done_ev[0]);
+    (void)hipEventDestroy(done_ev[1]);
+    return fail(c, MP_ENOMEM, "pinned state slots");
+  }
+  long long slot_base[2] = {0, 0};
+  int slot_len[2] = {0, 0};
+  mp_status status = MP_OK;
+  auto account = [&](int k) {
+    if (!c->profiling) return;
+    const long long t_after = h_slot[k].t;
+    for (int j = 0; j < slot_len[k]; ++j) {
+      if (slot_base[k] + j >= t_after) break;
+      if ((slot_base[k] + j) % c->prof_every != 0) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
+                              c->ev[(k * kMaxChunk + j) * 2 + 1]) == hipSuccess) {
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+      }
+    }
+  };
+  bool finished = c->h_st->done != 0;
+  int next = 0;      // slot the next chunk goes to
+  int inflight = 0;  // chunks enqueued but not yet waited for
+  while (!finished && status == MP_OK) {
+    while (inflight < 2 && issued < T && status == MP_OK) {
+      const int k = next;
+      const int len = static_cast<int>(std::min<long long>(chunk, T - issued));
+      for (int j = 0; j < len; ++j) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->profiling && (issued + j) % c->prof_every == 0) {
+          e0 = c->ev[(k * kMaxChunk + j) * 2];
+          e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
+        }
+        hipError_t e = enqueue(e0, e1);
+        if (e != hipSuccess) {
+          status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+          break;
+        }
+      }
+      if (status != MP_OK) break;
+      slot_base[k] = issued;
+      slot_len[k] = len;
+      issued += len;
+      hipError_t e = hipMemcpyAsync(&h_slot[k], c->st, sizeof(mp::DevState),
+                                    hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(done_ev[k], s);
+      if (e != hipSuccess) {
+        status = fail(c, MP_EDEVICE, std::string("state copy: ") + hipGetErrorString(e));
+        break;
+      }
+      ++inflight;
+      next ^= 1;
+      chunk = std::min(chunk * 2, kMaxChunk);
+    }
+    if (status != MP_OK || inflight == 0) break;
+    const int old = inflight == 2 ? next : (next ^ 1);  // the older chunk in flight
+    hipError_t e = hipEventSynchronize(done_ev[old]);
+    if (e != hipSuccess) {
+      status = fail(c, MP_EDEVICE, std::string("sync: ") + hipGetErrorString(e));
+      break;
+    }
+    --inflight;
+    account(old);
+    if (h_slot[old].done) finished = true;
+  }
+  // drain the chunk still in flight (its launches return at once)
+  if (hipStreamSynchronize(s) != hipSuccess && status == MP_OK)
+    status = fail(c, MP_EDEVICE, "stream synchronize failed");
+  (void)hipHostFree(h_slot);
+  (void)hipEventDestroy(done_ev[0]);
+  (void)hipEventDestroy(done_ev[1]);
+  return status;
+}
+
+// Final state of a single-signal decode into `res`, with the internal stop
+// reasons mapped to errors.
+mp_status finish_result(mp_ctx* c, mp_result* res) {
+  const mp::DevState& d = *c->h_st;
+  if (d.reason == mp::kStopNonFinite) return fail(c, MP_ENONFINITE, "y holds NaN or Inf");
+  if (d.reason == mp::kStopInternal)
+    return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
+  if (res) {
+    res->iters = d.t;
+    res->yy = d.yy;
+    res->rr = d.rr;
+    res->stop_reason = d.reason;
+    res->reserved = 0;
+  }
+  return MP_OK;
 }
 
 }  // namespace
@@ -135,18 +292,13 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (n > kMaxN) return fail(nullptr, MP_EINVAL, "n exceeds 16384");
   if (m >= (int64_t{1} << 31)) return fail(nullptr, MP_EINVAL, "m must be < 2^31");
   if (flags & ~MP_SKIP_NORM_CHECK) return fail(nullptr, MP_EINVAL, "unknown flags");
+  if (storage == MP_F64)
+    return fail(nullptr, MP_EINVAL, "an FP64 dictionary is taken by mp_create_f64");
   if (storage != MP_F32 && storage != MP_BF16 && storage != MP_FP8_E4M3)
     return fail(nullptr, MP_EINVAL, "unknown storage type");
   int dev = 0;
-  int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
-    return fail(nullptr, MP_EDEVICE, "no HIP device");
-  HIP_TRY(nullptr, hipGetDevice(&dev));
   hipDeviceProp_t prop;
-  HIP_TRY(nullptr, hipGetDeviceProperties(&prop, dev));
-  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(nullptr, MP_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName +
-                                              ", this library is built for gfx950");
+  if (mp_status ds = open_device(dev, prop); ds != MP_OK) return ds;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   mp_ctx* c = new mp_ctx();
@@ -192,18 +344,10 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d_norm2);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("norms: ") + hipGetErrorString(e));
-  for (int64_t j = 0; j < m; ++j) {
-    if (!isfinite(norm2[j])) {
-      char buf[96];
-      snprintf(buf, sizeof buf, "column %lld holds NaN or Inf", static_cast<long long>(j));
-      return bail(MP_ENONFINITE, buf);
-    }
-    if (!(flags & MP_SKIP_NORM_CHECK) && fabs(sqrt(norm2[j]) - 1.0) > kNormTol) {
-      char buf[128];
-      snprintf(buf, sizeof buf, "column %lld has norm %.9g (must be 1 within 1e-4)",
-               static_cast<long long>(j), sqrt(norm2[j]));
-      return bail(MP_ENOTNORM, buf);
-    }
+  {
+    std::string msg;
+    const mp_status ns = check_norms(norm2, flags, msg);
+    if (ns != MP_OK) return bail(ns, msg);
   }
   // Reduced-precision copy the correlation pass streams (same padded layout).
   if (storage == MP_BF16 || storage == MP_FP8_E4M3) {
@@ -250,7 +394,10 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
   mp_ctx* c = const_cast<mp_ctx*>(ctx);
   if (c->ragged) return fail(c, MP_EINVAL, "not available for a ragged context");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->storage == MP_F32) {
+  if (c->storage == MP_F64) {
+    HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(double), c->psi64, c->ld * sizeof(double),
+                                c->n * sizeof(double), c->m, hipMemcpyDeviceToDevice, s));
+  } else if (c->storage == MP_F32) {
     HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(float), c->psi32, c->ld * sizeof(float),
                                 c->n * sizeof(float), c->m, hipMemcpyDeviceToDevice, s));
   } else {
@@ -270,13 +417,10 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   if (!ctx) return MP_EINVAL;
   ctx->err.clear();
   if (ctx->ragged) return fail(ctx, MP_EINVAL, "a ragged context is decoded with mp_solve_ragged");
+  if (ctx->storage == MP_F64)
+    return fail(ctx, MP_EINVAL, "an MP_F64 context is decoded with mp_solve_f64");
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
-  if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
-    return fail(ctx, MP_EINVAL, "eps must be finite and >= 0");
-  if (opts->max_iters < 0) return fail(ctx, MP_EINVAL, "max_iters must be >= 0");
-  if (opts->flags != 0) return fail(ctx, MP_EINVAL, "opts.flags must be 0");
-  if (opts->rescore_k < 0 || opts->rescore_k > 8)
-    return fail(ctx, MP_EINVAL, "rescore_k must be in 0..8");
+  if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
   mp_trace tr{};
   if (trace) {
     if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
@@ -286,117 +430,127 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_ctx* c = ctx;
   c->rescore_k = opts->rescore_k == 0 ? mp::kLpTopK : opts->rescore_k;
-  c->prof_ms = 0.0;
-  c->prof_launches = 0;
 
   HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, c->r_work, c->st, opts->eps,
                              static_cast<long long>(opts->max_iters), s));
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-
-  // Enqueue chunks of iterations; the kernels themselves stop doing work once
-  // the device state says the run is over.  Two chunks stay in flight: after
-  // enqueuing chunk k the host waits for the state copy that follows chunk k-1.
-  const long long T = opts->max_iters;
-  long long issued = 0;
-  int chunk = 4;
-  hipEvent_t done_ev[2] = {nullptr, nullptr};
-  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
-  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
-  mp::DevState* h_slot = nullptr;
-  if (hipHostMalloc(&h_slot, 2 * sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess) {
-    (void)hipEventDestroy(done_ev[0]);
-    (void)hipEventDestroy(done_ev[1]);
-    return fail(c, MP_ENOMEM, "pinned state slots");
-  }
-  long long slot_base[2] = {0, 0};
-  int slot_len[2] = {0, 0};
-  mp_status status = MP_OK;
-  auto account = [&](int k) {
-    // after chunk slot k has completed: add the kernel time of the launches
-    // that did an iteration (iteration index < t after the chunk)
-    if (!c->profiling) return;
-    const long long t_after = h_slot[k].t;
-    for (int j = 0; j < slot_len[k]; ++j) {
-      if (slot_base[k] + j >= t_after) break;
-      if ((slot_base[k] + j) % c->prof_every != 0) continue;
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
-                              c->ev[(k * kMaxChunk + j) * 2 + 1]) == hipSuccess) {
-        c->prof_ms += ms;
-        c->prof_launches += 1;
-      }
-    }
-  };
-  bool finished = c->h_st->done != 0;
-  int next = 0;      // slot the next chunk goes to
-  int inflight = 0;  // chunks enqueued but not yet waited for
-  while (!finished && status == MP_OK) {
-    while (inflight < 2 && issued < T && status == MP_OK) {
-      const int k = next;
-      const int len = static_cast<int>(std::min<long long>(chunk, T - issued));
-      for (int j = 0; j < len; ++j) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->profiling && (issued + j) % c->prof_every == 0) {
-          e0 = c->ev[(k * kMaxChunk + j) * 2];
-          e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
-        }
-        hipError_t e = enqueue_iteration(c, x, tr, s, e0, e1);
-        if (e != hipSuccess) {
-          status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
-          break;
-        }
-      }
-      if (status != MP_OK) break;
-      slot_base[k] = issued;
-      slot_len[k] = len;
-      issued += len;
-      hipError_t e = hipMemcpyAsync(&h_slot[k], c->st, sizeof(mp::DevState),
-                                    hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipEventRecord(done_ev[k], s);
-      if (e != hipSuccess) {
-        status = fail(c, MP_EDEVICE, std::string("state copy: ") + hipGetErrorString(e));
-        break;
-      }
-      ++inflight;
-      next ^= 1;
-      chunk = std::min(chunk * 2, kMaxChunk);
-    }
-    if (status != MP_OK || inflight == 0) break;
-    const int old = inflight == 2 ? next : (next ^ 1);  // the older chunk in flight
-    hipError_t e = hipEventSynchronize(done_ev[old]);
-    if (e != hipSuccess) {
-      status = fail(c, MP_EDEVICE, std::string("sync: ") + hipGetErrorString(e));
-      break;
-    }
-    --inflight;
-    account(old);
-    if (h_slot[old].done) finished = true;
-  }
-  // drain the chunk still in flight (its launches return at once)
-  if (hipStreamSynchronize(s) != hipSuccess && status == MP_OK)
-    status = fail(c, MP_EDEVICE, "stream synchronize failed");
-  (void)hipHostFree(h_slot);
-  (void)hipEventDestroy(done_ev[0]);
-  (void)hipEventDestroy(done_ev[1]);
-  if (status != MP_OK) return status;
+  const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    return enqueue_iteration(c, x, tr, s, e0, e1);
+  });
+  if (st != MP_OK) return st;
 
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   if (r)
     HIP_TRY(c, hipMemcpyAsync(r, c->r_work, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  const mp::DevState& d = *c->h_st;
-  if (d.reason == mp::kStopNonFinite) return fail(c, MP_ENONFINITE, "y holds NaN or Inf");
-  if (d.reason == mp::kStopInternal)
-    return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
-  if (res) {
-    res->iters = d.t;
-    res->yy = d.yy;
-    res->rr = d.rr;
-    res->stop_reason = d.reason;
-    res->reserved = 0;
+  return finish_result(c, res);
+}
+
+mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, int64_t ld,
+                        uint32_t flags, void* stream) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, MP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!psi) return fail(nullptr, MP_EINVAL, "psi is NULL");
+  if (n < 1 || m < 1) return fail(nullptr, MP_EINVAL, "n and m must be >= 1");
+  if (ld < n) return fail(nullptr, MP_EINVAL, "ld must be >= n");
+  if (n > kMaxN) return fail(nullptr, MP_EINVAL, "n exceeds 16384");
+  if (m >= (int64_t{1} << 31)) return fail(nullptr, MP_EINVAL, "m must be < 2^31");
+  if (flags & ~MP_SKIP_NORM_CHECK) return fail(nullptr, MP_EINVAL, "unknown flags");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (mp_status ds = open_device(dev, prop); ds != MP_OK) return ds;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  mp_ctx* c = new mp_ctx();
+  c->device = dev;
+  c->num_cus = prop.multiProcessorCount;
+  c->n = n;
+  c->m = m;
+  c->ld = round_up(n, kLdAlign);
+  c->storage = MP_F64;
+  c->geom = mp::corr_f32_geometry(m, c->num_cus);  // same workgroup layout as FP32
+
+  auto bail = [&](mp_status st, const std::string& msg) {
+    free_ctx(c);
+    return fail(nullptr, st, msg);
+  };
+  const size_t psi_bytes = static_cast<size_t>(c->ld) * static_cast<size_t>(m) * sizeof(double);
+  if (hipMalloc(&c->psi64, psi_bytes) != hipSuccess) return bail(MP_ENOMEM, "dictionary copy");
+  if (hipMalloc(&c->r64_work, c->ld * sizeof(double)) != hipSuccess) return bail(MP_ENOMEM, "r");
+  if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
+  if (c->geom.grid * 2 > 2 * 1024)
+    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
+  const size_t nkeys = static_cast<size_t>(c->geom.grid) * 2;  // two words per workgroup
+  if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
+    return bail(MP_ENOMEM, "partials");
+  if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
+    return bail(MP_ENOMEM, "pinned state");
+
+  hipError_t e = hipMemsetAsync(c->psi64, 0, psi_bytes, s);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(c->psi64, c->ld * sizeof(double), psi, ld * sizeof(double),
+                         n * sizeof(double), m, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->r64_work, 0, c->ld * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
+
+  double* d_norm2 = nullptr;
+  if (hipMalloc(&d_norm2, sizeof(double) * m) != hipSuccess) return bail(MP_ENOMEM, "norms");
+  std::vector<double> norm2(static_cast<size_t>(m));
+  e = mp::launch_norms_f64(c->psi64, c->ld, n, m, d_norm2, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(norm2.data(), d_norm2, sizeof(double) * m, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_norm2);
+  if (e != hipSuccess) return bail(MP_EDEVICE, std::string("norms: ") + hipGetErrorString(e));
+  {
+    std::string msg;
+    const mp_status ns = check_norms(norm2, flags, msg);
+    if (ns != MP_OK) return bail(ns, msg);
   }
+  *out = c;
   return MP_OK;
+}
+
+mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const mp_opts* opts,
+                       mp_result* res, const mp_trace_f64* trace, void* stream) {
+  if (!ctx) return MP_EINVAL;
+  ctx->err.clear();
+  if (ctx->ragged || ctx->storage != MP_F64)
+    return fail(ctx, MP_EINVAL, "mp_solve_f64 needs a context from mp_create_f64");
+  if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
+  if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
+  mp_trace_f64 tr{};
+  if (trace) {
+    if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
+    tr = *trace;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mp_ctx* c = ctx;
+
+  HIP_TRY(c, mp::launch_init_f64(y, c->n, c->ld, x, c->m, c->r64_work, c->st, opts->eps,
+                                 static_cast<long long>(opts->max_iters), s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    hipError_t e;
+    if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+    e = mp::launch_mp_step_f64(c->psi64, c->ld, c->n, c->m, c->r64_work, c->geom, c->partials,
+                               x, c->st, tr, s);
+    if (e != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
+    return hipSuccess;
+  });
+  if (st != MP_OK) return st;
+
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  if (r)
+    HIP_TRY(c, hipMemcpyAsync(r, c->r64_work, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return finish_result(c, res);
 }
 
 
@@ -448,6 +602,8 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
   ctx->err.clear();
   mp_ctx* c = ctx;
   if (c->ragged) return fail(c, MP_EINVAL, "a ragged context is decoded with mp_solve_ragged");
+  if (c->storage == MP_F64)
+    return fail(c, MP_EINVAL, "batched decoding needs an FP32, BF16 or FP8 context");
   if (B < 0) return fail(c, MP_EINVAL, "B must be >= 0");
   if (B == 0) return MP_OK;
   if (B >= (int64_t{1} << 31) / 2) return fail(c, MP_EINVAL, "B too large");

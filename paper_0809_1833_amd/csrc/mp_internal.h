@@ -71,6 +71,16 @@ hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m
                               const CorrGeom& g, uint64_t* keys, float* x, DevState* st,
                               mp_trace tr, hipStream_t s);
 
+// ---- kernels of the FP64 single-signal path (k_f64.hip) ---------------------
+hipError_t launch_norms_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* norm2,
+                            hipStream_t s);
+hipError_t launch_init_f64(const double* y, int64_t n, int64_t ld, double* x, int64_t m,
+                           double* r, DevState* st, double eps, long long max_iters,
+                           hipStream_t s);
+hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* r,
+                              const CorrGeom& g, uint64_t* keys, double* x, DevState* st,
+                              mp_trace_f64 tr, hipStream_t s);
+
 // ---- batched decode against one dictionary (k_batched.hip) ------------------
 // Per-signal state; written only by the workgroup handling that signal.
 struct BSlot {
@@ -144,6 +154,8 @@ struct mp_ctx {
   int64_t n = 0, m = 0, ld = 0;  // ld: padded leading dimension of the owned copies
   mp_dtype storage = MP_F32;
   float* psi32 = nullptr;        // FP32 master, ld x m, zero padded rows n..ld-1
+  double* psi64 = nullptr;       // MP_F64 storage: the FP64 dictionary (same layout)
+  double* r64_work = nullptr;    // MP_F64 storage: ld doubles, rows n..ld-1 stay zero
   void* psiq = nullptr;          // BF16 / FP8 copy (same layout), if any
   float* scales = nullptr;       // FP8 per-column scales
   // per-decode work buffers

@@ -22,11 +22,11 @@ LIB_PATH = os.path.join(HERE, "libmp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mp.h")
 
 MP_OK, MP_EINVAL, MP_ENOTNORM, MP_ENONFINITE, MP_ENOMEM, MP_EDEVICE, MP_EUNSUPPORTED = range(7)
-MP_F32, MP_BF16, MP_FP8_E4M3 = 0, 1, 2
+MP_F32, MP_BF16, MP_FP8_E4M3, MP_F64 = 0, 1, 2, 3
 STOP_CONVERGED, STOP_MAX_ITERS, STOP_STALLED, STOP_ZERO_INPUT = 0, 1, 2, 3
 STOP_NAMES = {0: "converged", 1: "max_iters", 2: "stalled", 3: "zero_input"}
 MP_SKIP_NORM_CHECK = 0x1
-DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3}
+DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3, "f64": MP_F64}
 
 
 class Opts(ctypes.Structure):
@@ -40,6 +40,11 @@ class Result(ctypes.Structure):
 
 
 class Trace(ctypes.Structure):
+    _fields_ = [("idx", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("rr", ctypes.c_void_p),
+                ("cap", ctypes.c_int64)]
+
+
+class TraceF64(ctypes.Structure):
     _fields_ = [("idx", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("rr", ctypes.c_void_p),
                 ("cap", ctypes.c_int64)]
 
@@ -102,6 +107,11 @@ def _load():
     lib.mp_set_profiling.argtypes = [p, ctypes.c_int]
     lib.mp_kernel_time.restype = ctypes.c_int
     lib.mp_kernel_time.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.mp_create_f64.restype = ctypes.c_int
+    lib.mp_create_f64.argtypes = [ctypes.POINTER(ctypes.c_void_p), p, i64, i64, i64, u32, p]
+    lib.mp_solve_f64.restype = ctypes.c_int
+    lib.mp_solve_f64.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
+                                 ctypes.POINTER(TraceF64), p]
     _lib = lib
     return lib
 
@@ -156,6 +166,23 @@ def mp_solve(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
     st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
                           ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve", ctx)
+    return res
+
+
+def mp_create_f64(psi_ptr: int, n: int, m: int, ld: int, flags: int = 0,
+                  stream: Optional[int] = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = _load().mp_create_f64(ctypes.byref(h), psi_ptr, n, m, ld, flags, stream)
+    _check(st, "mp_create_f64", None)
+    return h
+
+
+def mp_solve_f64(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
+                 trace: Optional[TraceF64] = None, stream: Optional[int] = None) -> Result:
+    res = Result()
+    st = _load().mp_solve_f64(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
+                              ctypes.byref(trace) if trace is not None else None, stream)
+    _check(st, "mp_solve_f64", ctx)
     return res
 
 
@@ -238,9 +265,9 @@ def mp_kernel_time(ctx):
 
 # ---- torch-facing convenience ------------------------------------------------
 
-def _check_psi(psi: torch.Tensor):
-    if not psi.is_cuda or psi.dtype != torch.float32 or psi.dim() != 2:
-        raise ValueError("psi must be a 2-D float32 CUDA tensor of shape (N, M)")
+def _check_psi(psi: torch.Tensor, dtype=torch.float32):
+    if not psi.is_cuda or psi.dtype != dtype or psi.dim() != 2:
+        raise ValueError(f"psi must be a 2-D {dtype} CUDA tensor of shape (N, M)")
     n, m = psi.shape
     if psi.stride(0) != 1 and n > 1:
         raise ValueError("psi must be column-major: stride(0) == 1")
@@ -249,19 +276,27 @@ def _check_psi(psi: torch.Tensor):
 
 
 class Decoder:
-    """A dictionary prepared on the GPU (``mp_create``) and decodes against it.
+    """A dictionary prepared on the GPU (``mp_create`` / ``mp_create_f64``) and
+    decodes against it.
 
-    ``psi``: (N, M) float32 CUDA tensor, column-major (``stride(0) == 1``).
-    ``storage``: ``"f32"``, ``"bf16"`` or ``"fp8"``.
+    ``psi``: (N, M) CUDA tensor, column-major (``stride(0) == 1``): float32
+    for ``storage`` ``"f32"``, ``"bf16"`` or ``"fp8"``; float64 for ``"f64"``
+    (the FP64 decode: y, x~ and r are then float64 as well).
     """
 
     def __init__(self, psi: torch.Tensor, storage: str = "f32", check_norms: bool = True,
                  stream=None):
-        n, m, ld = _check_psi(psi)
+        if storage not in DTYPES:
+            raise ValueError(f"unknown storage {storage!r}")
+        self.dtype = torch.float64 if storage == "f64" else torch.float32
+        n, m, ld = _check_psi(psi, self.dtype)
         self.n, self.m, self.storage = n, m, storage
         flags = 0 if check_norms else MP_SKIP_NORM_CHECK
-        self._ctx = mp_create(psi.data_ptr(), n, m, ld, DTYPES[storage], flags,
-                              _stream_ptr(stream))
+        if storage == "f64":
+            self._ctx = mp_create_f64(psi.data_ptr(), n, m, ld, flags, _stream_ptr(stream))
+        else:
+            self._ctx = mp_create(psi.data_ptr(), n, m, ld, DTYPES[storage], flags,
+                                  _stream_ptr(stream))
 
     def close(self):
         if getattr(self, "_ctx", None) is not None:
@@ -288,24 +323,27 @@ class Decoder:
               r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
               stream=None):
         """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, trace...)."""
-        if not y.is_cuda or y.dtype != torch.float32 or y.numel() != self.n:
-            raise ValueError("y must be a float32 CUDA tensor of N elements")
+        dt = self.dtype
+        if not y.is_cuda or y.dtype != dt or y.numel() != self.n:
+            raise ValueError(f"y must be a {dt} CUDA tensor of N elements")
         y = y.contiguous()
         dev = y.device
         if x is None:
-            x = torch.empty(self.m, dtype=torch.float32, device=dev)
+            x = torch.empty(self.m, dtype=dt, device=dev)
         if r is None:
-            r = torch.empty(self.n, dtype=torch.float32, device=dev)
+            r = torch.empty(self.n, dtype=dt, device=dev)
         tr = None
         tidx = tcoef = trr = None
         if trace_cap > 0:
             tidx = torch.full((trace_cap,), -1, dtype=torch.int32, device=dev)
-            tcoef = torch.zeros(trace_cap, dtype=torch.float32, device=dev)
+            tcoef = torch.zeros(trace_cap, dtype=dt, device=dev)
             trr = torch.zeros(trace_cap, dtype=torch.float64, device=dev)
-            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+            tr = (TraceF64 if self.storage == "f64" else Trace)(
+                tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
         opts = Opts(float(eps), int(max_iters), int(rescore_k), 0)
-        res = mp_solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
-                       _stream_ptr(stream))
+        solve = mp_solve_f64 if self.storage == "f64" else mp_solve
+        res = solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
+                    _stream_ptr(stream))
         out = dict(x=x, r=r, iters=res.iters, yy=res.yy, rr=res.rr,
                    stop=STOP_NAMES.get(res.stop_reason, res.stop_reason))
         if tr is not None:
@@ -359,7 +397,8 @@ class Decoder:
     def storage_copy(self, stream=None):
         """The dictionary copy the correlation pass streams, unpadded:
         (codes tensor (N, M) column-major view, scales or None)."""
-        dt = {"f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8}[self.storage]
+        dt = {"f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8,
+              "f64": torch.float64}[self.storage]
         codes = torch.empty((self.m, self.n), dtype=dt, device="cuda")
         scales = torch.empty(self.m, dtype=torch.float32, device="cuda") \
             if self.storage == "fp8" else None

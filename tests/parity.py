@@ -32,12 +32,14 @@ import numpy as np
 import oracle
 
 U32 = 2.0 ** -24
+U64 = 2.0 ** -53
 
 
-def fp32_dot_bound(n: int, rnorm: float) -> float:
-    """Bound on |fl32(<r, psi>) - <r, psi>| for a unit column: a lane-sequential
-    sum of about N/64 terms followed by a 6-level butterfly, plus FMA rounding."""
-    return (n / 64.0 + 8.0) * U32 * rnorm * 1.001
+def fp32_dot_bound(n: int, rnorm: float, unit: float = U32) -> float:
+    """Bound on |fl(<r, psi>) - <r, psi>| for a unit column in the working
+    precision with unit roundoff ``unit``: a lane-sequential sum of about N/64
+    terms followed by a 6-level lane sum, plus FMA rounding."""
+    return (n / 64.0 + 8.0) * unit * rnorm * 1.001
 
 
 @dataclass
@@ -55,18 +57,23 @@ class ParityReport:
 
 def run_parity(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
                gpu_solve: Callable, tol: float = 1e-5, tol_sel: float = 1e-5,
-               samples_after: int = 4, oracle_cap=None, ora=None) -> ParityReport:
+               samples_after: int = 4, oracle_cap=None, ora=None, unit: float = U32,
+               solver=None) -> ParityReport:
     """``gpu_solve(eps, max_iters, trace_cap)`` -> dict of numpy arrays with keys
     x, r, iters, stop, idx, coef, rr_trace (the GPU decoder on psi, y).
 
     ``oracle_cap``: run the oracle for at most that many steps (large sizes);
     the prefix comparison then covers those steps and the validity checks
-    sample the rest of the GPU run."""
+    sample the rest of the GPU run.  ``unit``: unit roundoff of the GPU's
+    working precision (FP32 by default, ``U64`` for the FP64 decode);
+    ``solver``: the oracle entry for these inputs (``oracle.solve`` by
+    default, ``oracle.solve64`` for FP64 y)."""
+    solver = oracle.solve if solver is None else solver
     n = psi.shape[0]
     ynorm = float(np.linalg.norm(y.astype(np.float64)))
     cap = max_iters if oracle_cap is None else min(max_iters, int(oracle_cap))
     if ora is None:
-        ora = oracle.solve(psi, y, eps, cap)
+        ora = solver(psi, y, eps, cap)
     capped = cap < max_iters and ora.iters == cap
     g = gpu_solve(eps, max_iters, max_iters)
     L = min(len(g["idx"]), len(ora.idx))
@@ -81,7 +88,7 @@ def run_parity(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
         assert oracle.REASONS[ora.reason] == g["stop"], (ora.reason, g["stop"])
     else:
         gp = gpu_solve(0.0, t_star, 0)
-        op = oracle.solve(psi, y, 0.0, t_star, trace=False)
+        op = solver(psi, y, 0.0, t_star, trace=False)
         gx, gr, ox, orr = gp["x"], gp["r"], op.x, op.r
     xn = max(float(np.linalg.norm(ox)), 1e-300)
     rep.x_err = float(np.linalg.norm(gx.astype(np.float64) - ox)) / xn
@@ -96,7 +103,7 @@ def run_parity(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
         elif t_star < L:
             dr = float(np.linalg.norm(gr.astype(np.float64) - orr))
             rn = float(np.linalg.norm(orr))
-            allowed = tol_sel * rn + 2.0 * dr + 2.0 * fp32_dot_bound(n, rn)
+            allowed = tol_sel * rn + 2.0 * dr + 2.0 * fp32_dot_bound(n, rn, unit)
             gap = float(ora.gap[t_star])
             rep.diverged_legit = gap <= allowed
             assert rep.diverged_legit, (
@@ -114,12 +121,13 @@ def run_parity(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
             r_s = gs["r"].astype(np.float64)
             c = oracle.correlate(psi, r_s)
             rn = float(np.linalg.norm(r_s))
-            e32 = fp32_dot_bound(n, rn)
+            e32 = fp32_dot_bound(n, rn, unit)
             j = int(g["idx"][s])
             best = float(np.max(np.abs(c)))
             assert abs(c[j]) >= best - (tol_sel * rn + 2 * e32), (
                 f"step {s}: GPU atom {j} |c|={abs(c[j]):.6g} vs max {best:.6g}")
-            assert abs(float(g["coef"][s]) - c[j]) <= e32 + 1e-6 * abs(c[j]), (
+            coef_rel = 1e-6 if unit == U32 else 16 * unit  # FP32: the stored coefficient's rounding
+            assert abs(float(g["coef"][s]) - c[j]) <= e32 + coef_rel * abs(c[j]), (
                 f"step {s}: coefficient {g['coef'][s]} vs FP64 {c[j]}")
             rep.checked_after.append(int(s))
 
@@ -129,7 +137,7 @@ def run_parity(psi: np.ndarray, y: np.ndarray, eps: float, max_iters: int,
         assert rr <= (eps * ynorm) ** 2 * (1 + 1e-6) + 1e-30
     defect = y.astype(np.float64) - np.asarray(psi, dtype=np.float64) @ g["x"].astype(
         np.float64) - g["r"].astype(np.float64)
-    assert np.linalg.norm(defect) <= max(tol, 4 * U32 * np.sqrt(max(g["iters"], 1))) * max(
+    assert np.linalg.norm(defect) <= max(tol, 4 * unit * np.sqrt(max(g["iters"], 1))) * max(
         ynorm, 1e-300) + 1e-30, "y != Psi x~ + r"
     if (not full and not capped and g["stop"] == "converged"
             and oracle.REASONS[ora.reason] == "converged"):

@@ -67,3 +67,31 @@ def test_create_without_device_reports_edevice():
     h = ctypes.c_void_p()
     st = mp.library().mp_create(ctypes.byref(h), 0x1000, 4, 4, 4, 0, 0, None)
     assert st == mp.MP_EDEVICE
+
+
+@pytest.mark.parametrize("kw,detail", [
+    (dict(psi=None), "psi is NULL"),
+    (dict(n=0), "n and m"),
+    (dict(ld=3), "ld must be"),
+    (dict(n=16385, ld=16385), "16384"),
+    (dict(m=2 ** 31), "2^31"),
+    (dict(flags=0x10), "flags"),
+])
+def test_create_f64_rejects_bad_arguments(kw, detail):
+    args = dict(psi=0x1000, n=4, m=4, ld=4, flags=0)
+    args.update(kw)
+    h = ctypes.c_void_p(123)
+    st = mp.library().mp_create_f64(ctypes.byref(h), args["psi"], args["n"], args["m"],
+                                    args["ld"], args["flags"], None)
+    assert st == mp.MP_EINVAL
+    assert h.value is None
+    assert detail in mp.mp_last_error(None)
+
+
+def test_f64_storage_goes_through_its_own_entry_point():
+    h = ctypes.c_void_p(123)
+    st = mp.library().mp_create(ctypes.byref(h), 0x1000, 4, 4, 4, mp.MP_F64, 0, None)
+    assert st == mp.MP_EINVAL and "mp_create_f64" in mp.mp_last_error(None)
+    opts = mp.Opts(1e-5, 10, 0, 0)
+    assert mp.library().mp_solve_f64(None, 1, 1, None, ctypes.byref(opts), None, None,
+                                     None) == mp.MP_EINVAL

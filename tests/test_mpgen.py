@@ -66,3 +66,16 @@ def test_rational_columns_exact_unit_norm():
     cols = mpgen.rational_unit_dictionary(rng, 5, 7)
     for c in cols:
         assert sum(v * v for v in c) == 1
+
+
+def test_fp64_problem_is_the_fp32_problem_unrounded():
+    p32 = mpgen.make_problem("c0", 3)
+    p64 = mpgen.make_problem("c0", 3, precision="f64")
+    assert p64.psi.dtype == np.float64 and p64.psi.flags.f_contiguous
+    assert np.array_equal(p64.psi.astype(np.float32), p32.psi)
+    assert np.array_equal(p64.support, p32.support)
+    assert np.array_equal(p64.x.astype(np.float32), p32.x)
+    assert np.abs(np.linalg.norm(p64.psi, axis=0) - 1.0).max() < 1e-14
+    np.testing.assert_allclose(p64.y, p64.psi[:, p64.support] @ p64.x[p64.support],
+                               rtol=0, atol=1e-13)
+    assert p64.y.dtype == np.float64
