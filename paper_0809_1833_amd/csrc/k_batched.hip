@@ -1,5 +1,12 @@
 // Batched Matching Pursuit: many signals against one shared dictionary.
 //
+// Layouts read by the product: the dictionary's BF16 copy in tiles of 16
+// atoms x 32 K elements, each tile 1 KB contiguous (atom block, then K
+// chunk, then the 16 atoms' 32 elements), so one MFMA operand load reads
+// 1 KB in one piece; the residuals' BF16 copy with leading dimension ldq =
+// ld + 32 elements, which spreads the 16 signal rows of one operand load
+// over the memory channels (a stride of exactly 4 KB sends them all to one).
+//
 // One round performs one MP iteration (Section 3, eqs. 9-12) for every
 // signal still active.  The correlations of all active signals with all
 // atoms are one matrix product C = Psi^T R (the residuals as columns), run
@@ -29,14 +36,14 @@ constexpr int kBTopK = kTopK;
 // ||y||^2 in FP64, the loop's pre-test.  One workgroup per slot.
 __global__ __launch_bounds__(kBThreads) void k_binit(
     const float* __restrict__ Y, int64_t ldy, int64_t n, int64_t ld, float* __restrict__ X,
-    int64_t ldx, int64_t m, float* __restrict__ R32, uint16_t* __restrict__ Rq,
+    int64_t ldx, int64_t m, float* __restrict__ R32, uint16_t* __restrict__ Rq, int64_t ldq,
     BSlot* __restrict__ slots, const long long* __restrict__ tcap, long long tcap_all,
     double eps) {
   __shared__ double red[kBThreads / kWave];
   const int64_t b = blockIdx.x;
   const float* y = Y + b * ldy;
   float* r = R32 + b * ld;
-  uint16_t* rq = Rq + b * ld;
+  uint16_t* rq = Rq + b * ldq;
   float* x = X + b * ldx;
   for (int64_t j = threadIdx.x; j < m; j += kBThreads) x[j] = 0.0f;
   double s = 0.0;
@@ -70,6 +77,21 @@ __global__ __launch_bounds__(kBThreads) void k_binit(
       d.reason = MP_STOP_MAX_ITERS;
     }
     slots[b] = d;
+  }
+}
+
+// The BF16 dictionary in product tiles: element (atom a, row k) goes to
+// tile (a / 16, k / 32), position (a % 16) * 32 + k % 32; atoms past m (up to
+// the next multiple of 16) are zero.  One 256-thread workgroup per tile row
+// block of 16 atoms, looping over the K chunks.
+__global__ __launch_bounds__(256) void k_tile_bf16(const float* __restrict__ psi, int64_t ld,
+                                                   int64_t m, uint16_t* __restrict__ out) {
+  const int64_t blk = blockIdx.x;
+  const int64_t nchunks = ld / 32;
+  for (int64_t e = threadIdx.x; e < nchunks * 512; e += 256) {
+    const int64_t chunk = e / 512, within = e % 512;
+    const int64_t a = blk * 16 + within / 32, k = chunk * 32 + within % 32;
+    out[blk * 16 * ld + e] = a < m ? bf16_rne(psi[a * ld + k]) : uint16_t{0};
   }
 }
 
@@ -147,9 +169,10 @@ constexpr int kBCorrTileB = 64;                      // signals per workgroup
 constexpr int kBPre = 4;                             // K-steps in flight per wave
 
 template <int TI>
-__global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr(const uint16_t* __restrict__ psib,
+__global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr(const uint16_t* __restrict__ psit,
                                                          int64_t ld, int64_t m,
                                                          const uint16_t* __restrict__ Rq,
+                                                         int64_t ldq,
                                                          const int* __restrict__ act0,
                                                          const int* __restrict__ act1,
                                                          const BState* __restrict__ bs,
@@ -171,14 +194,14 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
   for (int ti = 0; ti < TI; ++ti) {
     int64_t row = m0 + 16 * ti + (lane % 16);
     if (row > m - 1) row = m - 1;
-    arow[ti] = psib + row * ld + koff;
+    arow[ti] = psit + (row / 16) * 16 * ld + (row % 16) * 32 + koff;  // its tile row
   }
   const uint16_t* bcol[4];
 #pragma unroll
   for (int tj = 0; tj < 4; ++tj) {
     int j = j0 + 16 * tj + (lane % 16);
     if (j > nact - 1) j = nact - 1;
-    bcol[tj] = Rq + static_cast<int64_t>(act[j]) * ld + koff;
+    bcol[tj] = Rq + static_cast<int64_t>(act[j]) * ldq + koff;
   }
   v4f acc[TI][4];
 #pragma unroll
@@ -193,7 +216,8 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
   auto load_step = [&](int slot, int q) {
     const int64_t k = static_cast<int64_t>(wave + q * kBCorrWaves) * 32;
 #pragma unroll
-    for (int ti = 0; ti < TI; ++ti) ra[slot][ti] = *reinterpret_cast<const v8bf*>(arow[ti] + k);
+    for (int ti = 0; ti < TI; ++ti)
+      ra[slot][ti] = *reinterpret_cast<const v8bf*>(arow[ti] + k * 16);  // K chunk k / 32
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) rb[slot][tj] = *reinterpret_cast<const v8bf*>(bcol[tj] + k);
   };
@@ -320,7 +344,8 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
 // compacts the list for the next round.
 __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m,
-    float* __restrict__ R32, uint16_t* __restrict__ Rq, float* __restrict__ X, int64_t ldx,
+    float* __restrict__ R32, uint16_t* __restrict__ Rq, int64_t ldq, float* __restrict__ X,
+    int64_t ldx,
     BSlot* __restrict__ slots, int* __restrict__ act0, int* __restrict__ act1,
     BState* __restrict__ bs, const uint64_t* __restrict__ partials, int mtiles,
     uint64_t* __restrict__ alive, int rescore_k, mp_trace tr) {
@@ -403,7 +428,7 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     // BF16 copy, four elements per thread and step
     const v4f* colp = reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld);
     v4f* r4 = reinterpret_cast<v4f*>(r);
-    uint2* rq4 = reinterpret_cast<uint2*>(Rq + static_cast<int64_t>(b) * ld);
+    uint2* rq4 = reinterpret_cast<uint2*>(Rq + static_cast<int64_t>(b) * ldq);
     double s = 0.0;
     for (int i = threadIdx.x; i < ld4; i += kBSelThreads) {
       const v4f a = colp[i], rv = r_lds[i];
@@ -466,11 +491,17 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
 
 // ---------------------------------------------------------------------------
 
+hipError_t launch_tile_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* out,
+                            hipStream_t s) {
+  k_tile_bf16<<<dim3(static_cast<unsigned>((m + 15) / 16)), dim3(256), 0, s>>>(psi, ld, m, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, float* X,
-                        int64_t ldx, int64_t m, float* R32, uint16_t* Rq, BSlot* slots,
+                        int64_t ldx, int64_t m, float* R32, uint16_t* Rq, int64_t ldq, BSlot* slots,
                         const long long* tcap, long long tcap_all, double eps, int nslots,
                         int* act0, int* act1, BState* bs, hipStream_t s) {
-  k_binit<<<dim3(nslots), dim3(kBThreads), 0, s>>>(Y, ldy, n, ld, X, ldx, m, R32, Rq, slots,
+  k_binit<<<dim3(nslots), dim3(kBThreads), 0, s>>>(Y, ldy, n, ld, X, ldx, m, R32, Rq, ldq, slots,
                                                    tcap, tcap_all, eps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -483,8 +514,8 @@ hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, floa
 int bcorr_tile_m(int nact_hint) { return nact_hint > 96 ? 64 : 32; }
 int bcorr_mtiles(int64_t m, int tile_m) { return static_cast<int>((m + tile_m - 1) / tile_m); }
 
-hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, int64_t n,
-                         int64_t m, float* R32, uint16_t* Rq, float* X, int64_t ldx,
+hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, int64_t n,
+                         int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
                          BSlot* slots, int* act0, int* act1, BState* bs, uint64_t* partials,
                          uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
                          hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -494,10 +525,10 @@ hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, i
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
   if (tile_m == 64)
-    k_bcorr<4><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psib, ld, m, Rq, act0, act1,
+    k_bcorr<4><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act0, act1,
                                                                     bs, partials, mtiles);
   else
-    k_bcorr<2><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psib, ld, m, Rq, act0, act1,
+    k_bcorr<2><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act0, act1,
                                                                     bs, partials, mtiles);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
@@ -509,7 +540,7 @@ hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, i
     if (e != hipSuccess) return e;
     big_lds = true;
   }
-  k_bselect<<<dim3(nact_hint), dim3(kBSelThreads), lds, s>>>(psi32, ld, n, m, R32, Rq, X, ldx,
+  k_bselect<<<dim3(nact_hint), dim3(kBSelThreads), lds, s>>>(psi32, ld, n, m, R32, Rq, ldq, X, ldx,
                                                              slots, act0, act1, bs, partials,
                                                              mtiles, alive, rescore_k, tr);
   return hipGetLastError();

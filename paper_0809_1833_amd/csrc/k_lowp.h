@@ -75,6 +75,40 @@ __device__ inline float dot_column_lp(const v4u* __restrict__ p, const v4f* __re
   return wave_sum(acc);
 }
 
+// CC columns at once by one wave (CC x U loads in flight per lane); each
+// column's chunks are accumulated in the same order as dot_column_lp, so the
+// results are identical.
+template <int S, int U, int CC>
+__device__ inline void lp_block_cols(const v4u* const (&p)[CC], const v4f* __restrict__ r_lds,
+                                     int& i, float (&acc)[CC]) {
+  constexpr int R = 16 / S / 4;
+  v4u a[CC][U];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int c = 0; c < CC; ++c) a[c][u] = __builtin_nontemporal_load(p[c] + i + kWave * u);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int c = 0; c < CC; ++c) lp_fma<S>(a[c][u], r_lds + (i + kWave * u) * R, acc[c]);
+  i += kWave * U;
+}
+
+template <int S, int CC>
+__device__ inline void dot_columns_lp(const v4u* const (&p)[CC], const v4f* __restrict__ r_lds,
+                                      int nq, int lane, float (&out)[CC]) {
+  float acc[CC];
+#pragma unroll
+  for (int c = 0; c < CC; ++c) acc[c] = 0.0f;
+  int i = lane;
+  while (i + kWave * 7 < nq) lp_block_cols<S, 8, CC>(p, r_lds, i, acc);
+  if (i + kWave * 3 < nq) lp_block_cols<S, 4, CC>(p, r_lds, i, acc);
+  if (i + kWave * 1 < nq) lp_block_cols<S, 2, CC>(p, r_lds, i, acc);
+  if (i < nq) lp_block_cols<S, 1, CC>(p, r_lds, i, acc);
+#pragma unroll
+  for (int c = 0; c < CC; ++c) out[c] = wave_sum(acc[c]);
+}
+
 // ---------------------------------------------------------------------------
 // Top-8 lists of packed keys (larger key = larger |c|, then smaller index;
 // 0 = empty).

@@ -24,6 +24,10 @@ namespace mp {
 
 constexpr int kLpThreads = 1024;
 constexpr int kLpWaves = kLpThreads / kWave;
+// Columns one wave streams at once: an FP8 column (N bytes) is short enough
+// that two in flight together keep more of HBM busy.
+template <int S>
+constexpr int kLpColsPerWave = S == 1 ? 2 : 1;
 
 // ---------------------------------------------------------------------------
 // Quantisers
@@ -103,7 +107,8 @@ hipError_t launch_quant_fp8(const float* psi, int64_t ld, int64_t m, uint8_t* ou
 // One MP iteration with a reduced-precision correlation pass (one launch).
 //
 // Same shape as the FP32 step: 16-wave workgroups, r staged in LDS, wave w
-// of workgroup b takes columns b*cpw + w, + 16, ...; each wave keeps a top-8
+// of workgroup b takes columns b*cpw + w, + 16, ... (FP8: pairs b*cpw + 2w,
+// 2w + 1, + 32, ...); each wave keeps a top-8
 // list of its columns' keys, the workgroup merges its 16 lists and publishes
 // 8 keys.  The last workgroup merges all published keys into the launch's
 // top 8, re-scores the first `rescore_k` of them in FP32 and finishes the
@@ -135,10 +140,22 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   uint64_t L[kTopK];
 #pragma unroll
   for (int j = 0; j < kTopK; ++j) L[j] = 0;
-  for (int64_t col = col0 + wave; col < col1; col += kLpWaves) {
-    float c = dot_column_lp<S>(psiq + col * nq, r_lds, nq, lane);
-    if constexpr (S == 1) c *= scales[col];
-    top8_insert(L, make_key(c, static_cast<int>(col)));
+  // wave w takes columns in runs of CC: col0 + CC*w, ..., then + CC*16
+  constexpr int CC = kLpColsPerWave<S>;
+  for (int64_t col = col0 + CC * wave; col < col1; col += CC * kLpWaves) {
+    const v4u* p[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) p[c] = psiq + (col + c < col1 ? col + c : col) * nq;
+    float cv[CC];
+    dot_columns_lp<S, CC>(p, r_lds, nq, lane, cv);
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      if (col + c < col1) {
+        float v = cv[c];
+        if constexpr (S == 1) v *= scales[col + c];
+        top8_insert(L, make_key(v, static_cast<int>(col + c)));
+      }
+    }
   }
   {
     uint64_t v = 0;

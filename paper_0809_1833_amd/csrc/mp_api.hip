@@ -76,7 +76,7 @@ void free_ctx(mp_ctx* c) {
   if (!c) return;
   free_batched(c);
   free_ragged(c);
-  if (c->psib_owned) (void)hipFree(c->psib);
+  (void)hipFree(c->psibt);
   (void)hipFree(c->psi32);
   (void)hipFree(c->psi64);
   (void)hipFree(c->r64_work);
@@ -557,23 +557,21 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
 // Make sure the context has a BF16 copy for the batched product and buffers
 // for `B` signals.
 static mp_status ensure_batched(mp_ctx* c, int64_t B, hipStream_t s) {
-  if (!c->psib) {
-    if (c->storage == MP_BF16) {
-      c->psib = static_cast<uint16_t*>(c->psiq);
-    } else {
-      const size_t bytes = static_cast<size_t>(c->ld) * static_cast<size_t>(c->m) * 2;
-      if (hipMalloc(&c->psib, bytes) != hipSuccess) return fail(c, MP_ENOMEM, "BF16 copy");
-      c->psib_owned = true;
-      HIP_TRY(c, mp::launch_quant_bf16(c->psi32, c->ld, c->m, c->psib, s));
-    }
+  if (!c->psibt) {
+    const size_t bytes =
+        static_cast<size_t>(c->ld) * static_cast<size_t>(round_up(c->m, 16)) * 2;
+    if (hipMalloc(&c->psibt, bytes) != hipSuccess) return fail(c, MP_ENOMEM, "BF16 tiles");
+    HIP_TRY(c, mp::launch_tile_bf16(c->psi32, c->ld, c->m, c->psibt, s));
   }
   if (B <= c->bcap) return MP_OK;
   free_batched(c);
   const int64_t cap = B;
   const int mtiles = mp::bcorr_mtiles(c->m, 32);  // the larger of the two tilings
   const size_t ldb = static_cast<size_t>(c->ld);
+  c->ldq = c->ld + 32;
   bool ok = hipMalloc(&c->b_r32, sizeof(float) * ldb * cap) == hipSuccess &&
-            hipMalloc(&c->b_rq, sizeof(uint16_t) * ldb * cap) == hipSuccess &&
+            hipMalloc(&c->b_rq, sizeof(uint16_t) * static_cast<size_t>(c->ldq) * cap) ==
+                hipSuccess &&
             hipMalloc(&c->b_slots, sizeof(mp::BSlot) * cap) == hipSuccess &&
             hipMalloc(&c->b_act, sizeof(int) * 2 * cap) == hipSuccess &&
             hipMalloc(&c->b_state, sizeof(mp::BState)) == hipSuccess &&
@@ -641,7 +639,8 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
                               hipMemcpyHostToDevice, s));
   int* act0 = c->b_act;
   int* act1 = c->b_act + c->bcap;
-  HIP_TRY(c, mp::launch_binit(Y, ldy, c->n, c->ld, X, ldx, c->m, c->b_r32, c->b_rq, c->b_slots,
+  HIP_TRY(c, mp::launch_binit(Y, ldy, c->n, c->ld, X, ldx, c->m, c->b_r32, c->b_rq, c->ldq,
+                              c->b_slots,
                               max_iters_b ? c->b_tcap : nullptr, opts->max_iters, opts->eps,
                               static_cast<int>(B), act0, act1, c->b_state, s));
 
@@ -682,8 +681,9 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
           e0 = c->ev[(k * kMaxChunk + j) * 2];
           e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
         }
-        hipError_t e = mp::launch_bround(c->psib, c->psi32, c->ld, c->n, c->m, c->b_r32, c->b_rq,
-                                         X, ldx, c->b_slots, act0, act1, c->b_state,
+        hipError_t e = mp::launch_bround(c->psibt, c->psi32, c->ld, c->n, c->m, c->b_r32,
+                                         c->b_rq, c->ldq, X, ldx, c->b_slots, act0, act1,
+                                         c->b_state,
                                          c->b_partials, c->b_alive, static_cast<int>(B),
                                          nact_hint, rk, tr, s, e0, e1);
         if (e != hipSuccess) {

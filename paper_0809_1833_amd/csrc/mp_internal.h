@@ -94,16 +94,20 @@ struct BState {
   int n_active[2];
   unsigned arrive;  // workgroups of the current select launch that have counted in
 };
+// The BF16 dictionary in the product's 16-atom x 32-element tiles
+// (round_up(m, 16) x ld elements).
+hipError_t launch_tile_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* out,
+                            hipStream_t s);
 hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, float* X,
-                        int64_t ldx, int64_t m, float* R32, uint16_t* Rq, BSlot* slots,
+                        int64_t ldx, int64_t m, float* R32, uint16_t* Rq, int64_t ldq, BSlot* slots,
                         const long long* tcap, long long tcap_all, double eps, int nslots,
                         int* act0, int* act1, BState* bs, hipStream_t s);
 int bcorr_tile_m(int nact_hint);
 int bcorr_mtiles(int64_t m, int tile_m);
 // One round.  nact_hint >= the number of active signals (the host's last
 // reading; the count only decreases): it sizes the grids and picks the tile.
-hipError_t launch_bround(const uint16_t* psib, const float* psi32, int64_t ld, int64_t n,
-                         int64_t m, float* R32, uint16_t* Rq, float* X, int64_t ldx,
+hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, int64_t n,
+                         int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
                          BSlot* slots, int* act0, int* act1, BState* bs, uint64_t* partials,
                          uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
                          hipStream_t s, hipEvent_t e0, hipEvent_t e1);
@@ -171,12 +175,13 @@ struct mp_ctx {
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
   int rescore_k = mp::kLpTopK;   // for the current decode
-  // batched decode: BF16 dictionary copy and per-signal buffers (grown on demand)
-  uint16_t* psib = nullptr;      // == psiq for MP_BF16 storage, else owned here
-  bool psib_owned = false;
+  // batched decode: BF16 dictionary in product tiles and per-signal buffers
+  // (grown on demand)
+  uint16_t* psibt = nullptr;     // round_up(m, 16) x ld BF16, 16 x 32 tiles
   int64_t bcap = 0;              // signal slots allocated
+  int64_t ldq = 0;               // leading dimension of b_rq: ld + 32
   float* b_r32 = nullptr;        // bcap x ld
-  uint16_t* b_rq = nullptr;      // bcap x ld
+  uint16_t* b_rq = nullptr;      // bcap x ldq
   mp::BSlot* b_slots = nullptr;
   mp::BSlot* h_slots = nullptr;  // pinned
   int* b_act = nullptr;          // 2 x bcap
