@@ -147,13 +147,18 @@ __device__ inline uint64_t block_max(uint64_t v, uint64_t* red) {
 // same result bit for bit.
 
 // U loads of 16 bytes in flight per lane, then U x 4 FMAs against the LDS
-// copy of r; advances i by 64 * U float4s.
-template <int U>
+// copy of r; advances i by 64 * U float4s.  Streaming passes load with the
+// non-temporal hint; STREAM = false keeps the lines cached (a column read
+// again soon after).
+template <int U, bool STREAM = true>
 __device__ inline void dot_block(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
                                  int& i, float& acc) {
   v4f a[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+  for (int u = 0; u < U; ++u) {
+    if constexpr (STREAM) a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+    else a[u] = p[i + kWave * u];
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const v4f b = r_lds[i + kWave * u];
@@ -207,18 +212,20 @@ __device__ inline float dot_column_f32(const v4f* __restrict__ p, const v4f* __r
 }
 
 // One chain of the inner product (float4s base+l, base+l+64, ... below
-// base+len) as this lane's partial sum, without the lane sum.
+// base+len) as this lane's partial sum, without the lane sum.  Used for
+// re-scoring, whose winning column is read again by the update, so its lines
+// stay cached.
 __device__ inline float dot_chain_f32(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
                                       int base, int len, int lane) {
   p += base;
   r_lds += base;
   float acc = 0.0f;
   int i = lane;
-  while (i + kWave * 15 < len) dot_block<16>(p, r_lds, i, acc);
-  if (i + kWave * 7 < len) dot_block<8>(p, r_lds, i, acc);
-  if (i + kWave * 3 < len) dot_block<4>(p, r_lds, i, acc);
-  if (i + kWave * 1 < len) dot_block<2>(p, r_lds, i, acc);
-  if (i < len) dot_block<1>(p, r_lds, i, acc);
+  while (i + kWave * 15 < len) dot_block<16, false>(p, r_lds, i, acc);
+  if (i + kWave * 7 < len) dot_block<8, false>(p, r_lds, i, acc);
+  if (i + kWave * 3 < len) dot_block<4, false>(p, r_lds, i, acc);
+  if (i + kWave * 1 < len) dot_block<2, false>(p, r_lds, i, acc);
+  if (i < len) dot_block<1, false>(p, r_lds, i, acc);
   return acc;
 }
 
