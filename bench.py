@@ -11,9 +11,9 @@ steps; `roofline` is the correlation kernel's algorithmic HBM bandwidth
 (dictionary + residual bytes per launch / mean launch time from HIP events on
 the decode stream) against the 8 TB/s peak; `cpu_baseline` is the FP64
 oracle timed on a bounded sample of the same decode on this host.  The line
-also carries the batched form, the ragged instances and the FP64 decode of
-the same workload (each skippable with --no-batched / --no-ragged /
---no-f64).
+also carries the batched form, the ragged instances, the FP64 decode of the
+same workload and the Fig. 1 error grid (each skippable with --no-batched /
+--no-ragged / --no-f64 / --no-phase).
 """
 from __future__ import annotations
 
@@ -152,6 +152,24 @@ def bench_f64(seed: int, steps: int = 2, warmup: int = 1, profile_every: int = 1
                          "traffic": traffic_from_counters(n, m, "f64"),
                          "bytes_per_launch": b, "avg_launch_us": round(avg_ms * 1e3, 3),
                          "launches": kt_n}}
+
+
+def bench_phase(seed: int):
+    """The Fig. 1 experiment on the batched decoder: M=1000, a 20 x 20 grid of
+    sigma = K/M and rho = N/M (steps of 0.05), 100 trials per cell over 4
+    Bernoulli dictionaries per rho, eps=1e-7, T=N.  Reports decodes per second
+    of device time and a few landmarks of E(sigma, rho)."""
+    from paper_0809_1833_amd import phase
+    res = phase.phase_diagram(seed=seed, log=log)
+    E = res["E"]
+    return {"workload": "Fig. 1 grid: M=1000, sigma, rho in {0.05..1.0} (20 x 20), 100 trials "
+                        "per cell, Bernoulli dictionary, U[-1,1] nonzeros, eps=1e-7, T=N",
+            "decodes": res["decodes"], "decode_s": round(res["decode_seconds"], 3),
+            "signals_per_s": round(res["signals_per_s"], 1),
+            "E_percent": {"sigma0.05_rho1.0": round(float(E[-1][0]), 6),
+                          "sigma0.25_rho0.5": round(float(E[9][4]), 4),
+                          "sigma0.5_rho0.5": round(float(E[9][9]), 4),
+                          "sigma1.0_rho0.05": round(float(E[0][-1]), 4)}}
 
 
 def cpu_baseline(p, budget_s=15.0):
@@ -294,6 +312,8 @@ def main():
                     help="skip the ragged-instances measurement added to the line")
     ap.add_argument("--no-f64", action="store_true",
                     help="skip the FP64-decode measurement added to the line")
+    ap.add_argument("--no-phase", action="store_true",
+                    help="skip the Fig. 1 experiment (reconstruction error grid) added to the line")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every k-th iteration's kernel launch with HIP events")
     ap.add_argument("--max-iters", type=int, default=None,
@@ -378,6 +398,9 @@ def main():
     if not args.no_f64 and args.storage != "f64":
         log("[bench] FP64 decode of the same workload")
         line["f64"] = bench_f64(args.seed)
+    if not args.no_phase:
+        log("[bench] Fig. 1 experiment (batched decodes over the sigma-rho grid)")
+        line["phase"] = bench_phase(args.seed)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p)

@@ -19,6 +19,9 @@ Workloads (all synthetic; the paper measures on no dataset):
 * ``c3``  shared N=2048, M=8192 dictionary, B=256 signals, K_b ~ U{16..256}
 * ``c4``  512 independent problems, N_i ~ U{128,256,512,1024}, M_i=4N_i,
           K_i=N_i/16
+* ``phase`` the Fig. 1 experiment: M=1000, sigma = K/M and rho = N/M on a
+          grid, the +-1/sqrt(N) Bernoulli dictionary of eq. 13, nonzeros
+          U[-1, 1], eps=1e-7, T=N, 100 trials per cell
 
 Dictionaries are Gaussian N(0,1) with every column divided by its FP64 L2 norm
 and then rounded to FP32; supports are uniform without replacement; y is
@@ -37,7 +40,8 @@ import numpy as np
 
 __all__ = [
     "WORKLOADS", "Problem", "workload", "make_problem", "make_batch",
-    "make_ragged", "gaussian_unit_dictionary", "bernoulli_dictionary",
+    "make_ragged", "make_phase_batch", "PhaseBatch", "gaussian_unit_dictionary",
+    "bernoulli_dictionary",
     "hadamard_dictionary", "qr_orthonormal_dictionary", "sparse_signal",
     "encode", "rational_unit_dictionary", "rng_streams",
 ]
@@ -50,6 +54,9 @@ WORKLOADS = {
     "c2": dict(wid=2, n=8192, m=32768, k=256, eps=1e-5, max_iters=20 * 256),
     "c3": dict(wid=3, n=2048, m=8192, b=256, kmin=16, kmax=256, eps=1e-5),
     "c4": dict(wid=4, count=512, n_choices=(128, 256, 512, 1024), eps=1e-5),
+    # Fig. 1: M = 1000, sigma = K/M and rho = N/M on a grid, Bernoulli
+    # dictionary, nonzeros U[-1, 1], eps = 1e-7, T = N, 100 trials per cell
+    "phase": dict(wid=5, m=1000, eps=1e-7, trials=100, draws=4),
 }
 
 
@@ -235,6 +242,46 @@ def make_ragged(seed: int, count: Optional[int] = None,
         probs.append(Problem(psi, x, encode(psi, x, sup), sup, w["eps"], 20 * k,
                              meta=dict(workload="c4", seed=seed, index=i, k=k)))
     return probs
+
+
+@dataclass
+class PhaseBatch:
+    """One dictionary draw of the Fig. 1 experiment at one rho: every sigma of
+    the grid, ``per_sigma`` signals each, decoded against the same psi."""
+    psi: np.ndarray          # (N, M) float32 Fortran, +-fp32(1/sqrt(N))
+    x: np.ndarray            # (M, B) float32 Fortran
+    y: np.ndarray            # (N, B) float32 Fortran
+    sigma_index: np.ndarray  # (B,) index into the sigma grid of each signal
+    ks: np.ndarray           # (B,) K of each signal
+    eps: float
+    max_iters: int           # T = N
+
+
+def make_phase_batch(seed: int, rho: float, sigmas, draw: int, per_sigma: int,
+                     m: Optional[int] = None) -> PhaseBatch:
+    """Draw ``draw`` of the Fig. 1 experiment at ``rho``: N = round(rho M)
+    rows of the Bernoulli dictionary (eq. 13), and for every sigma in
+    ``sigmas`` ``per_sigma`` signals with K = round(sigma M) nonzeros drawn
+    from U[-1, 1] on a support uniform without replacement (K is capped at
+    M).  y = psi x in FP64, rounded to FP32."""
+    w = workload("phase")
+    m = w["m"] if m is None else m
+    n = max(1, int(round(rho * m)))
+    ss = np.random.SeedSequence([w["wid"], int(seed), n, int(draw)])
+    r_psi, r_sup, r_val = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(3)]
+    psi = bernoulli_dictionary(r_psi, n, m)
+    sig = np.asarray(list(sigmas), dtype=np.float64)
+    b = len(sig) * per_sigma
+    x = np.zeros((m, b), dtype=np.float32, order="F")
+    y = np.zeros((n, b), dtype=np.float32, order="F")
+    sidx = np.repeat(np.arange(len(sig)), per_sigma)
+    ks = np.minimum(np.maximum(np.rint(sig[sidx] * m).astype(np.int64), 1), m)
+    for j in range(b):
+        k = int(ks[j])
+        sup = np.sort(r_sup.choice(m, size=k, replace=False))
+        x[sup, j] = r_val.uniform(-1.0, 1.0, size=k).astype(np.float32)
+        y[:, j] = encode(psi, x[:, j], sup)
+    return PhaseBatch(psi, x, y, sidx, ks, w["eps"], n)
 
 
 def rational_unit_dictionary(rng: np.random.Generator, n: int, m: int,

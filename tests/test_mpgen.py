@@ -79,3 +79,24 @@ def test_fp64_problem_is_the_fp32_problem_unrounded():
     np.testing.assert_allclose(p64.y, p64.psi[:, p64.support] @ p64.x[p64.support],
                                rtol=0, atol=1e-13)
     assert p64.y.dtype == np.float64
+
+
+def test_phase_batch_follows_the_experiment():
+    """Fig. 1 inputs: Bernoulli +-1/sqrt(N) columns (eq. 13), K = sigma M
+    nonzeros from U[-1, 1], y = psi x."""
+    sig = [0.01, 0.1, 0.5]
+    pb = mpgen.make_phase_batch(0, 0.2, sig, draw=1, per_sigma=3)
+    n, m = pb.psi.shape
+    assert (n, m) == (200, 1000) and pb.max_iters == n and pb.eps == 1e-7
+    v = np.float32(1.0 / np.sqrt(n))
+    assert set(np.unique(np.abs(pb.psi))) == {v}
+    assert pb.ks.tolist() == [10, 10, 10, 100, 100, 100, 500, 500, 500]
+    for j in range(pb.x.shape[1]):
+        nz = np.flatnonzero(pb.x[:, j])
+        assert len(nz) == pb.ks[j] and np.all(np.abs(pb.x[nz, j]) <= 1.0)
+    np.testing.assert_allclose(pb.y, (pb.psi.astype(np.float64) @ pb.x.astype(np.float64)),
+                               rtol=0, atol=1e-6)
+    again = mpgen.make_phase_batch(0, 0.2, sig, draw=1, per_sigma=3)
+    assert np.array_equal(again.y, pb.y)
+    other = mpgen.make_phase_batch(0, 0.2, sig, draw=2, per_sigma=3)
+    assert not np.array_equal(other.psi, pb.psi)
