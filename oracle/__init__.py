@@ -9,7 +9,9 @@ Contents
   Section 3 (eqs. 8-12, argmax tie rule of eq. 16), in C (``mp_oracle.c``);
   ``solve`` takes y as FP32 (the FP32 decoder's input), ``solve64`` an FP64
   dictionary and an FP64 y (the FP64 decoder's inputs).
-* :mod:`oracle.exact` -- exact rational MP and brute-force pins.
+* :mod:`oracle.omp` -- Orthogonal Matching Pursuit in FP64 (MP's selection,
+  least-squares re-fit of all selected atoms).
+* :mod:`oracle.exact` -- exact rational MP and OMP, brute-force pins.
 * :mod:`oracle.quant` -- reference BF16 / FP8-e4m3fn quantisers.
 """
 from __future__ import annotations

@@ -14,6 +14,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * :func:`best_k_support` enumerates every K-subset of atoms (the l0 problem of
   eq. 6, feasible only for tiny M) and returns the one with the smallest
   least-squares residual.
+* :func:`exact_omp` runs OMP (see ``oracle.omp``) in exact rational
+  arithmetic, re-fitting the selected atoms through the normal equations
+  solved by Gaussian elimination on Fractions -- a different route to the
+  least-squares fit than the LAPACK solver the FP64 OMP oracle uses.
 """
 from __future__ import annotations
 
@@ -112,3 +116,65 @@ def best_k_support(psi: np.ndarray, y: np.ndarray, k: int):
         if best is None or e < best[2]:
             best = (sup, coef, e)
     return best
+
+
+def _solve_exact(a: List[List[Fraction]], b: List[Fraction]) -> List[Fraction]:
+    """Solve the square system a z = b exactly (Gaussian elimination with
+    the first non-zero pivot; a must be non-singular)."""
+    k = len(b)
+    aug = [list(a[i]) + [b[i]] for i in range(k)]
+    for col in range(k):
+        piv = next(r for r in range(col, k) if aug[r][col] != 0)
+        aug[col], aug[piv] = aug[piv], aug[col]
+        for r in range(k):
+            if r != col and aug[r][col] != 0:
+                f = aug[r][col] / aug[col][col]
+                aug[r] = [aug[r][j] - f * aug[col][j] for j in range(k + 1)]
+    return [aug[i][k] / aug[i][i] for i in range(k)]
+
+
+def exact_omp(cols: Sequence[Sequence[Fraction]], y: Sequence[Fraction],
+              eps: Fraction, max_iters: int):
+    """OMP in exact rational arithmetic (same loop, tie rule and stopping
+    test as ``exact_mp``).  Returns dict(idx, coef (c_i of each selection),
+    rr, x, r, iters, reason)."""
+    n, m = len(y), len(cols)
+    yv = [Fraction(v) for v in y]
+    r = list(yv)
+    yy = sum(v * v for v in yv)
+    thr = Fraction(eps) * Fraction(eps) * yy
+    sel: List[int] = []
+    coef: List[Fraction] = []
+    rrs: List[Fraction] = []
+    xs: List[Fraction] = []
+    if yy == 0:
+        return dict(idx=sel, coef=coef, rr=rrs, x=[Fraction(0)] * m, r=r, iters=0,
+                    reason="zero_input")
+    rr = yy
+    t = 0
+    while True:
+        if not rr > thr:
+            reason = "converged"
+            break
+        if t >= max_iters:
+            reason = "max_iters"
+            break
+        c = [sum(col[i] * r[i] for i in range(n)) for col in cols]
+        a = [abs(v) for v in c]
+        i = a.index(max(a))
+        if c[i] == 0 or i in sel:
+            reason = "stalled"
+            break
+        sel.append(i)
+        g = [[sum(cols[p][k] * cols[q][k] for k in range(n)) for q in sel] for p in sel]
+        b = [sum(cols[p][k] * yv[k] for k in range(n)) for p in sel]
+        xs = _solve_exact(g, b)
+        r = [yv[k] - sum(xs[j] * cols[sel[j]][k] for j in range(len(sel))) for k in range(n)]
+        rr = sum(v * v for v in r)
+        coef.append(c[i])
+        rrs.append(rr)
+        t += 1
+    x = [Fraction(0)] * m
+    for j, s in enumerate(sel):
+        x[s] = xs[j]
+    return dict(idx=sel, coef=coef, rr=rrs, x=x, r=r, iters=t, reason=reason)
