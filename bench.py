@@ -11,9 +11,9 @@ steps; `roofline` is the correlation kernel's algorithmic HBM bandwidth
 (dictionary + residual bytes per launch / mean launch time from HIP events on
 the decode stream) against the 8 TB/s peak; `cpu_baseline` is the FP64
 oracle timed on a bounded sample of the same decode on this host.  The line
-also carries the batched form, the ragged instances, the FP64 decode of the
-same workload and the Fig. 1 error grid (each skippable with --no-batched /
---no-ragged / --no-f64 / --no-phase).
+also carries the batched form, the ragged instances, the FP64 decode and the
+OMP decode of the same workload, and the Fig. 1 error grid (each skippable
+with --no-batched / --no-ragged / --no-f64 / --no-omp / --no-phase).
 """
 from __future__ import annotations
 
@@ -96,18 +96,20 @@ def step_bytes(n, m, storage):
     return b
 
 
-def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None):
+def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None, omp=False):
     """Warm up, then time `steps` whole decodes; the step kernel's launches are
-    timed with HIP events on the decode stream (every profile_every-th)."""
+    timed with HIP events on the decode stream (every profile_every-th).
+    ``omp``: decode with Orthogonal Matching Pursuit (the selection pass is
+    the timed kernel)."""
     import torch
     for _ in range(warmup):
-        dec.solve(y, p.eps, p.max_iters, x=x, r=r)
+        dec.solve(y, p.eps, p.max_iters, x=x, r=r, omp=omp)
     dec.set_profiling(profile_every)
     torch.cuda.synchronize()
     iters, kt_ms, kt_n, stops = 0, 0.0, 0, set()
     t0 = time.perf_counter()
     for _ in range(steps):
-        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream)
+        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream, omp=omp)
         iters += out["iters"]
         ms, cnt = dec.kernel_time()
         kt_ms += ms * cnt
@@ -312,6 +314,8 @@ def main():
                     help="skip the ragged-instances measurement added to the line")
     ap.add_argument("--no-f64", action="store_true",
                     help="skip the FP64-decode measurement added to the line")
+    ap.add_argument("--no-omp", action="store_true",
+                    help="skip the Orthogonal Matching Pursuit decode added to the line")
     ap.add_argument("--no-phase", action="store_true",
                     help="skip the Fig. 1 experiment (reconstruction error grid) added to the line")
     ap.add_argument("--profile-every", type=int, default=16,
@@ -388,6 +392,18 @@ def main():
             "launches": kt_n,
         },
     }
+    if not args.no_omp and args.storage == "f32":
+        log("[bench] OMP decode of the same signal")
+        o_it, o_dt, o_ms, o_n, o_stops = time_decodes(dec, y, p, args.steps, args.warmup,
+                                                      args.profile_every, x, r, stream, omp=True)
+        o_ach = bytes_per_launch / (o_ms * 1e-3) / 1e9 if o_n else None
+        line["omp"] = {
+            "workload": f"{args.workload}, Orthogonal Matching Pursuit (QR re-fit, CGS2)",
+            "iters_per_s": round(o_it / o_dt, 3), "ms_per_decode": round(o_dt / args.steps * 1e3, 3),
+            "iters_per_decode": o_it // max(args.steps, 1), "stop": sorted(o_stops),
+            "select_kernel": {"kernel": "k_omp_select", "avg_launch_us": round(o_ms * 1e3, 3),
+                              "achieved": round(o_ach, 2) if o_ach else None, "unit": "GB/s",
+                              "frac": round(o_ach / HBM_PEAK_GBS, 4) if o_ach else None}}
     dec.close()
     if not args.no_batched:
         log("[bench] batched form (256 signals, shared dictionary)")

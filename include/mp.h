@@ -233,6 +233,35 @@ mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, i
 mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const mp_opts* opts,
                        mp_result* res, const mp_trace_f64* trace, void* stream);
 
+/*
+ * mp_solve_omp -- decode one signal with Orthogonal Matching Pursuit, the
+ * refinement of MP the paper names as its next target: each iteration selects
+ * an atom exactly as mp_solve does (eq. 9, smallest index on ties as eq. 16),
+ * then re-fits all selected atoms by least squares, so r stays orthogonal to
+ * every selected atom:  x~_S = argmin ||y - Psi_S x~_S||_2,  r = y - Psi_S x~_S.
+ * The fit is kept as a QR factorisation of the selected atoms grown by one
+ * column per iteration (classical Gram-Schmidt run twice), FP32 with FP64
+ * norms; x~_S is solved at the end in FP64.
+ *
+ *   ctx      from mp_create with MP_F32 storage
+ *   y, x, r  as mp_solve (x~ is nonzero only on the selected atoms)
+ *   opts     eps, max_iters (at most min(max_iters, N) atoms are selected),
+ *            rescore_k ignored, flags 0
+ *   res      host or NULL
+ *   trace    host struct of device arrays, or NULL: idx[t] the atom selected
+ *            at step t, coef[t] its correlation <r, psi_idx>, rr[t] ||r||^2
+ *            after the re-fit
+ *
+ * A selection that repeats an atom, or a new atom that is a combination of
+ * the selected ones to FP32 accuracy (||w||^2 <= 1e-10), ends the run with
+ * MP_STOP_STALLED.  Work buffers of min(max_iters, N) x ld and
+ * min(max_iters, N)^2 floats are kept by the context.  Errors: MP_EINVAL
+ * (not an MP_F32 context, NULL ctx/y/x/opts, bad opts), MP_ENONFINITE,
+ * MP_ENOMEM, MP_EDEVICE.
+ */
+mp_status mp_solve_omp(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
+                       mp_result* res, const mp_trace* trace, void* stream);
+
 /* One problem of a ragged set: its own dictionary (device, FP32, column-major
    N x M with leading dimension ld). */
 typedef struct mp_instance {

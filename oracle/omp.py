@@ -31,6 +31,8 @@ import numpy as np
 from . import correlate
 
 CONVERGED, MAX_ITERS, STALLED, ZERO_INPUT = 0, 1, 2, 3
+REASONS = {CONVERGED: "converged", MAX_ITERS: "max_iters", STALLED: "stalled",
+           ZERO_INPUT: "zero_input"}
 
 
 @dataclass

@@ -171,14 +171,19 @@ __device__ inline void dot_block(const v4f* __restrict__ p, const v4f* __restric
 }
 
 // Both chains at once: U loads from each half (2U in flight per lane).
-template <int U>
+template <int U, bool STREAM = true>
 __device__ inline void dot_block2(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
                                   int h0, int& i, float& acc_a, float& acc_b) {
   v4f a[U], b[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    a[u] = __builtin_nontemporal_load(p + i + kWave * u);
-    b[u] = __builtin_nontemporal_load(p + h0 + i + kWave * u);
+    if constexpr (STREAM) {
+      a[u] = __builtin_nontemporal_load(p + i + kWave * u);
+      b[u] = __builtin_nontemporal_load(p + h0 + i + kWave * u);
+    } else {
+      a[u] = p[i + kWave * u];
+      b[u] = p[h0 + i + kWave * u];
+    }
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -198,16 +203,18 @@ __device__ inline void dot_block2(const v4f* __restrict__ p, const v4f* __restri
 
 // <r, psi_col> for one column by one wave: both chains in blocks of 8 loads
 // each while they fit, then at most one block each of 4, 2 and 1 (so short
-// columns still have several loads in flight), then the lane sum.
+// columns still have several loads in flight), then the lane sum.  STREAM =
+// false keeps the column's lines cached (a vector read again soon).
+template <bool STREAM = true>
 __device__ inline float dot_column_f32(const v4f* __restrict__ p, const v4f* __restrict__ r_lds,
                                        int ld4, int lane) {
   const int h0 = ld4 / 2;
   float acc_a = 0.0f, acc_b = 0.0f;
   int i = lane;
-  while (i + kWave * 7 < h0) dot_block2<8>(p, r_lds, h0, i, acc_a, acc_b);
-  if (i + kWave * 3 < h0) dot_block2<4>(p, r_lds, h0, i, acc_a, acc_b);
-  if (i + kWave * 1 < h0) dot_block2<2>(p, r_lds, h0, i, acc_a, acc_b);
-  if (i < h0) dot_block2<1>(p, r_lds, h0, i, acc_a, acc_b);
+  while (i + kWave * 7 < h0) dot_block2<8, STREAM>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i + kWave * 3 < h0) dot_block2<4, STREAM>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i + kWave * 1 < h0) dot_block2<2, STREAM>(p, r_lds, h0, i, acc_a, acc_b);
+  if (i < h0) dot_block2<1, STREAM>(p, r_lds, h0, i, acc_a, acc_b);
   return wave_sum(acc_a + acc_b);
 }
 

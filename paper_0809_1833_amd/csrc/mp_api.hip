@@ -72,10 +72,26 @@ void free_ragged(mp_ctx* c) {
   if (c->r_cap_stream) (void)hipStreamDestroy(c->r_cap_stream);
 }
 
+void free_omp(mp_ctx* c) {
+  mp::OmpBufs& b = c->omp;
+  (void)hipFree(b.q);
+  (void)hipFree(b.rmat);
+  (void)hipFree(b.z);
+  (void)hipFree(b.sel);
+  (void)hipFree(b.in_s);
+  (void)hipFree(b.w);
+  (void)hipFree(b.h1);
+  (void)hipFree(b.h2);
+  (void)hipFree(b.part);
+  (void)hipFree(b.os);
+  b = mp::OmpBufs{};
+}
+
 void free_ctx(mp_ctx* c) {
   if (!c) return;
   free_batched(c);
   free_ragged(c);
+  free_omp(c);
   (void)hipFree(c->psibt);
   (void)hipFree(c->psi32);
   (void)hipFree(c->psi64);
@@ -440,6 +456,69 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   });
   if (st != MP_OK) return st;
 
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  if (r)
+    HIP_TRY(c, hipMemcpyAsync(r, c->r_work, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return finish_result(c, res);
+}
+
+static mp_status ensure_omp(mp_ctx* c, int64_t tq) {
+  mp::OmpBufs& b = c->omp;
+  if (b.tq >= tq) return MP_OK;
+  free_omp(c);
+  const size_t ld = static_cast<size_t>(c->ld), t = static_cast<size_t>(tq);
+  bool ok = hipMalloc(&b.q, sizeof(float) * t * ld) == hipSuccess &&
+            hipMalloc(&b.rmat, sizeof(float) * t * t) == hipSuccess &&
+            hipMalloc(&b.z, sizeof(double) * t) == hipSuccess &&
+            hipMalloc(&b.sel, sizeof(int) * t) == hipSuccess &&
+            hipMalloc(&b.in_s, static_cast<size_t>(c->m)) == hipSuccess &&
+            hipMalloc(&b.w, sizeof(float) * ld) == hipSuccess &&
+            hipMalloc(&b.h1, sizeof(float) * t) == hipSuccess &&
+            hipMalloc(&b.h2, sizeof(float) * t) == hipSuccess &&
+            hipMalloc(&b.part, sizeof(double) * (ld / 64)) == hipSuccess &&
+            hipMalloc(&b.os, sizeof(mp::OmpState)) == hipSuccess;
+  if (!ok) {
+    free_omp(c);
+    return fail(c, MP_ENOMEM, "OMP work buffers");
+  }
+  b.tq = tq;
+  return MP_OK;
+}
+
+mp_status mp_solve_omp(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
+                       mp_result* res, const mp_trace* trace, void* stream) {
+  if (!ctx) return MP_EINVAL;
+  ctx->err.clear();
+  if (ctx->ragged || ctx->storage != MP_F32)
+    return fail(ctx, MP_EINVAL, "mp_solve_omp needs an MP_F32 context from mp_create");
+  if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
+  if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
+  mp_trace tr{};
+  if (trace) {
+    if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
+    tr = *trace;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mp_ctx* c = ctx;
+  // at most min(T, N) atoms: beyond N the selected atoms span the whole space
+  const long long T = std::min<long long>(opts->max_iters, c->n);
+  if (mp_status bs = ensure_omp(c, std::max<long long>(T, 1)); bs != MP_OK) return bs;
+  mp::OmpBufs& b = c->omp;
+  HIP_TRY(c, hipMemsetAsync(b.in_s, 0, static_cast<size_t>(c->m), s));
+  HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, c->r_work, c->st, opts->eps, T, s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  long long it = 0;  // iterations enqueued so far: a bound on the atoms selected
+  const mp_status st = run_iterations(c, T, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    const hipError_t e = mp::launch_omp_iteration(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom,
+                                                  c->partials, c->st, b, it, tr, s, e0, e1);
+    ++it;
+    return e;
+  });
+  if (st != MP_OK) return st;
+  HIP_TRY(c, mp::launch_omp_solve(b, c->st, x, s));
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   if (r)
     HIP_TRY(c, hipMemcpyAsync(r, c->r_work, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -81,6 +81,33 @@ hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t 
                               const CorrGeom& g, uint64_t* keys, double* x, DevState* st,
                               mp_trace_f64 tr, hipStream_t s);
 
+// ---- Orthogonal Matching Pursuit, FP32 (k_omp.hip) --------------------------
+struct OmpState {           // the atom selected in the current iteration
+  int sel;
+  float c;                  // its correlation <r, psi_sel>
+  int pad[2];
+};
+struct OmpBufs {            // work buffers of one OMP decode (context-owned)
+  int64_t tq = 0;           // capacity: atoms (rows of q, order of R)
+  float* q = nullptr;       // tq x ld: orthonormal basis of the selected atoms
+  float* rmat = nullptr;    // tq x tq column-major upper triangle R (Psi_S = Q R)
+  double* z = nullptr;      // tq: coordinates of y on q_0..q_{t-1}
+  int* sel = nullptr;       // tq: selected atoms in order
+  unsigned char* in_s = nullptr;  // m flags: atom already selected
+  float* w = nullptr;       // ld: the vector being orthogonalised
+  float* h1 = nullptr;      // tq: Q^T psi_i (first Gram-Schmidt pass)
+  float* h2 = nullptr;      // tq: Q^T w (second pass)
+  double* part = nullptr;   // ld / 64: per-workgroup sums of w^2
+  OmpState* os = nullptr;
+};
+// One OMP iteration (five launches); t_bound >= the number of atoms selected
+// so far (sizes the projection grid).  e0/e1 time the selection pass.
+hipError_t launch_omp_iteration(const float* psi, int64_t ld, int64_t n, int64_t m, float* r,
+                                const CorrGeom& g, uint64_t* keys, DevState* st, OmpBufs& b,
+                                long long t_bound, mp_trace tr, hipStream_t s, hipEvent_t e0,
+                                hipEvent_t e1);
+hipError_t launch_omp_solve(const OmpBufs& b, const DevState* st, float* x, hipStream_t s);
+
 // ---- batched decode against one dictionary (k_batched.hip) ------------------
 // Per-signal state; written only by the workgroup handling that signal.
 struct BSlot {
@@ -208,5 +235,7 @@ struct mp_ctx {
   hipStream_t r_cap_stream = nullptr;
   hipGraphExec_t r_graph = nullptr;
   std::vector<unsigned char> r_graph_key;
+  // OMP decode buffers (grown on demand)
+  mp::OmpBufs omp;
   std::string err;
 };

@@ -107,6 +107,9 @@ def _load():
     lib.mp_set_profiling.argtypes = [p, ctypes.c_int]
     lib.mp_kernel_time.restype = ctypes.c_int
     lib.mp_kernel_time.argtypes = [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.mp_solve_omp.restype = ctypes.c_int
+    lib.mp_solve_omp.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
+                                 ctypes.POINTER(Trace), p]
     lib.mp_create_f64.restype = ctypes.c_int
     lib.mp_create_f64.argtypes = [ctypes.POINTER(ctypes.c_void_p), p, i64, i64, i64, u32, p]
     lib.mp_solve_f64.restype = ctypes.c_int
@@ -166,6 +169,15 @@ def mp_solve(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
     st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
                           ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve", ctx)
+    return res
+
+
+def mp_solve_omp(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
+                 trace: Optional[Trace] = None, stream: Optional[int] = None) -> Result:
+    res = Result()
+    st = _load().mp_solve_omp(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
+                              ctypes.byref(trace) if trace is not None else None, stream)
+    _check(st, "mp_solve_omp", ctx)
     return res
 
 
@@ -321,8 +333,10 @@ class Decoder:
 
     def solve(self, y: torch.Tensor, eps: float, max_iters: int, x: Optional[torch.Tensor] = None,
               r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
-              stream=None):
-        """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, trace...)."""
+              stream=None, omp: bool = False):
+        """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, trace...).
+        ``omp=True`` decodes with Orthogonal Matching Pursuit (mp_solve_omp;
+        MP_F32 storage)."""
         dt = self.dtype
         if not y.is_cuda or y.dtype != dt or y.numel() != self.n:
             raise ValueError(f"y must be a {dt} CUDA tensor of N elements")
@@ -341,7 +355,9 @@ class Decoder:
             tr = (TraceF64 if self.storage == "f64" else Trace)(
                 tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
         opts = Opts(float(eps), int(max_iters), int(rescore_k), 0)
-        solve = mp_solve_f64 if self.storage == "f64" else mp_solve
+        if omp and self.storage != "f32":
+            raise ValueError("OMP decodes need f32 storage")
+        solve = mp_solve_f64 if self.storage == "f64" else (mp_solve_omp if omp else mp_solve)
         res = solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
                     _stream_ptr(stream))
         out = dict(x=x, r=r, iters=res.iters, yy=res.yy, rr=res.rr,
