@@ -44,6 +44,8 @@ TRAFFIC = {
                                               "mp_internal.h")]),
     "f64": (os.path.join(ROOT, "profiles", "mp_step_f64_traffic.json"),
             [os.path.join(_CSRC, f) for f in ("k_f64.hip", "k_common.h", "mp_internal.h")]),
+    "omp": (os.path.join(ROOT, "profiles", "omp_select_traffic.json"),
+            [os.path.join(_CSRC, f) for f in ("k_omp.hip", "k_common.h", "mp_internal.h")]),
 }
 ESIZE = {"f64": 8.0, "f32": 4.0, "bf16": 2.0, "fp8": 1.0}
 KERNEL = {"f64": "k_mp_step_f64", "f32": "k_mp_step_f32", "bf16": "k_mp_step_lp",
@@ -403,7 +405,8 @@ def main():
             "iters_per_decode": o_it // max(args.steps, 1), "stop": sorted(o_stops),
             "select_kernel": {"kernel": "k_omp_select", "avg_launch_us": round(o_ms * 1e3, 3),
                               "achieved": round(o_ach, 2) if o_ach else None, "unit": "GB/s",
-                              "frac": round(o_ach / HBM_PEAK_GBS, 4) if o_ach else None}}
+                              "frac": round(o_ach / HBM_PEAK_GBS, 4) if o_ach else None,
+                              "traffic": traffic_from_counters(p.n, p.m, "omp")}}
     dec.close()
     if not args.no_batched:
         log("[bench] batched form (256 signals, shared dictionary)")

@@ -22,6 +22,9 @@ Workloads (all synthetic; the paper measures on no dataset):
 * ``phase`` the Fig. 1 experiment: M=1000, sigma = K/M and rho = N/M on a
           grid, the +-1/sqrt(N) Bernoulli dictionary of eq. 13, nonzeros
           U[-1, 1], eps=1e-7, T=N, 100 trials per cell
+* sign-bit problems (:func:`make_sign_problem`): the sizes of ``c0``,
+          ``c1a`` or ``c1b`` on the Bernoulli dictionary of eq. 13 held as one
+          sign bit per entry (the packed format below)
 
 Dictionaries are Gaussian N(0,1) with every column divided by its FP64 L2 norm
 and then rounded to FP32; supports are uniform without replacement; y is
@@ -44,6 +47,7 @@ __all__ = [
     "bernoulli_dictionary",
     "hadamard_dictionary", "qr_orthonormal_dictionary", "sparse_signal",
     "encode", "rational_unit_dictionary", "rng_streams",
+    "bernoulli_signs", "pack_signs", "encode_signs", "make_sign_problem", "SignProblem",
 ]
 
 # name -> (id used in the seed sequence, N, M, K, eps, iteration cap rule)
@@ -114,6 +118,73 @@ def bernoulli_dictionary(rng: np.random.Generator, n: int, m: int) -> np.ndarray
     s = rng.integers(0, 2, size=(m, n), dtype=np.int8) * 2 - 1
     cols = (s.astype(np.float64) / np.sqrt(n)).astype(np.float32)
     return cols.T
+
+
+def bernoulli_signs(rng: np.random.Generator, n: int, m: int) -> np.ndarray:
+    """The signs of the Bernoulli dictionary (eq. 13): an (M, N) int8 array of
+    +-1, row m holding column m's N signs (the same draw as
+    :func:`bernoulli_dictionary`)."""
+    return rng.integers(0, 2, size=(m, n), dtype=np.int8) * 2 - 1
+
+
+def pack_signs(s: np.ndarray, ldw: Optional[int] = None) -> np.ndarray:
+    """Packed sign-bit format of a +-1 dictionary: an (M, ldw) uint32 array;
+    bit q of word w of row m is 1 when entry (32 w + q, m) is negative, 0 when
+    positive.  Bits past N in a column's last word, and words past
+    ceil(N / 32), are zero."""
+    m, n = s.shape
+    need = (n + 31) // 32
+    ldw = need if ldw is None else int(ldw)
+    if ldw < need:
+        raise ValueError("ldw must be >= ceil(N / 32)")
+    neg = np.zeros((m, ldw * 32), dtype=np.uint8)
+    neg[:, :n] = s < 0
+    by = np.packbits(neg, axis=1, bitorder="little")          # (M, 4 ldw) bytes
+    return np.ascontiguousarray(by).view("<u4").astype(np.uint32, copy=False)
+
+
+def encode_signs(s: np.ndarray, x: np.ndarray, support: Optional[np.ndarray] = None,
+                 dtype=np.float32) -> np.ndarray:
+    """y = Psi x (eq. 2) for Psi = S / sqrt(N) with S the (M, N) +-1 array, in
+    FP64, rounded to ``dtype``."""
+    if support is None:
+        support = np.flatnonzero(x)
+    n = s.shape[1]
+    y = s[support].T.astype(np.float64) @ np.asarray(x[support], dtype=np.float64)
+    return (y / np.sqrt(n)).astype(dtype)
+
+
+@dataclass
+class SignProblem:
+    """One decoding problem on a Bernoulli dictionary held as sign bits:
+    psi_nm = (1 - 2 b_nm) / sqrt(N) with b the bits of :func:`pack_signs`."""
+    bits: np.ndarray         # (M, ldw) uint32, packed sign bits
+    n: int
+    x: np.ndarray            # (M,) float32 ground truth (K nonzeros)
+    y: np.ndarray            # (N,) float32 measurements
+    support: np.ndarray      # (K,) int64, sorted
+    eps: float
+    max_iters: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.bits.shape[0]
+
+
+def make_sign_problem(name: str, seed: int, dist: str = "normal") -> SignProblem:
+    """The sizes and stopping rule of the single-signal workload ``name``
+    (``c0``, ``c1a`` or ``c1b``) on a sign-bit Bernoulli dictionary; x drawn
+    as for that workload, y computed in FP64 from the +-1 signs."""
+    w = workload(name)
+    r_psi, r_sup, r_val = rng_streams(w["wid"] + 200, seed, 3)
+    s = bernoulli_signs(r_psi, w["n"], w["m"])
+    x, support = sparse_signal(r_sup, r_val, w["m"], w["k"], dist)
+    y = encode_signs(s, x, support)
+    bits = pack_signs(s)
+    return SignProblem(bits, w["n"], x, y, support, w["eps"], w["max_iters"],
+                       meta=dict(workload=name, seed=seed, dist=dist, k=w["k"],
+                                 dictionary="bernoulli sign bits"))
 
 
 def hadamard_dictionary(n: int) -> np.ndarray:

@@ -11,6 +11,8 @@ Contents
   dictionary and an FP64 y (the FP64 decoder's inputs).
 * :mod:`oracle.omp` -- Orthogonal Matching Pursuit in FP64 (MP's selection,
   least-squares re-fit of all selected atoms).
+* :mod:`oracle.signs` -- the Bernoulli dictionary of eq. 13 held as sign bits,
+  read back into FP64 entries +-1/sqrt(N) and decoded by the FP64 MP above.
 * :mod:`oracle.exact` -- exact rational MP and OMP, brute-force pins.
 * :mod:`oracle.quant` -- reference BF16 / FP8-e4m3fn quantisers.
 """
