@@ -12,8 +12,9 @@ steps; `roofline` is the correlation kernel's algorithmic HBM bandwidth
 the decode stream) against the 8 TB/s peak; `cpu_baseline` is the FP64
 oracle timed on a bounded sample of the same decode on this host.  The line
 also carries the batched form, the ragged instances, the FP64 decode and the
-OMP decode of the same workload, and the Fig. 1 error grid (each skippable
-with --no-batched / --no-ragged / --no-f64 / --no-omp / --no-phase).
+OMP decode of the same workload, the decode on the sign-bit Bernoulli
+dictionary of the same sizes, and the Fig. 1 error grid (each skippable
+with --no-batched / --no-ragged / --no-f64 / --no-omp / --no-sign / --no-phase).
 """
 from __future__ import annotations
 
@@ -156,6 +157,46 @@ def bench_f64(seed: int, steps: int = 2, warmup: int = 1, profile_every: int = 1
                          "traffic": traffic_from_counters(n, m, "f64"),
                          "bytes_per_launch": b, "avg_launch_us": round(avg_ms * 1e3, 3),
                          "launches": kt_n}}
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CUs x 128 FP32 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 16):
+    """Decode on the Bernoulli dictionary of eq. 13 held as sign bits
+    (mp_create_signs): N=8192, M=32768 (32 MiB of bits), K=512, eps=1e-5,
+    T=10240.  The pass is bound by the arithmetic: achieved = the dense GEMV's
+    2 N M flop per launch (each entry's product with r is a signed add) over
+    the step kernel's mean launch time, against the FP32 vector peak."""
+    import torch
+
+    import mpgen
+    from paper_0809_1833_amd.mp import Decoder
+
+    p = mpgen.make_sign_problem("c1b", seed)
+    n, m = p.n, p.m
+    bits = torch.from_numpy(p.bits.view("int32")).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    with Decoder(bits, storage="sign", n=n) as dec:
+        del bits
+        x = torch.empty(m, dtype=torch.float32, device="cuda")
+        r = torch.empty(n, dtype=torch.float32, device="cuda")
+        iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
+                                                      x, r)
+    flop = 2.0 * n * m
+    achieved = flop / (avg_ms * 1e-3) / 1e12 if kt_n else None
+    return {"workload": f"N={n}, M={m}, Bernoulli dictionary (eq. 13) as sign bits "
+                        "(32 MiB), K=512, eps=1e-5, T=10240, single signal, FP32 residual",
+            "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
+            "iters_per_decode": iters // max(steps, 1), "stop": sorted(stops),
+            "roofline": {"bound": "alu", "kernel": "k_mp_step_sign",
+                         "achieved": round(achieved, 2) if achieved else None,
+                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4) if achieved
+                         else None,
+                         "traffic": None, "flop_per_launch": flop,
+                         "bit_bytes_per_launch": n * m / 8.0,
+                         "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kt_n}}
 
 
 def bench_phase(seed: int):
@@ -316,6 +357,8 @@ def main():
                     help="skip the ragged-instances measurement added to the line")
     ap.add_argument("--no-f64", action="store_true",
                     help="skip the FP64-decode measurement added to the line")
+    ap.add_argument("--no-sign", action="store_true",
+                    help="skip the sign-bit Bernoulli decode")
     ap.add_argument("--no-omp", action="store_true",
                     help="skip the Orthogonal Matching Pursuit decode added to the line")
     ap.add_argument("--no-phase", action="store_true",
@@ -417,6 +460,9 @@ def main():
     if not args.no_f64 and args.storage != "f64":
         log("[bench] FP64 decode of the same workload")
         line["f64"] = bench_f64(args.seed)
+    if not args.no_sign:
+        log("[bench] sign-bit Bernoulli dictionary (same sizes)")
+        line["sign"] = bench_sign(args.seed)
     if not args.no_phase:
         log("[bench] Fig. 1 experiment (batched decodes over the sigma-rho grid)")
         line["phase"] = bench_phase(args.seed)

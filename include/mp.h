@@ -62,8 +62,10 @@ typedef enum mp_dtype {
     MP_FP8_E4M3 = 2,      /* OCP FP8 E4M3 (e4m3fn) with one FP32 scale per column:
                              s_m = fp32(max_n |psi_nm| / 448) (1 for a zero column),
                              code = RNE-saturate(fp32(psi_nm / s_m)) */
-    MP_F64 = 3            /* FP64 dictionary and FP64 decode (mp_create_f64 /
+    MP_F64 = 3,           /* FP64 dictionary and FP64 decode (mp_create_f64 /
                              mp_solve_f64 only) */
+    MP_SIGN1 = 4          /* one sign bit per entry, psi_nm = (1 - 2 b_nm) / sqrt(N):
+                             the Bernoulli dictionary of eq. 13 (mp_create_signs) */
 } mp_dtype;
 
 /* Why a decode stopped (mp_result.stop_reason). */
@@ -234,6 +236,36 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
                        mp_result* res, const mp_trace_f64* trace, void* stream);
 
 /*
+ * mp_create_signs -- a context for the paper's own dictionary, the Bernoulli
+ * matrix of eq. 13 (entries +-1/sqrt(N), every column of unit norm), held as
+ * one sign bit per entry: psi_nm = (1 - 2 b_nm) / sqrt(N).  Decoded with
+ * mp_solve (FP32 y, x~ and r, as for MP_F32 storage): the correlation
+ * c_m = (sum_n (1 - 2 b_nm) r_n) / sqrt(N) is an FP32 signed sum scaled by
+ * fp32(1/sqrt(N)), and the update r_n -= c psi_nm adds or subtracts
+ * fp32(c / sqrt(N)).  The dictionary pass reads N/8 bytes per column instead
+ * of 4N.  The context has storage MP_SIGN1; mp_solve_batched and
+ * mp_solve_omp return MP_EINVAL for it.
+ *
+ *   out      host: receives the new context (set to NULL on failure)
+ *   signs    device: packed bits, column m in words [m ldw, m ldw + ldw);
+ *            bit q of word w is b_nm for row n = 32 w + q (1: -1/sqrt(N),
+ *            0: +1/sqrt(N)); bits of rows n >= N are ignored
+ *   n, m     1 <= N <= 8192, 1 <= M < 2^31
+ *   ldw      words per column, ldw >= ceil(N / 32)
+ *   flags    0 or MP_SKIP_NORM_CHECK (no effect: the columns have unit norm
+ *            by construction)
+ *   stream   hipStream_t as void*
+ *
+ * The context keeps its own copy of the bits (re-arranged for the pass); the
+ * caller may free signs when the call returns.  mp_get_storage returns the
+ * bits in the packed form above with ldw = ceil(N / 32).  Errors: MP_EINVAL
+ * (NULL, n or m out of range, ldw too small, unknown flags), MP_ENOMEM,
+ * MP_EDEVICE, MP_EUNSUPPORTED (not a gfx950 device).
+ */
+mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_t m, int64_t ldw,
+                          uint32_t flags, void* stream);
+
+/*
  * mp_solve_omp -- decode one signal with Orthogonal Matching Pursuit, the
  * refinement of MP the paper names as its next target: each iteration selects
  * an atom exactly as mp_solve does (eq. 9, smallest index on ties as eq. 16),
@@ -342,8 +374,11 @@ const char* mp_last_error(const mp_ctx* ctx);
  * without its padding: FP64 (8-byte), FP32 (4-byte), BF16 (2-byte) or FP8
  * (1-byte) codes, column-major N x M with leading dimension N, and for
  * MP_FP8_E4M3 the M per-column FP32 scales (scales may be NULL otherwise).
+ * For MP_SIGN1 the sign bits in mp_create_signs' packed form, ceil(N/32)
+ * 32-bit words per column, bits of rows >= N zero.
  *
- *   codes    device: N*M elements of the storage type's size
+ *   codes    device: N*M elements of the storage type's size (MP_SIGN1:
+ *            M ceil(N/32) words)
  *   scales   device: M floats, or NULL
  * Errors: MP_EINVAL, MP_EDEVICE.
  */

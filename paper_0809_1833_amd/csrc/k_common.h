@@ -294,6 +294,49 @@ __device__ inline uint64_t take_slot(uint64_t* slot) {
 // instead of the global copy.  Column and r padding rows are zero, so the
 // update keeps the padding at +0 and the FP64 norm over ld equals the norm
 // over n.
+// The launch's winner (idx, c) before the update: false, with the run
+// stopped, for an index outside the dictionary (which a published key never
+// holds) or c = 0 (no atom correlates with r: MP cannot make progress).
+__device__ inline bool winner_usable(int idx, float c, int64_t m, DevState* __restrict__ st) {
+  if (idx < 0 || idx >= m) {
+    if (threadIdx.x == 0) {
+      st->done = 1;
+      st->reason = kStopInternal;
+    }
+    return false;
+  }
+  if (c == 0.0f) {
+    if (threadIdx.x == 0) {
+      st->done = 1;
+      st->reason = MP_STOP_STALLED;
+    }
+    return false;
+  }
+  return true;
+}
+
+// Thread 0 of the last workgroup, after the update: x~_idx += c (eq. 10), the
+// trace entry, t + 1 (eq. 12), and the stopping test on the new ||r||^2.
+__device__ inline void record_step(int idx, float c, double rr, float* __restrict__ x,
+                                   DevState* __restrict__ st, const mp_trace& tr) {
+  x[idx] += c;
+  const long long t = st->t;
+  if (t < tr.cap) {
+    if (tr.idx) tr.idx[t] = idx;
+    if (tr.coef) tr.coef[t] = c;
+    if (tr.rr) tr.rr[t] = rr;
+  }
+  st->t = t + 1;
+  st->rr = rr;
+  if (!(rr > st->thr)) {
+    st->done = 1;
+    st->reason = MP_STOP_CONVERGED;
+  } else if (t + 1 >= st->max_iters) {
+    st->done = 1;
+    st->reason = MP_STOP_MAX_ITERS;
+  }
+}
+
 template <int NT>
 __device__ void select_update_tail(uint64_t best, const float* __restrict__ psi, int64_t ld,
                                    int64_t n, int64_t m, float* __restrict__ x,
@@ -301,20 +344,7 @@ __device__ void select_update_tail(uint64_t best, const float* __restrict__ psi,
                                    DevState* __restrict__ st, const mp_trace& tr, double* dred) {
   const int idx = key_index(best);
   const float c = key_value(best);
-  if (idx < 0 || idx >= m) {  // cannot happen for a key a workgroup published
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = kStopInternal;
-    }
-    return;
-  }
-  if (c == 0.0f) {  // no atom correlates with r: MP cannot make progress
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = MP_STOP_STALLED;
-    }
-    return;
-  }
+  if (!winner_usable(idx, c, m, st)) return;
   // r <- r - c psi_idx: all of this thread's column loads are issued first
   // (ld <= 16384 gives at most P float4s per thread), then the updates.
   constexpr int P = 16384 / 4 / NT > 0 ? 16384 / 4 / NT : 1;
@@ -355,24 +385,7 @@ __device__ void select_update_tail(uint64_t best, const float* __restrict__ psi,
          (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
   }
   const double rr = block_sum<NT>(s, dred);
-  if (threadIdx.x == 0) {
-    x[idx] += c;
-    const long long t = st->t;
-    if (t < tr.cap) {
-      if (tr.idx) tr.idx[t] = idx;
-      if (tr.coef) tr.coef[t] = c;
-      if (tr.rr) tr.rr[t] = rr;
-    }
-    st->t = t + 1;
-    st->rr = rr;
-    if (!(rr > st->thr)) {
-      st->done = 1;
-      st->reason = MP_STOP_CONVERGED;
-    } else if (t + 1 >= st->max_iters) {
-      st->done = 1;
-      st->reason = MP_STOP_MAX_ITERS;
-    }
-  }
+  if (threadIdx.x == 0) record_step(idx, c, rr, x, st, tr);
 }
 
 }  // namespace mp

@@ -28,7 +28,7 @@ struct alignas(64) DevState {
   int done;             // 1 once the run has stopped
   int reason;           // MP_STOP_* or kStopNonFinite
   unsigned arrive;      // workgroups of the current launch that have published a key
-  int pad0;
+  int r_sel;            // sign-bit decode: half of the residual buffer holding r (0 or 1)
   int pad[4];
 };
 
@@ -80,6 +80,21 @@ hipError_t launch_init_f64(const double* y, int64_t n, int64_t ld, double* x, in
 hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* r,
                               const CorrGeom& g, uint64_t* keys, double* x, DevState* st,
                               mp_trace_f64 tr, hipStream_t s);
+
+// ---- sign-bit Bernoulli dictionary (k_sign.hip) ------------------------------
+// Words per lane of one column load (1, 2 or 4; the column covers 2048 J rows).
+int sign_words_per_lane(int64_t n);
+hipError_t launch_tile_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int J,
+                             uint32_t* out, hipStream_t s);
+hipError_t launch_untile_signs(const uint32_t* tiles, int64_t n, int64_t m, int J, uint32_t* out,
+                               hipStream_t s);
+// Launch k of a decode (parity = k mod 2, first = k == 0): finishes iteration
+// k-1 and runs pass k.  rbuf: 2 x ld floats (r in half `parity`), keys:
+// 2 x grid slots.
+hipError_t launch_mp_step_sign(const uint32_t* tiles, int J, int64_t n, int64_t m, int64_t ld,
+                               float* rbuf, float inv_sqrt_n, const CorrGeom& g, uint64_t* keys,
+                               int parity, int first, float* x, DevState* st, mp_trace tr,
+                               hipStream_t s);
 
 // ---- Orthogonal Matching Pursuit, FP32 (k_omp.hip) --------------------------
 struct OmpState {           // the atom selected in the current iteration
@@ -188,6 +203,9 @@ struct mp_ctx {
   double* psi64 = nullptr;       // MP_F64 storage: the FP64 dictionary (same layout)
   double* r64_work = nullptr;    // MP_F64 storage: ld doubles, rows n..ld-1 stay zero
   void* psiq = nullptr;          // BF16 / FP8 copy (same layout), if any
+  uint32_t* psis = nullptr;      // MP_SIGN1 storage: sign-bit tiles, 64 sign_j words per column
+  int sign_j = 0;                // words per lane of one sign column load
+  float inv_sqrt_n = 0.0f;       // MP_SIGN1: 1/sqrt(n) rounded to FP32
   float* scales = nullptr;       // FP8 per-column scales
   // per-decode work buffers
   float* r_work = nullptr;       // ld floats, rows n..ld-1 stay zero

@@ -22,11 +22,11 @@ LIB_PATH = os.path.join(HERE, "libmp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mp.h")
 
 MP_OK, MP_EINVAL, MP_ENOTNORM, MP_ENONFINITE, MP_ENOMEM, MP_EDEVICE, MP_EUNSUPPORTED = range(7)
-MP_F32, MP_BF16, MP_FP8_E4M3, MP_F64 = 0, 1, 2, 3
+MP_F32, MP_BF16, MP_FP8_E4M3, MP_F64, MP_SIGN1 = 0, 1, 2, 3, 4
 STOP_CONVERGED, STOP_MAX_ITERS, STOP_STALLED, STOP_ZERO_INPUT = 0, 1, 2, 3
 STOP_NAMES = {0: "converged", 1: "max_iters", 2: "stalled", 3: "zero_input"}
 MP_SKIP_NORM_CHECK = 0x1
-DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3, "f64": MP_F64}
+DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3, "f64": MP_F64, "sign": MP_SIGN1}
 
 
 class Opts(ctypes.Structure):
@@ -112,6 +112,8 @@ def _load():
                                  ctypes.POINTER(Trace), p]
     lib.mp_create_f64.restype = ctypes.c_int
     lib.mp_create_f64.argtypes = [ctypes.POINTER(ctypes.c_void_p), p, i64, i64, i64, u32, p]
+    lib.mp_create_signs.restype = ctypes.c_int
+    lib.mp_create_signs.argtypes = [ctypes.POINTER(ctypes.c_void_p), p, i64, i64, i64, u32, p]
     lib.mp_solve_f64.restype = ctypes.c_int
     lib.mp_solve_f64.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
                                  ctypes.POINTER(TraceF64), p]
@@ -186,6 +188,14 @@ def mp_create_f64(psi_ptr: int, n: int, m: int, ld: int, flags: int = 0,
     h = ctypes.c_void_p()
     st = _load().mp_create_f64(ctypes.byref(h), psi_ptr, n, m, ld, flags, stream)
     _check(st, "mp_create_f64", None)
+    return h
+
+
+def mp_create_signs(signs_ptr: int, n: int, m: int, ldw: int, flags: int = 0,
+                    stream: Optional[int] = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = _load().mp_create_signs(ctypes.byref(h), signs_ptr, n, m, ldw, flags, stream)
+    _check(st, "mp_create_signs", None)
     return h
 
 
@@ -293,17 +303,31 @@ class Decoder:
 
     ``psi``: (N, M) CUDA tensor, column-major (``stride(0) == 1``): float32
     for ``storage`` ``"f32"``, ``"bf16"`` or ``"fp8"``; float64 for ``"f64"``
-    (the FP64 decode: y, x~ and r are then float64 as well).
+    (the FP64 decode: y, x~ and r are then float64 as well).  For ``"sign"``
+    (``mp_create_signs``, the Bernoulli dictionary of eq. 13 as sign bits)
+    ``psi`` is the packed bits, an (M, ldw) int32 CUDA tensor with contiguous
+    rows, and ``n`` gives N.
     """
 
     def __init__(self, psi: torch.Tensor, storage: str = "f32", check_norms: bool = True,
-                 stream=None):
+                 stream=None, n: Optional[int] = None):
         if storage not in DTYPES:
             raise ValueError(f"unknown storage {storage!r}")
         self.dtype = torch.float64 if storage == "f64" else torch.float32
+        flags = 0 if check_norms else MP_SKIP_NORM_CHECK
+        if storage == "sign":
+            if not psi.is_cuda or psi.dtype != torch.int32 or psi.dim() != 2 or psi.stride(1) != 1:
+                raise ValueError("sign bits must be an (M, ldw) int32 CUDA tensor, rows contiguous")
+            if n is None:
+                raise ValueError("storage 'sign' needs n")
+            m, ldw = psi.shape
+            self.n, self.m, self.storage = int(n), m, storage
+            ldw = psi.stride(0) if m > 1 else ldw
+            self._ctx = mp_create_signs(psi.data_ptr(), int(n), m, ldw, flags,
+                                        _stream_ptr(stream))
+            return
         n, m, ld = _check_psi(psi, self.dtype)
         self.n, self.m, self.storage = n, m, storage
-        flags = 0 if check_norms else MP_SKIP_NORM_CHECK
         if storage == "f64":
             self._ctx = mp_create_f64(psi.data_ptr(), n, m, ld, flags, _stream_ptr(stream))
         else:
@@ -412,7 +436,12 @@ class Decoder:
 
     def storage_copy(self, stream=None):
         """The dictionary copy the correlation pass streams, unpadded:
-        (codes tensor (N, M) column-major view, scales or None)."""
+        (codes tensor (N, M) column-major view, scales or None); for "sign"
+        storage the packed bits, (M, ceil(N/32)) int32, and None."""
+        if self.storage == "sign":
+            codes = torch.empty((self.m, (self.n + 31) // 32), dtype=torch.int32, device="cuda")
+            mp_get_storage(self._ctx, codes.data_ptr(), None, _stream_ptr(stream))
+            return codes, None
         dt = {"f32": torch.float32, "bf16": torch.int16, "fp8": torch.uint8,
               "f64": torch.float64}[self.storage]
         codes = torch.empty((self.m, self.n), dtype=dt, device="cuda")

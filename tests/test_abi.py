@@ -95,3 +95,29 @@ def test_f64_storage_goes_through_its_own_entry_point():
     opts = mp.Opts(1e-5, 10, 0, 0)
     assert mp.library().mp_solve_f64(None, 1, 1, None, ctypes.byref(opts), None, None,
                                      None) == mp.MP_EINVAL
+
+
+@pytest.mark.parametrize("kw,detail", [
+    (dict(signs=None), "signs is NULL"),
+    (dict(n=0), "n and m"),
+    (dict(m=0), "n and m"),
+    (dict(n=8193, ldw=300), "8192"),
+    (dict(n=33, ldw=1), "ldw must be"),
+    (dict(m=2 ** 31), "2^31"),
+    (dict(flags=0x10), "flags"),
+])
+def test_create_signs_rejects_bad_arguments(kw, detail):
+    args = dict(signs=0x1000, n=64, m=4, ldw=2, flags=0)
+    args.update(kw)
+    h = ctypes.c_void_p(123)
+    st = mp.library().mp_create_signs(ctypes.byref(h), args["signs"], args["n"], args["m"],
+                                      args["ldw"], args["flags"], None)
+    assert st == mp.MP_EINVAL
+    assert h.value is None
+    assert detail in mp.mp_last_error(None)
+
+
+def test_sign_storage_goes_through_its_own_entry_point():
+    h = ctypes.c_void_p(123)
+    st = mp.library().mp_create(ctypes.byref(h), 0x1000, 4, 4, 4, mp.MP_SIGN1, 0, None)
+    assert st == mp.MP_EINVAL and "mp_create_signs" in mp.mp_last_error(None)
