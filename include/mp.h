@@ -239,28 +239,31 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
  * mp_create_signs -- a context for the paper's own dictionary, the Bernoulli
  * matrix of eq. 13 (entries +-1/sqrt(N), every column of unit norm), held as
  * one sign bit per entry: psi_nm = (1 - 2 b_nm) / sqrt(N).  Decoded with
- * mp_solve (FP32 y, x~ and r, as for MP_F32 storage): the correlation
- * c_m = (sum_n (1 - 2 b_nm) r_n) / sqrt(N) is an FP32 signed sum scaled by
- * fp32(1/sqrt(N)), and the update r_n -= c psi_nm adds or subtracts
- * fp32(c / sqrt(N)).  The dictionary pass reads N/8 bytes per column instead
- * of 4N.  The context has storage MP_SIGN1; mp_solve_batched and
- * mp_solve_omp return MP_EINVAL for it.
+ * mp_solve (FP32 y, x~ and r, as for MP_F32 storage).  The decode is the
+ * Section 3 loop with the correlations carried from step to step: two
+ * columns' inner product is (N - 2 popcount(b_i XOR b_m)) / N, exact, so
+ * after selecting (i, c*) every c_m drops by c* <psi_i, psi_m> (eq. 9 applied
+ * to eq. 11's r).  The correlations and r are kept in FP64 (c at the start is
+ * Psi^T y in FP64), so the selections follow the exact iteration closely;
+ * x~ accumulates fp32(c*) and r is returned rounded to FP32.  A pass reads
+ * N/8 bytes per column instead of 4N.  The context has storage MP_SIGN1;
+ * mp_solve_batched and mp_solve_omp return MP_EINVAL for it.
  *
  *   out      host: receives the new context (set to NULL on failure)
  *   signs    device: packed bits, column m in words [m ldw, m ldw + ldw);
  *            bit q of word w is b_nm for row n = 32 w + q (1: -1/sqrt(N),
  *            0: +1/sqrt(N)); bits of rows n >= N are ignored
- *   n, m     1 <= N <= 8192, 1 <= M < 2^31
+ *   n, m     1 <= N <= 16384, 1 <= M < 2^31
  *   ldw      words per column, ldw >= ceil(N / 32)
  *   flags    0 or MP_SKIP_NORM_CHECK (no effect: the columns have unit norm
  *            by construction)
  *   stream   hipStream_t as void*
  *
- * The context keeps its own copy of the bits (re-arranged for the pass); the
- * caller may free signs when the call returns.  mp_get_storage returns the
- * bits in the packed form above with ldw = ceil(N / 32).  Errors: MP_EINVAL
- * (NULL, n or m out of range, ldw too small, unknown flags), MP_ENOMEM,
- * MP_EDEVICE, MP_EUNSUPPORTED (not a gfx950 device).
+ * The context keeps its own copy of the bits; the caller may free signs when
+ * the call returns.  mp_get_storage returns the bits in the packed form above
+ * with ldw = ceil(N / 32).  Errors: MP_EINVAL (NULL, n or m out of range, ldw
+ * too small, unknown flags), MP_ENOMEM, MP_EDEVICE, MP_EUNSUPPORTED (not a
+ * gfx950 device).
  */
 mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_t m, int64_t ldw,
                           uint32_t flags, void* stream);

@@ -14,6 +14,7 @@
 // RMW-only protocol as the FP32 form, and that workgroup updates x~ and r and
 // applies the FP64 stopping test.
 #include "k_common.h"
+#include "k_key2.h"
 #include "mp_internal.h"
 
 namespace mp {
@@ -22,64 +23,6 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int kF64Threads = 1024;
 constexpr int kF64Waves = kF64Threads / kWave;
-
-// ---- candidate pairs ----------------------------------------------------------
-
-struct Key2 {
-  uint64_t hi;  // |c| bits, sign cleared (NaN mapped to 0)
-  uint64_t lo;  // (0x7FFFFFFF - index) << 1 | sign of c; 0 = empty
-};
-
-__device__ inline Key2 make_key2(double c, int idx) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, c);
-  uint64_t ab = u & 0x7FFFFFFFFFFFFFFFull;
-  if (ab > 0x7FF0000000000000ull) ab = 0;
-  return Key2{ab, (static_cast<uint64_t>(0x7FFFFFFFu - static_cast<uint32_t>(idx)) << 1) |
-                      (u >> 63)};
-}
-__device__ inline int key2_index(const Key2& k) {
-  return static_cast<int>(0x7FFFFFFFu - (static_cast<uint32_t>(k.lo) >> 1));
-}
-__device__ inline double key2_value(const Key2& k) {
-  return __builtin_bit_cast(double, k.hi | ((k.lo & 1ull) << 63));
-}
-__device__ inline bool key2_greater(const Key2& a, const Key2& b) {
-  return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
-}
-__device__ inline Key2 key2_max(const Key2& a, const Key2& b) {
-  return key2_greater(b, a) ? b : a;
-}
-
-template <int CTRL>
-__device__ inline Key2 dpp_key2(const Key2& k) {
-  return Key2{dpp_u64<CTRL>(k.hi), dpp_u64<CTRL>(k.lo)};
-}
-__device__ inline Key2 lane_key2(const Key2& k, int l) {
-  return Key2{lane_u64(k.hi, l), lane_u64(k.lo, l)};
-}
-
-// Wave-uniform maximum pair (the DPP pattern of wave_max).
-__device__ inline Key2 wave_max_key2(Key2 k) {
-  k = key2_max(k, dpp_key2<kDppQuadSwap1>(k));
-  k = key2_max(k, dpp_key2<kDppQuadSwap2>(k));
-  k = key2_max(k, dpp_key2<kDppRowRor4>(k));
-  k = key2_max(k, dpp_key2<kDppRowRor8>(k));
-  return key2_max(key2_max(lane_key2(k, 0), lane_key2(k, 16)),
-                  key2_max(lane_key2(k, 32), lane_key2(k, 48)));
-}
-
-// Workgroup-wide maximum pair; every thread receives it.  `red` holds
-// kF64Waves pairs of LDS.
-__device__ inline Key2 block_max_key2(Key2 k, Key2* red) {
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  k = wave_max_key2(k);
-  if (lane == 0) red[wave] = k;
-  __syncthreads();
-  Key2 s = lane < kF64Waves ? red[lane] : Key2{0, 0};
-  s = wave_max_key2(s);
-  __syncthreads();
-  return s;
-}
 
 // ---- FP64 inner product of one column with the LDS copy of r -----------------
 //
@@ -207,7 +150,7 @@ __global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
         dot_column_f64(reinterpret_cast<const v2d*>(psi + col * ld), r2_lds, ld2, lane);
     best = key2_max(best, make_key2(c, static_cast<int>(col)));
   }
-  best = block_max_key2(best, kred);
+  best = block_max_key2<kF64Threads>(best, kred);
   // lane 0 of wave 0 publishes the |c| word, lane 1 the index word
   if (!publish_arrive<2>(lane == 0 ? best.hi : best.lo, keys, st)) return;
 
@@ -217,7 +160,7 @@ __global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
     const Key2 k{take_slot(keys + 2 * i), take_slot(keys + 2 * i + 1)};
     w = key2_max(w, k);
   }
-  w = block_max_key2(w, kred);
+  w = block_max_key2<kF64Threads>(w, kred);
   const int idx = key2_index(w);
   const double c = key2_value(w);
   if (w.lo == 0 || idx < 0 || idx >= m) {  // cannot happen for a published pair

@@ -1,375 +1,364 @@
 // Matching Pursuit on the Bernoulli dictionary of eq. 13 held as one sign bit
 // per entry, for gfx950.
 //
-// psi_nm = (1 - 2 b_nm) / sqrt(N).  With the signs s_nm = 1 - 2 b_nm the
-// correlation of eq. 9 is c_m = (sum_n s_nm r_n) / sqrt(N): no products, and
-// a column is N bits instead of 4N bytes, so the pass reads 32x less than the
-// FP32 one and is bound by the arithmetic instead of HBM.
+// psi_nm = (1 - 2 b_nm) / sqrt(N), so the inner product of two columns is an
+// integer over N: <psi_i, psi_m> = (N - 2 popcount(b_i XOR b_m)) / N.  The
+// correlations are therefore carried from step to step instead of being
+// recomputed from r: with r_k = r_{k-1} - c* psi_idx (eq. 11), eq. 9 gives
+//   c_m(k) = <r_k, psi_m> = c_m(k-1) - c* <psi_idx, psi_m>,
+// one XOR and one bit count per 32 rows, the Gram entry exact.  The carried
+// correlations and r are FP64 (after t steps the carried c stays within about
+// t 2^-53 |y| of a recomputation); c(0) = Psi^T y is computed once per
+// decode, in FP64, by k_sign_c0.  A pass reads N/8 bytes per column.
 //
-// Signed sums by table look-up.  Rows are taken in groups of four; for every
-// group g each workgroup tabulates in LDS the 16 signed sums
-//   T_g[b] = sum_{k<4} (bit k of b set ? -r_{4g+k} : +r_{4g+k}),
-// after which a column's signed sum is one LDS read and one add per four rows:
-//   sum_n s_nm r_n = sum_g T_g[nibble g of column m].
+// Storage: column m is ws words at m ws (ws = ceil(N/32) rounded up to a
+// multiple of 4); bit q of word w is row 32 w + q; bits of rows >= N are
+// zero.  The wave that handles a column reads it in 16-byte chunks, lane l
+// taking chunks l, l + 64, ... (CPL of them), and reads the winning column
+// the same way, so the XOR pairs words of the same rows.
 //
-// Layout of the sign bits (built once by k_tile_signs from the packed input):
-// the wave that handles a column reads all of it with one load of J words
-// per lane (J = 1, 2 or 4; N <= 2048 J).  Nibble k of lane l's word j holds
-// the four bits of group g = l + 64 (8 j + k), bit i of the nibble being row
-// 4 g + i.  The table is stored plane by plane, T_g[b] at b G + g with
-// G = 512 J: every group a lane looks up is congruent to the lane mod 64 and
-// G is a multiple of 64, so the 64 reads of a look-up fall in 64 different
-// LDS banks whatever the nibbles are.
-//
-// One MP iteration is one launch; the selection of a pass is made at the
-// start of the next launch, by every workgroup alike (see k_mp_step_sign).
+// One launch per iteration, with the selection carried into the next launch
+// so that no workgroup waits for another inside a launch.  Launch k:
+//  1. reads the pair keys and the partial squared norms of r published by
+//     launch k-1 (one of each per workgroup; the kernel boundary orders
+//     them), sums the norms and runs the stop test for the k-1 steps taken
+//     (||r||^2 <= eps^2 ||y||^2, or k-1 = T), then takes the largest key,
+//     (idx, c*), as step k; every workgroup reaches the same result;
+//  2. updates its columns' c_m with the Gram column of idx, stores them and
+//     stores its best new key;
+//  3. updates its own slice of rows of r in FP64 (r_n -/+ c*/sqrt(N)) and
+//     stores the slice's partial ||r||^2;
+//  4. in workgroup 0 only: x~_idx += c* (eq. 10), the trace entries and the
+//     state (t, ||r||^2, stop reason).
+// Keys and partial norms alternate between two halves by launch parity.  The
+// first launch of a decode publishes the keys of c(0) and the norms of r = y;
+// T steps take T+2 launches.  After the stop every launch returns at once.
 #include "k_common.h"
+#include "k_key2.h"
 #include "mp_internal.h"
 
 namespace mp {
 
 constexpr int kSignThreads = 1024;
 constexpr int kSignWaves = kSignThreads / kWave;
-constexpr int kSignBatch = 8;  // columns a wave loads before it sums them
-
-typedef unsigned v2u __attribute__((ext_vector_type(2)));
+// Columns a wave handles at once: the same 128 bytes per lane in flight
+// whatever the column length.
+template <int CPL>
+constexpr int kSignBatch = 8 / CPL;
 
 // ---------------------------------------------------------------------------
-// Set-up: packed input (column m: ldw words, bit q of word w = row 32 w + q)
-// -> lane-interleaved tiles (column m: 64 J words, lane l's J words together).
-// Bits of rows >= n are cleared.
-__global__ __launch_bounds__(256) void k_tile_signs(const uint32_t* __restrict__ in, int64_t ldw,
-                                                    int n, int64_t m, int J,
+// Set-up: the caller's packed bits (column m: ldw words) into the padded
+// layout, bits of rows >= n cleared.
+__global__ __launch_bounds__(256) void k_copy_signs(const uint32_t* __restrict__ in, int64_t ldw,
+                                                    int n, int64_t m, int64_t ws,
                                                     uint32_t* __restrict__ out) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t per_col = 64 * J;
-  if (i >= m * per_col) return;
-  const int64_t col = i / per_col;
-  const int rem = static_cast<int>(i % per_col);
-  const int l = rem / J, j = rem % J;
-  const uint32_t* src = in + col * ldw;
-  uint32_t w = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int row = 4 * (l + 64 * (8 * j + k));
-    if (row >= n) continue;
-    uint32_t nib = (src[row >> 5] >> (row & 31)) & 0xFu;  // a group never straddles a word
-    if (n - row < 4) nib &= (1u << (n - row)) - 1u;
-    w |= nib << (4 * k);
-  }
-  out[i] = w;
-}
-
-// The reverse, for mp_get_storage: tiles -> packed (ceil(n/32) words per column).
-__global__ __launch_bounds__(256) void k_untile_signs(const uint32_t* __restrict__ tiles, int n,
-                                                      int64_t m, int J,
-                                                      uint32_t* __restrict__ out) {
-  const int64_t words = (n + 31) / 32;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= m * words) return;
-  const int64_t col = i / words;
-  const int w = static_cast<int>(i % words);
-  const uint32_t* src = tiles + col * 64 * J;
+  if (i >= m * ws) return;
+  const int64_t col = i / ws;
+  const int w = static_cast<int>(i % ws);
+  const int row = 32 * w;
   uint32_t v = 0;
-#pragma unroll
-  for (int q = 0; q < 32; q += 4) {
-    const int row = 32 * w + q;
-    if (row >= n) break;
-    const int g = row >> 2, t = g >> 6;
-    v |= ((src[(g & 63) * J + (t >> 3)] >> (4 * (t & 7))) & 0xFu) << q;
+  if (row < n) {
+    v = in[col * ldw + w];
+    if (n - row < 32) v &= (1u << (n - row)) - 1u;
   }
   out[i] = v;
 }
 
+// Integer sum over the wave (exact; every lane receives it).
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+  v += dpp_u32<kDppQuadSwap1>(v);
+  v += dpp_u32<kDppQuadSwap2>(v);
+  v += dpp_u32<kDppRowMirror>(v);
+  v += dpp_u32<kDppRowHalfMirror>(v);
+  v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), 16, kWave));
+  v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), 32, kWave));
+  return v;
+}
+
+// Rows of a 16-byte chunk whose signs differ between two columns.
+__device__ inline uint32_t disagree(const v4u& a, const v4u& b) {
+  return __builtin_popcount(a.x ^ b.x) + __builtin_popcount(a.y ^ b.y) +
+         __builtin_popcount(a.z ^ b.z) + __builtin_popcount(a.w ^ b.w);
+}
+
 // ---------------------------------------------------------------------------
-template <int J>
-__device__ inline void load_sign_words(const uint32_t* __restrict__ p, uint32_t (&w)[J]) {
-  if constexpr (J == 4) {
-    const v4u v = *reinterpret_cast<const v4u*>(p);
-    w[0] = v.x;
-    w[1] = v.y;
-    w[2] = v.z;
-    w[3] = v.w;
-  } else if constexpr (J == 2) {
-    const v2u v = *reinterpret_cast<const v2u*>(p);
-    w[0] = v.x;
-    w[1] = v.y;
-  } else {
-    w[0] = *p;
+// c(0)_m = <y, psi_m> = (sum_n (1 - 2 b_nm) y_n) / sqrt(N) in FP64 for every
+// column (eq. 9 at t = 0), and r = y in FP64.  One wave per column; lane l
+// sums the rows of its chunks in increasing order, then the wave sums the
+// lanes.  y is staged in LDS (32 ws floats, zero past n).
+constexpr int kC0Threads = 256;
+__global__ __launch_bounds__(kC0Threads) void k_sign_c0(const uint32_t* __restrict__ bits,
+                                                        int64_t ws, int n, int64_t m,
+                                                        const float* __restrict__ y,
+                                                        double inv_sqrt_n, int64_t ld,
+                                                        double* __restrict__ c64,
+                                                        double* __restrict__ r64) {
+  extern __shared__ float y_lds[];
+  const int rows = static_cast<int>(32 * ws);
+  for (int i = threadIdx.x; i < rows; i += kC0Threads) y_lds[i] = i < n ? y[i] : 0.0f;
+  if (blockIdx.x == 0)
+    for (int64_t i = threadIdx.x; i < ld; i += kC0Threads)
+      r64[i] = i < n ? static_cast<double>(y[i]) : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x % kWave;
+  const int nch = static_cast<int>(ws / 4);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * (kC0Threads / kWave);
+  for (int64_t col = static_cast<int64_t>(blockIdx.x) * (kC0Threads / kWave) +
+                     threadIdx.x / kWave;
+       col < m; col += stride) {
+    const v4u* p = reinterpret_cast<const v4u*>(bits + col * ws);
+    double acc = 0.0;
+    for (int ch = lane; ch < nch; ch += kWave) {
+      const v4u w = p[ch];
+      const uint32_t word[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row0 = 128 * ch + 32 * q;
+#pragma unroll 8
+        for (int b = 0; b < 32; ++b) {
+          const double v = static_cast<double>(y_lds[row0 + b]);
+          acc += ((word[q] >> b) & 1u) ? -v : v;
+        }
+      }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) c64[col] = acc * inv_sqrt_n;
   }
 }
 
-// One launch per MP iteration, with the selection carried into the next
-// launch so that no workgroup hands off to another inside a launch.  Launch k
-// finishes iteration k-1 and runs the correlation pass of iteration k:
-//  1. every workgroup reads the keys of pass k-1 (one per workgroup, stored
-//     by launch k-1; the kernel boundary orders them) and r_{k-1}; all take
-//     the same winner, the largest key, and compute the same
-//     r_k = r_{k-1} - c psi_idx (eq. 11: r_n -/+ c / sqrt(N)) for every row;
-//  2. workgroup 0 alone stores r_k for launch k+1, adds c to x~_idx
-//     (eq. 10), writes the trace entry, counts t (eq. 12) and runs the stop
-//     test on ||r_k||^2 in FP64, with every value it reads requested
-//     together with the launch's first loads or the winner's bits;
-//  3. every workgroup builds the table from r_k, runs the pass over its
-//     columns and stores its best key for launch k+1.
-// r and the keys alternate between two halves by launch parity.  The first
-// launch of a decode has no pass to finish (`first`).  After the stop every
-// launch returns at once; in the launch that sets it, the other workgroups
-// may still run a pass whose keys are never read.
-//
-// Workgroup b takes columns [b cols_per_wg, (b+1) cols_per_wg); wave w of it
-// the columns w, w+16, ... of that range, kSignBatch at a time (past the
-// range's end the last column is read again, which leaves the maximum
-// unchanged).  `width` is always 4, the nibble width: taken as an argument it
-// keeps each nibble read a single bit-field extract, which the address add
-// can then absorb (with a constant width the compiler splits it into a shift
-// and a mask).
-template <int J>
+// ---------------------------------------------------------------------------
+template <int CPL>
 __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
-    const uint32_t* __restrict__ tiles, int n, int64_t m, int64_t ld, float* __restrict__ rbuf,
-    float inv_sqrt_n, int cols_per_wg, unsigned width, uint64_t* __restrict__ keys, int parity,
-    int first, float* __restrict__ x, DevState* __restrict__ st, mp_trace tr) {
-  constexpr int G = 512 * J;  // groups of four rows covered by one column load
-  constexpr int GPT = (G + kSignThreads - 1) / kSignThreads;  // groups per thread
-  extern __shared__ float lut[];  // 16 planes of G floats
-  __shared__ uint64_t kred[kSignWaves];
+    const uint32_t* __restrict__ bits, int64_t ws, int n, int64_t m, int64_t ld,
+    double* __restrict__ c64, double* __restrict__ r64, float* __restrict__ r32,
+    double* __restrict__ rrp, double inv_n, double inv_sqrt_n, int cols_per_wg, int rows_per_wg,
+    uint64_t* __restrict__ keys, long long k, long long max_iters, double thr,
+    float* __restrict__ x, DevState* __restrict__ st, mp_trace tr) {
+  __shared__ Key2 kred[kSignWaves];
   __shared__ double dred[kSignWaves];
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  __shared__ int s_done;
+  constexpr int B = kSignBatch<CPL>;
+  const int lane = threadIdx.x % kWave;
+  // the wave index as a wave-uniform value, so that per-column values sit in
+  // scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
   const int64_t col1 = col0 + cols_per_wg < m ? col0 + cols_per_wg : m;
-  const int64_t step = kSignWaves * kSignBatch;
-  const int ld4 = static_cast<int>(ld / 4);  // r: ld floats, rows >= n zero
-  const v4f* r_in = reinterpret_cast<const v4f*>(rbuf + (parity ? ld : 0));
-  v4f* r_out = reinterpret_cast<v4f*>(rbuf + (parity ? 0 : ld));
-  const uint64_t* k_in = keys + (parity ? gridDim.x : 0);
-  uint64_t* k_out = keys + (parity ? 0 : gridDim.x);
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * rows_per_wg;  // this workgroup's rows
+  const int64_t row1 = row0 + rows_per_wg < ld ? row0 + rows_per_wg : ld;
+  const int nch = static_cast<int>(ws / 4);  // 16-byte chunks per column
+  const int nk = static_cast<int>(gridDim.x);
+  const int par = static_cast<int>(k & 1);
+  const bool first = k == 0;
+  const uint64_t* k_in = keys + (par ? 2 * nk : 0);
+  uint64_t* k_out = keys + (par ? 0 : 2 * nk);
+  const double* rr_in = rrp + (par ? nk : 0);
+  double* rr_out = rrp + (par ? 0 : nk);
 
-  // Requests first, all of them unconditional (clamped indices into valid
-  // memory; what lies outside is zeroed afterwards), so none waits for
-  // another: the stop flag, r_{k-1} for this thread's groups (g = i + 1024 t,
-  // rows 4g..4g+3), the previous pass's keys and the first batch of columns.
-  // The flag is broadcast from thread 0, so the whole workgroup sees one
-  // value even in the launch in which workgroup 0 sets it.
-  __shared__ int s_done;
+  // Requests first, all unconditional (clamped indices into valid memory;
+  // what lies outside is discarded afterwards), so none waits for another.
+  // The small ones go first, ahead of the columns' bits that every
+  // workgroup requests at once: the stop flag, the previous keys and partial
+  // norms, this wave's c and (wave 0) this workgroup's rows of r, then the
+  // bits.
   const int done_v = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // workgroup 0 keeps the run's state: what its bookkeeping reads, now
-  long long st_t = 0, st_max = 0;
-  double st_thr = 0.0;
-  if (blockIdx.x == 0) {
-    st_t = st->t;
-    st_max = st->max_iters;
-    st_thr = st->thr;
-  }
-  v4f q[GPT];
+  const int ki = static_cast<int>(threadIdx.x) < nk ? static_cast<int>(threadIdx.x) : nk - 1;
+  Key2 kp{k_in[2 * ki], k_in[2 * ki + 1]};
+  double rrq = rr_in[ki];
+  double cm[B];
+  int64_t colu[B];
 #pragma unroll
-  for (int t = 0; t < GPT; ++t) {
-    const int g = threadIdx.x + t * kSignThreads;
-    q[t] = r_in[g < ld4 ? g : ld4 - 1];
+  for (int u = 0; u < B; ++u) {
+    const int64_t col = col0 + wave + u * kSignWaves;
+    colu[u] = col < col1 ? col : col1 - 1;
+    cm[u] = c64[colu[u]];
   }
-  const int nkeys = static_cast<int>(gridDim.x);  // <= kSignThreads
-  uint64_t kprev = k_in[static_cast<int>(threadIdx.x) < nkeys ? threadIdx.x : nkeys - 1];
-  uint32_t w[kSignBatch][J];
-  int64_t cb = col0 + wave;
+  // wave 0: r_{k-1} of this workgroup's first 64 rows, one per lane
+  double rq0 = 0.0;
+  if (wave == 0) {
+    const int64_t i = row0 + lane < ld ? row0 + lane : ld - 1;
+    rq0 = r64[i];
+  }
+  v4u wb[B][CPL];
 #pragma unroll
-  for (int u = 0; u < kSignBatch; ++u) {
-    int64_t col = cb + u * kSignWaves;
-    col = col < col1 ? col : col1 - 1;
-    load_sign_words<J>(tiles + col * 64 * J + lane * J, w[u]);
+  for (int u = 0; u < B; ++u) {
+    const v4u* p = reinterpret_cast<const v4u*>(bits + colu[u] * ws);
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int ch = lane + kWave * cc;
+      wb[u][cc] = p[ch < nch ? ch : nch - 1];
+    }
+  }
+  if (first || static_cast<int>(threadIdx.x) >= nk) {
+    kp = Key2{0, 0};
+    rrq = 0.0;
   }
 #pragma unroll
-  for (int t = 0; t < GPT; ++t)
-    if (threadIdx.x + t * kSignThreads >= ld4) q[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-  if (first || static_cast<int>(threadIdx.x) >= nkeys) kprev = 0;
+  for (int u = 0; u < B; ++u)
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc)
+      if (lane + kWave * cc >= nch) wb[u][cc] = v4u{0u, 0u, 0u, 0u};
+  // one value of the flag for the whole workgroup, even in the launch in
+  // which workgroup 0 sets it
   if (threadIdx.x == 0) s_done = done_v;
   __syncthreads();
   if (s_done) return;
+
+  int idx = -1;
+  double cs = 0.0;
+  uint32_t wrow0 = 0;
   if (!first) {
-    // finish iteration k-1: the winner, then r_k in registers
-    const uint64_t win = block_max<kSignThreads>(kprev, kred);
-    const int idx = key_index(win);
-    const float c = key_value(win);
-    if (idx < 0 || idx >= m || c == 0.0f) {  // c = 0: no atom correlates with r
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->done = 1;
-        st->reason = (idx < 0 || idx >= m) ? kStopInternal : MP_STOP_STALLED;
-      }
-      return;
-    }
-    const float a = c * inv_sqrt_n;
-    const uint32_t* wc = tiles + static_cast<int64_t>(idx) * 64 * J;
-    const float x_old = blockIdx.x == 0 ? x[idx] : 0.0f;  // requested with the winner's bits
-    uint32_t word[GPT];
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) {
-      int g = threadIdx.x + t * kSignThreads;
-      g = g < ld4 ? g : ld4 - 1;  // rows past ld are not updated below
-      word[t] = wc[(g & 63) * J + ((g >> 6) >> 3)];
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) {
-      const int g = threadIdx.x + t * kSignThreads;
-      if (g < ld4) {
-        const uint32_t nib = word[t] >> (4 * ((g >> 6) & 7));
-        const int row = 4 * g;
-        v4f o;
-        o.x = row + 0 < n ? ((nib & 1u) ? q[t].x + a : q[t].x - a) : 0.0f;
-        o.y = row + 1 < n ? ((nib & 2u) ? q[t].y + a : q[t].y - a) : 0.0f;
-        o.z = row + 2 < n ? ((nib & 4u) ? q[t].z + a : q[t].z - a) : 0.0f;
-        o.w = row + 3 < n ? ((nib & 8u) ? q[t].w + a : q[t].w - a) : 0.0f;
-        q[t] = o;
-        s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
-             (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
-      }
-    }
-    if (blockIdx.x == 0) {
-      // r_k for the next launch, x~_idx += c (eq. 10), the trace entry,
-      // t + 1 (eq. 12) and the stop test on the FP64 ||r_k||^2
-#pragma unroll
-      for (int t = 0; t < GPT; ++t) {
-        const int g = threadIdx.x + t * kSignThreads;
-        if (g < ld4) r_out[g] = q[t];
-      }
-      const double rr = block_sum<kSignThreads>(s, dred);
-      if (threadIdx.x == 0) {
-        x[idx] = x_old + c;
-        if (st_t < tr.cap) {
-          if (tr.idx) tr.idx[st_t] = idx;
-          if (tr.coef) tr.coef[st_t] = c;
-          if (tr.rr) tr.rr[st_t] = rr;
-        }
-        st->t = st_t + 1;
+    // Step k-1's residual: the stop test of the loop (the same sum, and so
+    // the same decision, in every workgroup), then step k's atom.
+    const double rr = block_sum<kSignThreads>(rrq, dred);
+    const long long t = k - 1;  // steps taken so far
+    const Key2 win = block_max_key2<kSignThreads>(kp, kred);
+    idx = key2_index(win);
+    cs = key2_value(win);
+    int stop = -1;
+    if (t > 0 && !(rr > thr)) stop = MP_STOP_CONVERGED;
+    else if (t >= max_iters) stop = MP_STOP_MAX_ITERS;
+    else if (idx < 0 || idx >= m) stop = kStopInternal;
+    else if (cs == 0.0) stop = MP_STOP_STALLED;  // no atom correlates with r
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (t > 0) {
+        if (t - 1 < tr.cap && tr.rr) tr.rr[t - 1] = rr;
         st->rr = rr;
-        st->r_sel = parity ^ 1;
-        if (!(rr > st_thr)) {
-          st->reason = MP_STOP_CONVERGED;
-          st->done = 1;
-        } else if (st_t + 1 >= st_max) {
-          st->reason = MP_STOP_MAX_ITERS;
-          st->done = 1;
+      }
+      st->t = t;
+      if (stop != -1) {
+        st->reason = stop;
+        st->done = 1;
+      } else {
+        x[idx] += static_cast<float>(cs);
+        if (t < tr.cap) {
+          if (tr.idx) tr.idx[t] = idx;
+          if (tr.coef) tr.coef[t] = static_cast<float>(cs);
         }
       }
     }
-  } else if (blockIdx.x == 0) {
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) {
-      const int g = threadIdx.x + t * kSignThreads;
-      if (g < ld4) r_out[g] = q[t];
+    if (stop != -1) return;
+
+    // the winning column, chunk by chunk as this lane holds the others (and
+    // in wave 0 the word of its first row)
+    const v4u* pw = reinterpret_cast<const v4u*>(bits + static_cast<int64_t>(idx) * ws);
+    if (wave == 0) {
+      const int64_t i = row0 + lane < ld ? row0 + lane : ld - 1;
+      wrow0 = bits[static_cast<int64_t>(idx) * ws + (i >> 5)];
     }
-    if (threadIdx.x == 0) st->r_sel = parity ^ 1;
+    v4u wv[CPL];
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int ch = lane + kWave * cc;
+      wv[cc] = pw[ch < nch ? ch : nch - 1];
+    }
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc)
+      if (lane + kWave * cc >= nch) wv[cc] = v4u{0u, 0u, 0u, 0u};
+
+    // c_m -= c* (N - 2 p_m) / N with p_m = popcount(b_idx XOR b_m); two
+    // columns' counts share one 32-bit sum (each is at most N < 2^16)
+    const double a = cs * inv_n;
+#pragma unroll
+    for (int u = 0; u < B; u += 2) {
+      uint32_t pa = 0, pb = 0;
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        pa += disagree(wb[u][cc], wv[cc]);
+        pb += disagree(wb[u + 1][cc], wv[cc]);
+      }
+      const uint32_t sum = wave_sum_u32(pa | (pb << 16));
+      cm[u] = __builtin_fma(-a, static_cast<double>(n - 2 * static_cast<int>(sum & 0xFFFFu)),
+                            cm[u]);
+      cm[u + 1] = __builtin_fma(-a, static_cast<double>(n - 2 * static_cast<int>(sum >> 16)),
+                                cm[u + 1]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (col0 + wave + u * kSignWaves < col1) c64[colu[u]] = cm[u];
+    }
   }
 
-  // T_g[b] from r_k: bits 0 and 1 of b sign rows 4g and 4g+1 (pa), bits 2
-  // and 3 rows 4g+2 and 4g+3 (pb)
-#pragma unroll
-  for (int t = 0; t < GPT; ++t) {
-    const int g = threadIdx.x + t * kSignThreads;
-    if (g < G) {
-      const v4f v = q[t];
-      const float pa[4] = {v.x + v.y, v.y - v.x, v.x - v.y, -(v.x + v.y)};
-      const float pb[4] = {v.z + v.w, v.w - v.z, v.z - v.w, -(v.z + v.w)};
-#pragma unroll
-      for (int b = 0; b < 16; ++b) lut[b * G + g] = pa[b & 3] + pb[b >> 2];
+  // Wave 0: this workgroup's rows of r (r_k = r_{k-1} -/+ c* / sqrt(N), rows
+  // with a set bit get +, FP64) and their partial ||r_k||^2 for the next
+  // launch's stop test; the first launch publishes the partials of r = y.
+  if (wave == 0) {
+    const double step = cs * inv_sqrt_n;
+    const uint32_t* pw = bits + static_cast<int64_t>(idx < 0 ? 0 : idx) * ws;
+    double s = 0.0;
+    for (int64_t i = row0 + lane; i < row1; i += kWave) {
+      const bool lead = i == row0 + lane;
+      double v = lead ? rq0 : r64[i];
+      if (!first && i < n) {
+        const uint32_t w = lead ? wrow0 : pw[i >> 5];
+        v = ((w >> (i & 31)) & 1u) ? v + step : v - step;
+        r64[i] = v;
+        r32[i] = static_cast<float>(v);
+      }
+      s += v * v;
     }
+    s = wave_sum(s);
+    if (lane == 0) rr_out[blockIdx.x] = s;
   }
-  __syncthreads();
 
-  // look-up address of nibble value v for this lane: v * 4G bytes (the plane)
-  // + 4 * lane (its bank); the group's offset 256 (8j + k) is a constant
-  const uint32_t lane4 = 4u * static_cast<uint32_t>(lane);
-  const char* lut_b = reinterpret_cast<const char*>(lut);
-  uint64_t best = 0;
-  while (cb < col1) {
-    float acc[kSignBatch];
+  // this workgroup's best key for the next launch (a column read twice past
+  // the range's end gives the same key twice)
+  Key2 best{0, 0};
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-#pragma unroll
-        for (int u = 0; u < kSignBatch; ++u) {
-          const uint32_t nib = __builtin_amdgcn_ubfe(w[u][j], 4 * k, width);
-          const uint32_t off = nib * (4u * G) + lane4;
-          const float v = *reinterpret_cast<const float*>(lut_b + off + 256 * (8 * j + k));
-          acc[u] = (j == 0 && k == 0) ? v : acc[u] + v;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kSignBatch; ++u) {
-      int64_t col = cb + u * kSignWaves;
-      col = col < col1 ? col : col1 - 1;
-      const uint64_t key = make_key(wave_sum(acc[u]) * inv_sqrt_n, static_cast<int>(col));
-      best = key > best ? key : best;
-    }
-    cb += step;
-    if (cb < col1) {
-#pragma unroll
-      for (int u = 0; u < kSignBatch; ++u) {
-        int64_t col = cb + u * kSignWaves;
-        col = col < col1 ? col : col1 - 1;
-        load_sign_words<J>(tiles + col * 64 * J + lane * J, w[u]);
-      }
-    }
+  for (int u = 0; u < B; ++u)
+    best = key2_max(best, make_key2(cm[u], static_cast<int>(colu[u])));
+  best = block_max_key2<kSignThreads>(best, kred);
+  if (threadIdx.x == 0) {
+    k_out[2 * blockIdx.x] = best.hi;
+    k_out[2 * blockIdx.x + 1] = best.lo;
   }
-  best = block_max<kSignThreads>(best, kred);
-  if (threadIdx.x == 0) k_out[blockIdx.x] = best;
 }
 
-int sign_words_per_lane(int64_t n) { return n <= 2048 ? 1 : (n <= 4096 ? 2 : 4); }
+int sign_chunks_per_lane(int64_t n) { return n <= 8192 ? 1 : 2; }
 
-hipError_t launch_tile_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int J,
+hipError_t launch_copy_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int64_t ws,
                              uint32_t* out, hipStream_t s) {
-  const int64_t total = m * 64 * J;
-  k_tile_signs<<<dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s>>>(
-      in, ldw, static_cast<int>(n), m, J, out);
+  const int64_t total = m * ws;
+  k_copy_signs<<<dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s>>>(
+      in, ldw, static_cast<int>(n), m, ws, out);
   return hipGetLastError();
 }
 
-hipError_t launch_untile_signs(const uint32_t* tiles, int64_t n, int64_t m, int J, uint32_t* out,
-                               hipStream_t s) {
-  const int64_t total = m * ((n + 31) / 32);
-  k_untile_signs<<<dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s>>>(
-      tiles, static_cast<int>(n), m, J, out);
-  return hipGetLastError();
-}
-
-template <int J>
-static hipError_t launch_step_sign_j(const uint32_t* tiles, int64_t n, int64_t m, int64_t ld,
-                                     float* rbuf, float inv_sqrt_n, const CorrGeom& g,
-                                     uint64_t* keys, int parity, int first, float* x,
-                                     DevState* st, mp_trace tr, hipStream_t s) {
-  const size_t lds = sizeof(float) * 16 * 512 * J;
-  static bool attr_set = false;  // tables above 64 KB need the opt-in limit
+hipError_t launch_sign_c0(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, const float* y,
+                          int64_t ld, double* c64, double* r64, hipStream_t s) {
+  const size_t lds = sizeof(float) * 32 * static_cast<size_t>(ws);  // <= 64 KB (n <= 16384)
+  int64_t blocks = (m + kC0Threads / kWave - 1) / (kC0Threads / kWave);
+  if (blocks > 4096) blocks = 4096;
+  static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_mp_step_sign<J>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_sign_c0),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  k_mp_step_sign<J><<<dim3(g.grid), dim3(kSignThreads), lds, s>>>(
-      tiles, static_cast<int>(n), m, ld, rbuf, inv_sqrt_n, g.cols_per_wg, 4u, keys, parity,
-      first, x, st, tr);
+  k_sign_c0<<<dim3(static_cast<unsigned>(blocks)), dim3(kC0Threads), lds, s>>>(
+      bits, ws, static_cast<int>(n), m, y, 1.0 / sqrt(static_cast<double>(n)), ld, c64, r64);
   return hipGetLastError();
 }
 
-hipError_t launch_mp_step_sign(const uint32_t* tiles, int J, int64_t n, int64_t m, int64_t ld,
-                               float* rbuf, float inv_sqrt_n, const CorrGeom& g, uint64_t* keys,
-                               int parity, int first, float* x, DevState* st, mp_trace tr,
-                               hipStream_t s) {
-  switch (J) {
-    case 1:
-      return launch_step_sign_j<1>(tiles, n, m, ld, rbuf, inv_sqrt_n, g, keys, parity, first, x,
-                                   st, tr, s);
-    case 2:
-      return launch_step_sign_j<2>(tiles, n, m, ld, rbuf, inv_sqrt_n, g, keys, parity, first, x,
-                                   st, tr, s);
-    case 4:
-      return launch_step_sign_j<4>(tiles, n, m, ld, rbuf, inv_sqrt_n, g, keys, parity, first, x,
-                                   st, tr, s);
-    default:
-      return hipErrorInvalidValue;
-  }
+hipError_t launch_mp_step_sign(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, int64_t ld,
+                               double* c64, double* r64, float* r32, double* rrp,
+                               const CorrGeom& g, uint64_t* keys, long long k, long long max_iters,
+                               double thr, float* x, DevState* st, mp_trace tr, hipStream_t s) {
+  const double inv_n = 1.0 / static_cast<double>(n);
+  const double inv_sqrt_n = 1.0 / sqrt(static_cast<double>(n));
+  const int rows_per_wg = static_cast<int>((ld + g.grid - 1) / g.grid);
+  if (sign_chunks_per_lane(n) == 1)
+    k_mp_step_sign<1><<<dim3(g.grid), dim3(kSignThreads), 0, s>>>(
+        bits, ws, static_cast<int>(n), m, ld, c64, r64, r32, rrp, inv_n, inv_sqrt_n,
+        g.cols_per_wg, rows_per_wg, keys, k, max_iters, thr, x, st, tr);
+  else
+    k_mp_step_sign<2><<<dim3(g.grid), dim3(kSignThreads), 0, s>>>(
+        bits, ws, static_cast<int>(n), m, ld, c64, r64, r32, rrp, inv_n, inv_sqrt_n,
+        g.cols_per_wg, rows_per_wg, keys, k, max_iters, thr, x, st, tr);
+  return hipGetLastError();
 }
 
 }  // namespace mp

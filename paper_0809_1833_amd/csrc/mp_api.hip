@@ -15,7 +15,7 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr int64_t kMaxN = 16384;          // the residual is staged whole in LDS
-constexpr int64_t kMaxSignN = 8192;       // the signed-sum tables of r fill 128 KB of LDS
+constexpr int64_t kMaxSignN = 16384;      // two 16-byte chunks of a column per lane
 constexpr int64_t kMaxRaggedN = 8192;     // per-instance residual in LDS, 32 KB
 constexpr int64_t kLdAlign = 64;          // padded column length (floats): 256 B aligned
 constexpr int kMaxChunk = 64;             // iterations enqueued per host check
@@ -99,6 +99,9 @@ void free_ctx(mp_ctx* c) {
   (void)hipFree(c->r64_work);
   (void)hipFree(c->psiq);
   (void)hipFree(c->psis);
+  (void)hipFree(c->sign_c64);
+  (void)hipFree(c->sign_r64);
+  (void)hipFree(c->sign_rrp);
   (void)hipFree(c->scales);
   (void)hipFree(c->r_work);
   (void)hipFree(c->st);
@@ -418,8 +421,9 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
     HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(double), c->psi64, c->ld * sizeof(double),
                                 c->n * sizeof(double), c->m, hipMemcpyDeviceToDevice, s));
   } else if (c->storage == MP_SIGN1) {
-    HIP_TRY(c, mp::launch_untile_signs(c->psis, c->n, c->m, c->sign_j,
-                                       static_cast<uint32_t*>(codes), s));
+    const size_t w = static_cast<size_t>((c->n + 31) / 32) * sizeof(uint32_t);
+    HIP_TRY(c, hipMemcpy2DAsync(codes, w, c->psis, c->sign_ws * sizeof(uint32_t), w, c->m,
+                                hipMemcpyDeviceToDevice, s));
   } else if (c->storage == MP_F32) {
     HIP_TRY(c, hipMemcpy2DAsync(codes, c->n * sizeof(float), c->psi32, c->ld * sizeof(float),
                                 c->n * sizeof(float), c->m, hipMemcpyDeviceToDevice, s));
@@ -459,34 +463,32 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if (c->storage == MP_SIGN1) {
-    // launch k finishes iteration k-1 and runs pass k: T iterations take T+1
-    // launches; r ends in the half the state names
+    // c(0) = Psi^T y and r = y in FP64; launch k runs the stop test for the
+    // k-1 steps taken and takes step k, so T steps take T+2 launches
+    if (!c->h_st->done)
+      HIP_TRY(c, mp::launch_sign_c0(c->psis, c->sign_ws, c->n, c->m, y, c->ld, c->sign_c64,
+                                    c->sign_r64, s));
     long long k = 0;
-    const long long launches = opts->max_iters > 0 ? opts->max_iters + 1 : 0;
-    const mp_status st = run_iterations(c, launches, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    const long long T = opts->max_iters;
+    const double thr = c->h_st->thr;
+    const mp_status st = run_iterations(c, T > 0 ? T + 2 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
       hipError_t e;
       if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-      e = mp::launch_mp_step_sign(c->psis, c->sign_j, c->n, c->m, c->ld, c->r_work,
-                                  c->inv_sqrt_n, c->geom, c->partials, static_cast<int>(k & 1),
-                                  k == 0 ? 1 : 0, x, c->st, tr, s);
+      e = mp::launch_mp_step_sign(c->psis, c->sign_ws, c->n, c->m, c->ld, c->sign_c64,
+                                  c->sign_r64, c->r_work, c->sign_rrp, c->geom, c->partials, k, T,
+                                  thr, x, c->st, tr, s);
       ++k;
       if (e != hipSuccess) return e;
       if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
       return hipSuccess;
     });
     if (st != MP_OK) return st;
-    HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (r)
-      HIP_TRY(c, hipMemcpyAsync(r, c->r_work + (c->h_st->r_sel ? c->ld : 0),
-                                c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    return finish_result(c, res);
+  } else {
+    const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
+      return enqueue_iteration(c, x, tr, s, e0, e1);
+    });
+    if (st != MP_OK) return st;
   }
-  const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
-    return enqueue_iteration(c, x, tr, s, e0, e1);
-  });
-  if (st != MP_OK) return st;
 
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   if (r)
@@ -632,7 +634,7 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
   *out = nullptr;
   if (!signs) return fail(nullptr, MP_EINVAL, "signs is NULL");
   if (n < 1 || m < 1) return fail(nullptr, MP_EINVAL, "n and m must be >= 1");
-  if (n > kMaxSignN) return fail(nullptr, MP_EINVAL, "n exceeds 8192 for sign-bit storage");
+  if (n > kMaxSignN) return fail(nullptr, MP_EINVAL, "n exceeds 16384");
   if (ldw < (n + 31) / 32) return fail(nullptr, MP_EINVAL, "ldw must be >= ceil(n / 32)");
   if (m >= (int64_t{1} << 31)) return fail(nullptr, MP_EINVAL, "m must be < 2^31");
   if (flags & ~MP_SKIP_NORM_CHECK) return fail(nullptr, MP_EINVAL, "unknown flags");
@@ -648,30 +650,33 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
   c->m = m;
   c->ld = round_up(n, kLdAlign);
   c->storage = MP_SIGN1;
-  c->sign_j = mp::sign_words_per_lane(n);
-  c->inv_sqrt_n = static_cast<float>(1.0 / sqrt(static_cast<double>(n)));
+  c->sign_ws = round_up((n + 31) / 32, 4);
   c->geom = mp::corr_f32_geometry(m, c->num_cus);
 
   auto bail = [&](mp_status st, const std::string& msg) {
     free_ctx(c);
     return fail(nullptr, st, msg);
   };
-  const size_t tile_words = static_cast<size_t>(m) * 64 * static_cast<size_t>(c->sign_j);
-  if (hipMalloc(&c->psis, tile_words * sizeof(uint32_t)) != hipSuccess)
+  const size_t words = static_cast<size_t>(m) * static_cast<size_t>(c->sign_ws);
+  if (hipMalloc(&c->psis, words * sizeof(uint32_t)) != hipSuccess)
     return bail(MP_ENOMEM, "sign-bit copy");
-  // r and the per-workgroup keys in two halves, alternating by launch parity
-  if (hipMalloc(&c->r_work, 2 * c->ld * sizeof(float)) != hipSuccess)
-    return bail(MP_ENOMEM, "r");
+  if (hipMalloc(&c->sign_c64, sizeof(double) * m) != hipSuccess)
+    return bail(MP_ENOMEM, "correlations");
+  if (hipMalloc(&c->sign_r64, sizeof(double) * c->ld) != hipSuccess) return bail(MP_ENOMEM, "r");
+  if (hipMalloc(&c->r_work, c->ld * sizeof(float)) != hipSuccess) return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
   if (c->geom.grid > 1024)
     return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
-  const size_t nkeys = 2 * static_cast<size_t>(c->geom.grid);
+  // pair keys, one per workgroup, in two halves alternating by launch parity
+  const size_t nkeys = 4 * static_cast<size_t>(c->geom.grid);
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
+  if (hipMalloc(&c->sign_rrp, sizeof(double) * 2 * c->geom.grid) != hipSuccess)
+    return bail(MP_ENOMEM, "partial norms");
   if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
     return bail(MP_ENOMEM, "pinned state");
-  hipError_t e = mp::launch_tile_signs(signs, ldw, n, m, c->sign_j, c->psis, s);
-  if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, 2 * c->ld * sizeof(float), s);
+  hipError_t e = mp::launch_copy_signs(signs, ldw, n, m, c->sign_ws, c->psis, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));

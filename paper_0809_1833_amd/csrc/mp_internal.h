@@ -28,7 +28,7 @@ struct alignas(64) DevState {
   int done;             // 1 once the run has stopped
   int reason;           // MP_STOP_* or kStopNonFinite
   unsigned arrive;      // workgroups of the current launch that have published a key
-  int r_sel;            // sign-bit decode: half of the residual buffer holding r (0 or 1)
+  int pad0;
   int pad[4];
 };
 
@@ -82,19 +82,20 @@ hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t 
                               mp_trace_f64 tr, hipStream_t s);
 
 // ---- sign-bit Bernoulli dictionary (k_sign.hip) ------------------------------
-// Words per lane of one column load (1, 2 or 4; the column covers 2048 J rows).
-int sign_words_per_lane(int64_t n);
-hipError_t launch_tile_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int J,
+// 16-byte chunks of a column each lane reads (1 for n <= 8192, 2 above).
+int sign_chunks_per_lane(int64_t n);
+// Packed input (ldw words per column) -> ws words per column, rows >= n cleared.
+hipError_t launch_copy_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int64_t ws,
                              uint32_t* out, hipStream_t s);
-hipError_t launch_untile_signs(const uint32_t* tiles, int64_t n, int64_t m, int J, uint32_t* out,
-                               hipStream_t s);
-// Launch k of a decode (parity = k mod 2, first = k == 0): finishes iteration
-// k-1 and runs pass k.  rbuf: 2 x ld floats (r in half `parity`), keys:
-// 2 x grid slots.
-hipError_t launch_mp_step_sign(const uint32_t* tiles, int J, int64_t n, int64_t m, int64_t ld,
-                               float* rbuf, float inv_sqrt_n, const CorrGeom& g, uint64_t* keys,
-                               int parity, int first, float* x, DevState* st, mp_trace tr,
-                               hipStream_t s);
+// c(0) = Psi^T y and r = y, both FP64 (c64: m, r64: ld doubles).
+hipError_t launch_sign_c0(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, const float* y,
+                          int64_t ld, double* c64, double* r64, hipStream_t s);
+// Launch k of a decode: stop test for the k-1 steps taken, step k, the keys
+// of the next.  keys: 2 halves x 2 words x grid; rrp: 2 halves x grid.
+hipError_t launch_mp_step_sign(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, int64_t ld,
+                               double* c64, double* r64, float* r32, double* rrp,
+                               const CorrGeom& g, uint64_t* keys, long long k, long long max_iters,
+                               double thr, float* x, DevState* st, mp_trace tr, hipStream_t s);
 
 // ---- Orthogonal Matching Pursuit, FP32 (k_omp.hip) --------------------------
 struct OmpState {           // the atom selected in the current iteration
@@ -203,9 +204,11 @@ struct mp_ctx {
   double* psi64 = nullptr;       // MP_F64 storage: the FP64 dictionary (same layout)
   double* r64_work = nullptr;    // MP_F64 storage: ld doubles, rows n..ld-1 stay zero
   void* psiq = nullptr;          // BF16 / FP8 copy (same layout), if any
-  uint32_t* psis = nullptr;      // MP_SIGN1 storage: sign-bit tiles, 64 sign_j words per column
-  int sign_j = 0;                // words per lane of one sign column load
-  float inv_sqrt_n = 0.0f;       // MP_SIGN1: 1/sqrt(n) rounded to FP32
+  uint32_t* psis = nullptr;      // MP_SIGN1 storage: sign bits, sign_ws words per column
+  int64_t sign_ws = 0;           // words per column (ceil(n/32) rounded up to 4)
+  double* sign_c64 = nullptr;    // MP_SIGN1: the carried correlations, m doubles
+  double* sign_r64 = nullptr;    // MP_SIGN1: r in FP64, ld doubles
+  double* sign_rrp = nullptr;    // MP_SIGN1: per-workgroup partial ||r||^2, 2 x grid
   float* scales = nullptr;       // FP8 per-column scales
   // per-decode work buffers
   float* r_work = nullptr;       // ld floats, rows n..ld-1 stay zero

@@ -101,7 +101,7 @@ def test_f64_storage_goes_through_its_own_entry_point():
     (dict(signs=None), "signs is NULL"),
     (dict(n=0), "n and m"),
     (dict(m=0), "n and m"),
-    (dict(n=8193, ldw=300), "8192"),
+    (dict(n=16385, ldw=600), "16384"),
     (dict(n=33, ldw=1), "ldw must be"),
     (dict(m=2 ** 31), "2^31"),
     (dict(flags=0x10), "flags"),

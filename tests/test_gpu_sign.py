@@ -95,11 +95,12 @@ def test_parity_8192x32768_sampled():
 
 
 @pytest.mark.parametrize("n,m", [(1, 5), (3, 40), (33, 17), (100, 1000), (2047, 300),
-                                 (2048, 513), (2049, 300), (4097, 200), (6000, 129),
-                                 (8192, 70)])
+                                 (2049, 300), (6000, 129), (8192, 70), (8193, 33),
+                                 (12000, 100), (16384, 40)])
 def test_parity_ragged_shapes(n, m):
-    """Every words-per-lane form (N <= 2048, 4096, 8192), N not a multiple of
-    4, 32 or 64, M below and not a multiple of the workgroup's column count."""
+    """Columns of one and two 16-byte chunks per lane (N <= 8192 and above),
+    N not a multiple of 4, 32 or 64, M below and not a multiple of the
+    workgroup's column count."""
     rng = np.random.default_rng(n * 7 + m)
     s = mpgen.bernoulli_signs(rng, n, m)
     k = max(1, min(6, n // 8, m // 4))
@@ -156,7 +157,8 @@ def test_duplicate_and_negated_columns_tie_low():
     np.testing.assert_allclose(g["coef"][:upto], ora.coef[:upto], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("n,ldw", [(1, 1), (31, 2), (64, 2), (100, 5), (2049, 65), (8192, 256)])
+@pytest.mark.parametrize("n,ldw", [(1, 1), (31, 2), (64, 2), (100, 5), (2049, 65), (8192, 256),
+                                   (16383, 513)])
 def test_storage_round_trip(n, ldw):
     """mp_get_storage returns the packed bits the context decodes: the input
     with its tail bits and spare words dropped, bit for bit."""
