@@ -44,7 +44,11 @@ TRAFFIC = {
             [os.path.join(_CSRC, f) for f in ("k_lowp.hip", "k_lowp.h", "k_common.h",
                                               "mp_internal.h")]),
     "f64": (os.path.join(ROOT, "profiles", "mp_step_f64_traffic.json"),
-            [os.path.join(_CSRC, f) for f in ("k_f64.hip", "k_common.h", "mp_internal.h")]),
+            [os.path.join(_CSRC, f) for f in ("k_f64.hip", "k_common.h", "k_key2.h",
+                                              "mp_internal.h")]),
+    "sign": (os.path.join(ROOT, "profiles", "mp_step_sign_traffic.json"),
+             [os.path.join(_CSRC, f) for f in ("k_sign.hip", "k_common.h", "k_key2.h",
+                                               "mp_internal.h")]),
     "omp": (os.path.join(ROOT, "profiles", "omp_select_traffic.json"),
             [os.path.join(_CSRC, f) for f in ("k_omp.hip", "k_common.h", "mp_internal.h")]),
 }
@@ -166,7 +170,8 @@ def sign_step_bytes(n, m):
     return n * m / 8.0 + 16.0 * m + 20.0 * n
 
 
-def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 16):
+def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 16,
+               max_iters=None):
     """Decode on the Bernoulli dictionary of eq. 13 held as sign bits
     (mp_create_signs): N=8192, M=32768 (32 MiB of bits), K=512, eps=1e-5,
     T=10240.  The correlations are carried by exact Gram updates (XOR and
@@ -178,6 +183,8 @@ def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 
     from paper_0809_1833_amd.mp import Decoder
 
     p = mpgen.make_sign_problem("c1b", seed)
+    if max_iters is not None:
+        p.max_iters = min(p.max_iters, max_iters)
     n, m = p.n, p.m
     bits = torch.from_numpy(p.bits.view("int32")).cuda()
     y = torch.from_numpy(p.y).cuda()
@@ -197,7 +204,8 @@ def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 
                          "achieved": round(achieved, 2) if achieved else None,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                         "traffic": None, "bytes_per_launch": b,
+                         "traffic": traffic_from_counters(n, m, "sign"),
+                         "bytes_per_launch": b,
                          "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kt_n}}
 
 
@@ -464,7 +472,7 @@ def main():
         line["f64"] = bench_f64(args.seed)
     if not args.no_sign:
         log("[bench] sign-bit Bernoulli dictionary (same sizes)")
-        line["sign"] = bench_sign(args.seed)
+        line["sign"] = bench_sign(args.seed, max_iters=args.max_iters)
     if not args.no_phase:
         log("[bench] Fig. 1 experiment (batched decodes over the sigma-rho grid)")
         line["phase"] = bench_phase(args.seed)
