@@ -104,22 +104,35 @@ hipError_t launch_quant_fp8(const float* psi, int64_t ld, int64_t m, uint8_t* ou
 }
 
 // ---------------------------------------------------------------------------
-// One MP iteration with a reduced-precision correlation pass (one launch).
+// One MP iteration with a reduced-precision correlation pass (one launch),
+// the selection carried into the next launch so that no workgroup waits for
+// another (no hand-off through atomics, no single-workgroup tail).
 //
-// Same shape as the FP32 step: 16-wave workgroups, r staged in LDS, wave w
-// of workgroup b takes columns b*cpw + w, + 16, ... (FP8: pairs b*cpw + 2w,
-// 2w + 1, + 32, ...); each wave keeps a top-8
-// list of its columns' keys, the workgroup merges its 16 lists and publishes
-// 8 keys.  The last workgroup merges all published keys into the launch's
-// top 8, re-scores the first `rescore_k` of them in FP32 and finishes the
-// iteration with the best re-scored candidate.
+// Launch k (k >= 1) finishes step k and runs pass k+1:
+//  1. every workgroup requests at once r_{k-1} (half k mod 2 of rbuf) and
+//     the 8 keys each workgroup of launch k-1 stored;
+//  2. every workgroup merges the published keys into the top 8, re-scores up
+//     to `rescore_k` of them against the FP32 columns (two waves per
+//     candidate, the FP32 form's inner product bit for bit), takes the best
+//     re-scored candidate (idx, c) and updates its LDS copy of r,
+//     r_k = r_{k-1} - c psi_idx with the FP32 column (eq. 11), and ||r_k||^2
+//     in FP64 -- the same values in every workgroup, so the same stop test;
+//  3. workgroup 0 alone stores r_k (the other half of rbuf), adds c to x~_idx
+//     (eq. 10), writes the trace entry and the state (t = k, eq. 12);
+//  4. unless the run stops here, every workgroup runs the reduced-precision
+//     pass over its columns against r_k, keeps a top-8 list per wave, merges
+//     its 16 lists and stores 8 keys for launch k+1.
+// Launch 0 runs the first pass on r = y (workgroup 0 copies r to the other
+// half); T steps take T+1 launches.  Same shape as the FP32 step: 16-wave
+// workgroups, wave w of workgroup b takes columns b*cpw + w, + 16, ...
+// (FP8: pairs b*cpw + 2w, 2w + 1, + 32, ...).
 template <int S>
 __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
     const v4u* __restrict__ psiq, const float* __restrict__ scales,
-    const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m, float* __restrict__ r,
-    int cols_per_wg, int rescore_k, uint64_t* __restrict__ keys, float* __restrict__ x,
-    DevState* __restrict__ st, mp_trace tr) {
-  if (st->done) return;
+    const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m, float* __restrict__ rbuf,
+    int cols_per_wg, int rescore_k, uint64_t* __restrict__ keys, long long k,
+    long long max_iters, double thr, float* __restrict__ x, DevState* __restrict__ st,
+    mp_trace tr) {
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t lists[kLpWaves * kTopK];
   __shared__ uint64_t cand[kTopK];
@@ -127,21 +140,153 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   __shared__ float chain_b[kTopK][kWave];
   __shared__ uint64_t kred[kLpWaves];
   __shared__ double dred[kLpWaves];
+  __shared__ int s_done;
+  constexpr int CC = kLpColsPerWave<S>;
+  constexpr int RPT = 16384 / 4 / kLpThreads;  // float4s of r per thread (ld <= 16384)
   const int ld4 = static_cast<int>(ld / 4);
   const int nq = static_cast<int>(ld * S / 16);
-  const v4f* r4 = reinterpret_cast<const v4f*>(r);
-  for (int i = threadIdx.x; i < ld4; i += kLpThreads) r_lds[i] = r4[i];
-  __syncthreads();
-
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int par = static_cast<int>(k & 1);
+  const bool first = k == 0;
+  const v4f* r_in = reinterpret_cast<const v4f*>(rbuf + (par ? ld : 0));
+  v4f* r_out = reinterpret_cast<v4f*>(rbuf + (par ? 0 : ld));
+  const int nslots = static_cast<int>(gridDim.x) * kTopK;  // <= 2 * kLpThreads (host-checked)
+  const uint64_t* k_in = keys + (par ? nslots : 0);
+  uint64_t* k_out = keys + (par ? 0 : nslots);
   const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
   int64_t col1 = col0 + cols_per_wg;
   if (col1 > m) col1 = m;
+
+  // ---- 1. requests (clamped indices into valid memory, unused values dropped)
+  int done_v = 0;
+  if (threadIdx.x == 0)
+    done_v = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v4f rq[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = threadIdx.x + u * kLpThreads;
+    rq[u] = r_in[i < ld4 ? i : ld4 - 1];
+  }
+  const int ia = threadIdx.x < nslots ? threadIdx.x : nslots - 1;
+  const int ib = threadIdx.x + kLpThreads < nslots ? threadIdx.x + kLpThreads : nslots - 1;
+  uint64_t ka = k_in[ia], kb = k_in[ib];
+  if (first || threadIdx.x >= static_cast<unsigned>(nslots)) ka = 0;
+  if (first || threadIdx.x + kLpThreads >= static_cast<unsigned>(nslots)) kb = 0;
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = threadIdx.x + u * kLpThreads;
+    if (i < ld4) r_lds[i] = rq[u];
+  }
+  if (threadIdx.x == 0) s_done = done_v;
+  __syncthreads();
+  if (s_done) return;
+
+  if (!first) {
+    // ---- 2. the top 8 of the published keys (slot 8g + j holds workgroup g's
+    // rank-j key, so every group of 8 lanes holds one sorted list) ----
+    const uint64_t wtop = top8_of_lists16(ka, kb, lane);
+    if (lane < kTopK) lists[wave * kTopK + lane] = wtop;
+    __syncthreads();
+    if (wave == 0) {
+      const uint64_t t = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
+      if (lane < kTopK) cand[lane] = t;
+    }
+    __syncthreads();
+    // re-score: waves 2q and 2q+1 run the two chains of candidate q's inner
+    // product, which meet per lane in LDS
+    static_assert(kLpWaves >= 2 * kTopK, "two waves per candidate");
+    {
+      const int q = wave / 2;
+      const bool second = (wave % 2) != 0;
+      const int h0 = ld4 / 2;
+      int idx = -1;
+      if (q < rescore_k && cand[q] != 0) {
+        idx = key_index(cand[q]);
+        if (idx >= m) idx = -1;
+      }
+      float acc = 0.0f;
+      if (idx >= 0) {
+        acc = dot_chain_f32(reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld),
+                            r_lds, second ? h0 : 0, h0, lane);
+        if (second) chain_b[q][lane] = acc;
+      }
+      __syncthreads();
+      if (!second && q < rescore_k) {
+        uint64_t rk = 0;
+        if (idx >= 0) rk = make_key(wave_sum(acc + chain_b[q][lane]), idx);
+        if (lane == 0) rescored[q] = rk;
+      }
+    }
+    __syncthreads();
+    uint64_t best = 0;
+    for (int j = 0; j < rescore_k; ++j) best = rescored[j] > best ? rescored[j] : best;
+    const int idx = key_index(best);
+    const float c = key_value(best);
+    if (idx < 0 || idx >= m || c == 0.0f) {  // c = 0: no atom correlates with r
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->reason = (idx < 0 || idx >= m) ? kStopInternal : MP_STOP_STALLED;
+        st->done = 1;
+      }
+      return;
+    }
+    // r_k = r_{k-1} - c psi_idx (padding rows stay +0) and ||r_k||^2 in FP64,
+    // each thread on its own float4s (the re-score has finished reading r)
+    const v4f* col = reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld);
+    v4f a[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = threadIdx.x + u * kLpThreads;
+      a[u] = col[i < ld4 ? i : ld4 - 1];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = threadIdx.x + u * kLpThreads;
+      if (i < ld4) {
+        const v4f rv = r_lds[i];
+        v4f o;
+        o.x = __builtin_fmaf(-c, a[u].x, rv.x);
+        o.y = __builtin_fmaf(-c, a[u].y, rv.y);
+        o.z = __builtin_fmaf(-c, a[u].z, rv.z);
+        o.w = __builtin_fmaf(-c, a[u].w, rv.w);
+        r_lds[i] = o;
+        if (blockIdx.x == 0) r_out[i] = o;
+        s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
+             (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
+      }
+    }
+    const double rr = block_sum<kLpThreads>(s, dred);  // also orders the r_lds updates
+    const bool stop = !(rr > thr) || k >= max_iters;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      x[idx] += c;
+      const long long t = k - 1;
+      if (t < tr.cap) {
+        if (tr.idx) tr.idx[t] = idx;
+        if (tr.coef) tr.coef[t] = c;
+        if (tr.rr) tr.rr[t] = rr;
+      }
+      st->t = k;
+      st->rr = rr;
+      st->r_sel = par ^ 1;  // the half of rbuf that holds r
+      if (!(rr > thr)) {
+        st->reason = MP_STOP_CONVERGED;
+        st->done = 1;
+      } else if (k >= max_iters) {
+        st->reason = MP_STOP_MAX_ITERS;
+        st->done = 1;
+      }
+    }
+    if (stop) return;
+  } else if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < ld4; i += kLpThreads) r_out[i] = r_lds[i];
+    if (threadIdx.x == 0) st->r_sel = par ^ 1;
+  }
+
+  // ---- 4. the pass against r_k ----
   uint64_t L[kTopK];
 #pragma unroll
   for (int j = 0; j < kTopK; ++j) L[j] = 0;
   // wave w takes columns in runs of CC: col0 + CC*w, ..., then + CC*16
-  constexpr int CC = kLpColsPerWave<S>;
   for (int64_t col = col0 + CC * wave; col < col1; col += CC * kLpWaves) {
     const v4u* p[CC];
 #pragma unroll
@@ -165,61 +310,17 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
     if (lane < kTopK) lists[wave * kTopK + lane] = v;
   }
   __syncthreads();
-  uint64_t mine = 0;
-  if (wave == 0) mine = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
-  if (!publish_arrive<kTopK>(mine, keys, st)) return;
-
-  // ---- last workgroup: the launch's top 8.  Slot 8g + j holds workgroup
-  // g's rank-j key, so every group of 8 lanes below holds one sorted list ----
-  const int nslots = static_cast<int>(gridDim.x) * kTopK;  // <= 2 * kLpThreads (host-checked)
-  const uint64_t a = threadIdx.x < nslots ? take_slot(keys + threadIdx.x) : 0;
-  const uint64_t b =
-      threadIdx.x + kLpThreads < nslots ? take_slot(keys + threadIdx.x + kLpThreads) : 0;
-  const uint64_t wtop = top8_of_lists16(a, b, lane);
-  __syncthreads();  // everyone is done with `lists`
-  if (lane < kTopK) lists[wave * kTopK + lane] = wtop;
-  __syncthreads();
   if (wave == 0) {
-    const uint64_t t = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
-    if (lane < kTopK) cand[lane] = t;
+    const uint64_t mine = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
+    if (lane < kTopK) k_out[blockIdx.x * kTopK + lane] = mine;
   }
-  __syncthreads();
-  // ---- re-score candidates against the FP32 columns: waves 2q and 2q+1 run
-  // the two chains of candidate q's inner product, which meet per lane in
-  // LDS (the same arithmetic as the FP32 form's inner product) ----
-  static_assert(kLpWaves >= 2 * kTopK, "two waves per candidate");
-  {
-    const int q = wave / 2;
-    const bool second = (wave % 2) != 0;
-    const int h0 = ld4 / 2;
-    int idx = -1;
-    if (q < rescore_k && cand[q] != 0) {
-      idx = key_index(cand[q]);
-      if (idx >= m) idx = -1;
-    }
-    float acc = 0.0f;
-    if (idx >= 0) {
-      acc = dot_chain_f32(reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld),
-                          r_lds, second ? h0 : 0, h0, lane);
-      if (second) chain_b[q][lane] = acc;
-    }
-    __syncthreads();
-    if (!second && q < rescore_k) {
-      uint64_t rk = 0;
-      if (idx >= 0) rk = make_key(wave_sum(acc + chain_b[q][lane]), idx);
-      if (lane == 0) rescored[q] = rk;
-    }
-  }
-  __syncthreads();
-  uint64_t best = 0;
-  for (int j = 0; j < rescore_k; ++j) best = rescored[j] > best ? rescored[j] : best;
-  select_update_tail<kLpThreads>(best, psi32, ld, n, m, x, r, r_lds, st, tr, dred);
 }
 
 hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
-                             const float* psi32, int64_t ld, int64_t n, int64_t m, float* r,
-                             const CorrGeom& g, int rescore_k, uint64_t* keys, float* x,
-                             DevState* st, mp_trace tr, hipStream_t s) {
+                             const float* psi32, int64_t ld, int64_t n, int64_t m, float* rbuf,
+                             const CorrGeom& g, int rescore_k, uint64_t* keys, long long k,
+                             long long max_iters, double thr, float* x, DevState* st,
+                             mp_trace tr, hipStream_t s) {
   const size_t lds = static_cast<size_t>(ld) * sizeof(float);
   const v4u* q = static_cast<const v4u*>(psiq);
   static bool big_lds[2] = {false, false};
@@ -233,10 +334,12 @@ hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* sc
   }
   if (storage == MP_BF16)
     k_mp_step_lp<2><<<dim3(g.grid), dim3(kLpThreads), lds, s>>>(
-        q, nullptr, psi32, ld, n, m, r, g.cols_per_wg, rescore_k, keys, x, st, tr);
+        q, nullptr, psi32, ld, n, m, rbuf, g.cols_per_wg, rescore_k, keys, k, max_iters, thr, x,
+        st, tr);
   else
     k_mp_step_lp<1><<<dim3(g.grid), dim3(kLpThreads), lds, s>>>(
-        q, scales, psi32, ld, n, m, r, g.cols_per_wg, rescore_k, keys, x, st, tr);
+        q, scales, psi32, ld, n, m, rbuf, g.cols_per_wg, rescore_k, keys, k, max_iters, thr, x,
+        st, tr);
   return hipGetLastError();
 }
 

@@ -116,12 +116,8 @@ hipError_t enqueue_iteration(mp_ctx* c, float* x, const mp_trace& tr, hipStream_
                              hipEvent_t e0, hipEvent_t e1) {
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-  if (c->storage == MP_F32)
-    e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials, x,
-                               c->st, tr, s);
-  else
-    e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
-                              c->r_work, c->geom, c->rescore_k, c->partials, x, c->st, tr, s);
+  e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials, x,
+                             c->st, tr, s);
   if (e != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
   return hipSuccess;
@@ -339,11 +335,14 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   };
   const size_t psi_bytes = static_cast<size_t>(c->ld) * static_cast<size_t>(m) * sizeof(float);
   if (hipMalloc(&c->psi32, psi_bytes) != hipSuccess) return bail(MP_ENOMEM, "dictionary copy");
-  if (hipMalloc(&c->r_work, c->ld * sizeof(float)) != hipSuccess) return bail(MP_ENOMEM, "r");
+  // r and the published keys in two halves (the reduced-precision decode
+  // alternates between them by launch parity)
+  if (hipMalloc(&c->r_work, 2 * c->ld * sizeof(float)) != hipSuccess)
+    return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
   if (c->geom.grid * mp::kLpTopK > 2 * 1024)
     return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
-  const size_t nkeys = static_cast<size_t>(c->geom.grid) * mp::kLpTopK;
+  const size_t nkeys = 2 * static_cast<size_t>(c->geom.grid) * mp::kLpTopK;
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
   if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
@@ -353,7 +352,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(c->psi32, c->ld * sizeof(float), psi, ld * sizeof(float),
                          n * sizeof(float), m, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, 2 * c->ld * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
 
@@ -483,6 +482,31 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
       return hipSuccess;
     });
     if (st != MP_OK) return st;
+  } else if (c->storage == MP_BF16 || c->storage == MP_FP8_E4M3) {
+    // launch k takes step k (k >= 1) and runs pass k+1: T steps take T+1
+    // launches; r ends in the half the state names
+    long long k = 0;
+    const long long T = opts->max_iters;
+    const double thr = c->h_st->thr;
+    const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+      hipError_t e;
+      if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+      e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
+                                c->r_work, c->geom, c->rescore_k, c->partials, k, T, thr, x,
+                                c->st, tr, s);
+      ++k;
+      if (e != hipSuccess) return e;
+      if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
+      return hipSuccess;
+    });
+    if (st != MP_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (r)
+      HIP_TRY(c, hipMemcpyAsync(r, c->r_work + (c->h_st->r_sel ? c->ld : 0),
+                                c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return finish_result(c, res);
   } else {
     const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
       return enqueue_iteration(c, x, tr, s, e0, e1);

@@ -28,7 +28,7 @@ struct alignas(64) DevState {
   int done;             // 1 once the run has stopped
   int reason;           // MP_STOP_* or kStopNonFinite
   unsigned arrive;      // workgroups of the current launch that have published a key
-  int pad0;
+  int r_sel;            // reduced-precision decode: half of the residual buffer holding r
   int pad[4];
 };
 
@@ -187,10 +187,13 @@ hipError_t launch_quant_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* 
                              hipStream_t s);
 hipError_t launch_quant_fp8(const float* psi, int64_t ld, int64_t m, uint8_t* out,
                             float* scales, hipStream_t s);
+// Launch k of a reduced-precision decode: step k (k >= 1) and pass k+1.
+// rbuf: 2 x ld floats (r in half k mod 2); keys: 2 halves x 8 per workgroup.
 hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
-                             const float* psi32, int64_t ld, int64_t n, int64_t m, float* r,
-                             const CorrGeom& g, int rescore_k, uint64_t* keys, float* x,
-                             DevState* st, mp_trace tr, hipStream_t s);
+                             const float* psi32, int64_t ld, int64_t n, int64_t m, float* rbuf,
+                             const CorrGeom& g, int rescore_k, uint64_t* keys, long long k,
+                             long long max_iters, double thr, float* x, DevState* st,
+                             mp_trace tr, hipStream_t s);
 
 }  // namespace mp
 
