@@ -288,74 +288,48 @@ __device__ inline uint64_t take_slot(uint64_t* slot) {
   return __hip_atomic_exchange(slot, uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Selection and update, run by the last workgroup of a launch (NT threads).
-// `best` is the launch's winning key (largest |c|, smallest index); `r_lds`
-// holds this launch's r (ld floats, zero padded), which the update reads
-// instead of the global copy.  Column and r padding rows are zero, so the
-// update keeps the padding at +0 and the FP64 norm over ld equals the norm
-// over n.
-// The launch's winner (idx, c) before the update: false, with the run
-// stopped, for an index outside the dictionary (which a published key never
-// holds) or c = 0 (no atom correlates with r: MP cannot make progress).
-__device__ inline bool winner_usable(int idx, float c, int64_t m, DevState* __restrict__ st) {
-  if (idx < 0 || idx >= m) {
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = kStopInternal;
-    }
-    return false;
-  }
-  if (c == 0.0f) {
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = MP_STOP_STALLED;
-    }
-    return false;
+// ---- steps carried into the next launch ------------------------------------
+//
+// The FP32 and reduced-precision forms finish step k at the start of launch
+// k+1 (k counted from 1): every workgroup finds the same winner (idx, c) and
+// applies the step to its own LDS copy of r, so no workgroup hands anything
+// to another inside a launch; the kernel boundary orders the published keys.
+
+// The winner cannot be applied (an index outside the dictionary, which no
+// published key holds, or c = 0: no atom correlates with r): workgroup 0
+// records the stop.  Same value in every thread of every workgroup.
+__device__ inline bool carried_winner_stops(int idx, float c, int64_t m,
+                                            DevState* __restrict__ st) {
+  const bool bad = idx < 0 || idx >= m;
+  if (!bad && c != 0.0f) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->reason = bad ? kStopInternal : MP_STOP_STALLED;
+    st->done = 1;
   }
   return true;
 }
 
-// Thread 0 of the last workgroup, after the update: x~_idx += c (eq. 10), the
-// trace entry, t + 1 (eq. 12), and the stopping test on the new ||r||^2.
-__device__ inline void record_step(int idx, float c, double rr, float* __restrict__ x,
-                                   DevState* __restrict__ st, const mp_trace& tr) {
-  x[idx] += c;
-  const long long t = st->t;
-  if (t < tr.cap) {
-    if (tr.idx) tr.idx[t] = idx;
-    if (tr.coef) tr.coef[t] = c;
-    if (tr.rr) tr.rr[t] = rr;
-  }
-  st->t = t + 1;
-  st->rr = rr;
-  if (!(rr > st->thr)) {
-    st->done = 1;
-    st->reason = MP_STOP_CONVERGED;
-  } else if (t + 1 >= st->max_iters) {
-    st->done = 1;
-    st->reason = MP_STOP_MAX_ITERS;
-  }
-}
-
+// Step k applied in every workgroup: r -= c psi_idx with the FP32 column (one
+// FMA per element, padding rows stay +0) on the LDS copy and ||r||^2 in FP64
+// (per-thread sums over its float4s in order, then block_sum: the same value
+// in every workgroup); workgroup 0 also stores r in r_out, adds c to x~_idx
+// (eq. 10) and writes the trace entry and the state (t = k, eq. 12, the
+// stop test, `half` = the half of the residual buffer r_out is).  Returns
+// true, in every thread of every workgroup, when the run stops after step k.
 template <int NT>
-__device__ void select_update_tail(uint64_t best, const float* __restrict__ psi, int64_t ld,
-                                   int64_t n, int64_t m, float* __restrict__ x,
-                                   float* __restrict__ r, const v4f* __restrict__ r_lds,
-                                   DevState* __restrict__ st, const mp_trace& tr, double* dred) {
-  const int idx = key_index(best);
-  const float c = key_value(best);
-  if (!winner_usable(idx, c, m, st)) return;
-  // r <- r - c psi_idx: all of this thread's column loads are issued first
-  // (ld <= 16384 gives at most P float4s per thread), then the updates.
-  constexpr int P = 16384 / 4 / NT > 0 ? 16384 / 4 / NT : 1;
-  const v4f* col = reinterpret_cast<const v4f*>(psi + static_cast<int64_t>(idx) * ld);
-  v4f* r4 = reinterpret_cast<v4f*>(r);
+__device__ bool carried_update(int idx, float c, const float* __restrict__ psi32, int64_t ld,
+                               v4f* __restrict__ r_lds, v4f* __restrict__ r_out,
+                               float* __restrict__ x, DevState* __restrict__ st,
+                               const mp_trace& tr, long long k, long long max_iters, double thr,
+                               int half, double* dred) {
+  constexpr int P = 16384 / 4 / NT > 0 ? 16384 / 4 / NT : 1;  // ld <= 16384
   const int ld4 = static_cast<int>(ld / 4);
+  const v4f* col = reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld);
   v4f a[P];
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     const int i = threadIdx.x + u * NT;
-    if (i < ld4) a[u] = col[i];
+    a[u] = col[i < ld4 ? i : ld4 - 1];
   }
   double s = 0.0;
 #pragma unroll
@@ -368,24 +342,34 @@ __device__ void select_update_tail(uint64_t best, const float* __restrict__ psi,
       o.y = __builtin_fmaf(-c, a[u].y, rv.y);
       o.z = __builtin_fmaf(-c, a[u].z, rv.z);
       o.w = __builtin_fmaf(-c, a[u].w, rv.w);
-      r4[i] = o;
+      r_lds[i] = o;
+      if (blockIdx.x == 0) r_out[i] = o;
       s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
            (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
     }
   }
-  for (int i = threadIdx.x + P * NT; i < ld4; i += NT) {  // only if ld exceeds the bound
-    const v4f av = col[i], rv = r_lds[i];
-    v4f o;
-    o.x = __builtin_fmaf(-c, av.x, rv.x);
-    o.y = __builtin_fmaf(-c, av.y, rv.y);
-    o.z = __builtin_fmaf(-c, av.z, rv.z);
-    o.w = __builtin_fmaf(-c, av.w, rv.w);
-    r4[i] = o;
-    s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
-         (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
+  const double rr = block_sum<NT>(s, dred);  // its barriers also order the r_lds writes
+  const bool stop = !(rr > thr) || k >= max_iters;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    x[idx] += c;
+    const long long t = k - 1;
+    if (t < tr.cap) {
+      if (tr.idx) tr.idx[t] = idx;
+      if (tr.coef) tr.coef[t] = c;
+      if (tr.rr) tr.rr[t] = rr;
+    }
+    st->t = k;
+    st->rr = rr;
+    st->r_sel = half;
+    if (!(rr > thr)) {
+      st->reason = MP_STOP_CONVERGED;
+      st->done = 1;
+    } else if (k >= max_iters) {
+      st->reason = MP_STOP_MAX_ITERS;
+      st->done = 1;
+    }
   }
-  const double rr = block_sum<NT>(s, dred);
-  if (threadIdx.x == 0) record_step(idx, c, rr, x, st, tr);
+  return stop;
 }
 
 }  // namespace mp

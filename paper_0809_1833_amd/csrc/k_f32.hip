@@ -1,13 +1,13 @@
 // FP32 single-signal Matching Pursuit kernels for gfx950 (Section 3, eqs. 8-12).
 //
-// One MP iteration is one launch of k_mp_step_f32 on the caller's stream:
-// c_m = <r, psi_m> for every column (eq. 9), streaming the whole column-major
-// dictionary once with a per-workgroup argmax (largest |c_m|, smallest index
-// on ties, eq. 16); the last workgroup to finish then picks i, updates
-// x~_i += c_i (eq. 10) and r -= c_i psi_i (eq. 11), counts t (eq. 12) and runs
-// the FP64 stopping test.  A launch returns at once when the device state says
-// the run has stopped, so the host can enqueue iterations ahead without
-// reading anything back.
+// One MP step per launch of k_mp_step_f32 on the caller's stream: launch k
+// applies step k (the winner of launch k-1's pass: x~_i += c_i, eq. 10;
+// r -= c_i psi_i, eq. 11; t = k, eq. 12; the FP64 stopping test) and then
+// computes c_m = <r, psi_m> for every column (eq. 9), streaming the whole
+// column-major dictionary once with a per-workgroup argmax (largest |c_m|,
+// smallest index on ties, eq. 16).  A launch returns at once when the device
+// state says the run has stopped, so the host can enqueue launches ahead
+// without reading anything back.
 #include "k_common.h"
 #include "mp_internal.h"
 
@@ -95,32 +95,75 @@ hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// One MP iteration in one launch (eqs. 9-12).
+// One MP iteration per launch (eqs. 9-12), the selection carried into the
+// next launch so that no workgroup waits for another.
 //
-// Workgroup = 16 waves, one per CU.  The residual (ld floats, zero padded) is
-// staged once into LDS; wave w of workgroup b takes columns b*cpw + w, + 16, ... and
-// streams each column with 16-byte non-temporal loads (lane l reads float4s
-// l, l+64, ...), UNROLL loads in flight per lane, FP32 FMA accumulation,
-// then a butterfly sum across the wave.  Keys are max-reduced per wave and
-// across the 16 waves; each workgroup publishes its key and counts itself in
-// (publish_arrive).  The workgroup that arrives last (nobody waits: it is
-// simply the one that sees the count reach the grid size) takes the winning
-// key, updates x~ and r, computes ||r||^2 in FP64 and applies the stopping
-// test.
+// Workgroup = 16 waves, one per CU.  Launch k (k >= 1): every workgroup
+// stages r_{k-1} (half k mod 2 of the residual buffer, ld floats, zero
+// padded) into LDS and reads the keys the workgroups of launch k-1 stored
+// (the kernel boundary orders them); all take the same winner (largest |c|,
+// smallest index, eq. 16), apply step k to their LDS copy of r and compute
+// ||r_k||^2 in FP64 (carried_update: workgroup 0 also stores r_k in the
+// other half and keeps x~, the trace and the state); unless the run stops
+// there, each runs pass k+1: wave w of workgroup b takes columns
+// b*cpw + w, + 16, ... and streams each column with 16-byte non-temporal
+// loads (two per-lane FP32 FMA chains over the column halves, then a
+// butterfly sum across the wave), keys are max-reduced per wave and across
+// the 16 waves, and the workgroup stores its key for launch k+1.  Launch 0
+// runs the first pass on r = y; T steps take T+1 launches.
 constexpr int kCorrThreads = 1024;
 
 __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
-    const float* __restrict__ psi, int64_t ld, int64_t n, int64_t m, float* __restrict__ r,
-    int cols_per_wg, uint64_t* __restrict__ keys, float* __restrict__ x,
-    DevState* __restrict__ st, mp_trace tr) {
-  if (st->done) return;
+    const float* __restrict__ psi, int64_t ld, int64_t n, int64_t m, float* __restrict__ rbuf,
+    int cols_per_wg, uint64_t* __restrict__ keys, long long k, long long max_iters, double thr,
+    float* __restrict__ x, DevState* __restrict__ st, mp_trace tr) {
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t kred[kCorrThreads / kWave];
   __shared__ double dred[kCorrThreads / kWave];
+  __shared__ int s_done;
+  constexpr int RPT = 16384 / 4 / kCorrThreads;  // float4s of r per thread (ld <= 16384)
   const int ld4 = static_cast<int>(ld / 4);
-  const v4f* r4 = reinterpret_cast<const v4f*>(r);
-  for (int i = threadIdx.x; i < ld4; i += kCorrThreads) r_lds[i] = r4[i];
+  const int par = static_cast<int>(k & 1);
+  const bool first = k == 0;
+  const v4f* r_in = reinterpret_cast<const v4f*>(rbuf + (par ? ld : 0));
+  v4f* r_out = reinterpret_cast<v4f*>(rbuf + (par ? 0 : ld));
+  const int nk = static_cast<int>(gridDim.x);  // <= kCorrThreads (host-checked)
+  const uint64_t* k_in = keys + (par ? nk : 0);
+  uint64_t* k_out = keys + (par ? 0 : nk);
+
+  // requests first, all unconditional (clamped indices into valid memory)
+  int done_v = 0;
+  if (threadIdx.x == 0)
+    done_v = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v4f rq[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = threadIdx.x + u * kCorrThreads;
+    rq[u] = r_in[i < ld4 ? i : ld4 - 1];
+  }
+  uint64_t kp = k_in[static_cast<int>(threadIdx.x) < nk ? static_cast<int>(threadIdx.x) : nk - 1];
+  if (first || static_cast<int>(threadIdx.x) >= nk) kp = 0;
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = threadIdx.x + u * kCorrThreads;
+    if (i < ld4) r_lds[i] = rq[u];
+  }
+  if (threadIdx.x == 0) s_done = done_v;  // one value for the whole workgroup
   __syncthreads();
+  if (s_done) return;
+
+  if (!first) {
+    const uint64_t win = block_max<kCorrThreads>(kp, kred);
+    const int idx = key_index(win);
+    const float c = key_value(win);
+    if (carried_winner_stops(idx, c, m, st)) return;
+    if (carried_update<kCorrThreads>(idx, c, psi, ld, r_lds, r_out, x, st, tr, k, max_iters, thr,
+                                     par ^ 1, dred))
+      return;
+  } else if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < ld4; i += kCorrThreads) r_out[i] = r_lds[i];
+    if (threadIdx.x == 0) st->r_sel = par ^ 1;
+  }
 
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
@@ -129,19 +172,11 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   uint64_t best = 0;
   for (int64_t col = col0 + wave; col < col1; col += kCorrThreads / kWave) {
     const float c = dot_column_f32(reinterpret_cast<const v4f*>(psi + col * ld), r_lds, ld4, lane);
-    const uint64_t k = make_key(c, static_cast<int>(col));
-    best = k > best ? k : best;
+    const uint64_t key = make_key(c, static_cast<int>(col));
+    best = key > best ? key : best;
   }
   best = block_max<kCorrThreads>(best, kred);
-  if (!publish_arrive<1>(best, keys, st)) return;
-  // last workgroup: the launch's winner is the largest published key
-  uint64_t winner = 0;
-  for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += kCorrThreads) {
-    const uint64_t k = take_slot(keys + i);
-    winner = k > winner ? k : winner;
-  }
-  winner = block_max<kCorrThreads>(winner, kred);
-  select_update_tail<kCorrThreads>(winner, psi, ld, n, m, x, r, r_lds, st, tr, dred);
+  if (threadIdx.x == 0) k_out[blockIdx.x] = best;
 }
 
 CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
@@ -158,9 +193,9 @@ CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
   return g;
 }
 
-hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* r,
-                              const CorrGeom& g, uint64_t* keys, float* x, DevState* st,
-                              mp_trace tr, hipStream_t s) {
+hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
+                              const CorrGeom& g, uint64_t* keys, long long k, long long max_iters,
+                              double thr, float* x, DevState* st, mp_trace tr, hipStream_t s) {
   const size_t lds = static_cast<size_t>(ld) * sizeof(float);
   static bool big_lds = false;  // residuals above 60 KB need the opt-in limit
   if (!big_lds && lds > 60 * 1024) {
@@ -169,8 +204,8 @@ hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m
     if (e != hipSuccess) return e;
     big_lds = true;
   }
-  k_mp_step_f32<<<dim3(g.grid), dim3(kCorrThreads), lds, s>>>(psi, ld, n, m, r, g.cols_per_wg,
-                                                              keys, x, st, tr);
+  k_mp_step_f32<<<dim3(g.grid), dim3(kCorrThreads), lds, s>>>(psi, ld, n, m, rbuf, g.cols_per_wg,
+                                                              keys, k, max_iters, thr, x, st, tr);
   return hipGetLastError();
 }
 

@@ -222,61 +222,10 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
     for (int j = 0; j < rescore_k; ++j) best = rescored[j] > best ? rescored[j] : best;
     const int idx = key_index(best);
     const float c = key_value(best);
-    if (idx < 0 || idx >= m || c == 0.0f) {  // c = 0: no atom correlates with r
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->reason = (idx < 0 || idx >= m) ? kStopInternal : MP_STOP_STALLED;
-        st->done = 1;
-      }
+    if (carried_winner_stops(idx, c, m, st)) return;
+    if (carried_update<kLpThreads>(idx, c, psi32, ld, r_lds, r_out, x, st, tr, k, max_iters, thr,
+                                   par ^ 1, dred))
       return;
-    }
-    // r_k = r_{k-1} - c psi_idx (padding rows stay +0) and ||r_k||^2 in FP64,
-    // each thread on its own float4s (the re-score has finished reading r)
-    const v4f* col = reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld);
-    v4f a[RPT];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int i = threadIdx.x + u * kLpThreads;
-      a[u] = col[i < ld4 ? i : ld4 - 1];
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int i = threadIdx.x + u * kLpThreads;
-      if (i < ld4) {
-        const v4f rv = r_lds[i];
-        v4f o;
-        o.x = __builtin_fmaf(-c, a[u].x, rv.x);
-        o.y = __builtin_fmaf(-c, a[u].y, rv.y);
-        o.z = __builtin_fmaf(-c, a[u].z, rv.z);
-        o.w = __builtin_fmaf(-c, a[u].w, rv.w);
-        r_lds[i] = o;
-        if (blockIdx.x == 0) r_out[i] = o;
-        s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
-             (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
-      }
-    }
-    const double rr = block_sum<kLpThreads>(s, dred);  // also orders the r_lds updates
-    const bool stop = !(rr > thr) || k >= max_iters;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      x[idx] += c;
-      const long long t = k - 1;
-      if (t < tr.cap) {
-        if (tr.idx) tr.idx[t] = idx;
-        if (tr.coef) tr.coef[t] = c;
-        if (tr.rr) tr.rr[t] = rr;
-      }
-      st->t = k;
-      st->rr = rr;
-      st->r_sel = par ^ 1;  // the half of rbuf that holds r
-      if (!(rr > thr)) {
-        st->reason = MP_STOP_CONVERGED;
-        st->done = 1;
-      } else if (k >= max_iters) {
-        st->reason = MP_STOP_MAX_ITERS;
-        st->done = 1;
-      }
-    }
-    if (stop) return;
   } else if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < ld4; i += kLpThreads) r_out[i] = r_lds[i];
     if (threadIdx.x == 0) st->r_sel = par ^ 1;

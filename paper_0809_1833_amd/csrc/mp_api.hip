@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <string>
 #include <vector>
 
@@ -111,18 +112,6 @@ void free_ctx(mp_ctx* c) {
   delete c;
 }
 
-// Enqueue one MP iteration of the FP32 path.
-hipError_t enqueue_iteration(mp_ctx* c, float* x, const mp_trace& tr, hipStream_t s,
-                             hipEvent_t e0, hipEvent_t e1) {
-  hipError_t e;
-  if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-  e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials, x,
-                             c->st, tr, s);
-  if (e != hipSuccess) return e;
-  if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
-  return hipSuccess;
-}
-
 // The current device, if it is a gfx950 this library was built for.
 mp_status open_device(int& dev, hipDeviceProp_t& prop) {
   int count = 0;
@@ -192,11 +181,19 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, Enqueue enqueue)
   long long slot_base[2] = {0, 0};
   int slot_len[2] = {0, 0};
   mp_status status = MP_OK;
+  // Launch j of a decode ran its correlation pass unless the run had stopped
+  // by then.  A run that stops after t steps stops in launch t+1 in the
+  // one-bit form; in the others in launch t (converged or out of steps: step
+  // t applied, no pass) or t+1 (no usable winner).  Only launches that ran a
+  // pass are timed.
   auto account = [&](int k) {
     if (!c->profiling) return;
-    const long long t_after = h_slot[k].t;
+    const mp::DevState& sl = h_slot[k];
+    const bool late = c->storage == MP_SIGN1 ||
+                      (sl.reason != MP_STOP_CONVERGED && sl.reason != MP_STOP_MAX_ITERS);
+    const long long stop_launch = sl.done ? sl.t + (late ? 1 : 0) : LLONG_MAX;
     for (int j = 0; j < slot_len[k]; ++j) {
-      if (slot_base[k] + j >= t_after) break;
+      if (slot_base[k] + j >= stop_launch) break;
       if ((slot_base[k] + j) % c->prof_every != 0) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
@@ -482,41 +479,38 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
       return hipSuccess;
     });
     if (st != MP_OK) return st;
-  } else if (c->storage == MP_BF16 || c->storage == MP_FP8_E4M3) {
-    // launch k takes step k (k >= 1) and runs pass k+1: T steps take T+1
-    // launches; r ends in the half the state names
+  } else {
+    // FP32, BF16, FP8: launch k takes step k (k >= 1) and runs pass k+1, so
+    // T steps take T+1 launches; r ends in the half the state names
     long long k = 0;
     const long long T = opts->max_iters;
     const double thr = c->h_st->thr;
     const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
       hipError_t e;
       if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-      e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
-                                c->r_work, c->geom, c->rescore_k, c->partials, k, T, thr, x,
-                                c->st, tr, s);
+      if (c->storage == MP_F32)
+        e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials,
+                                   k, T, thr, x, c->st, tr, s);
+      else
+        e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
+                                  c->r_work, c->geom, c->rescore_k, c->partials, k, T, thr, x,
+                                  c->st, tr, s);
       ++k;
       if (e != hipSuccess) return e;
       if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
       return hipSuccess;
     });
     if (st != MP_OK) return st;
-    HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (r)
-      HIP_TRY(c, hipMemcpyAsync(r, c->r_work + (c->h_st->r_sel ? c->ld : 0),
-                                c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    return finish_result(c, res);
-  } else {
-    const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
-      return enqueue_iteration(c, x, tr, s, e0, e1);
-    });
-    if (st != MP_OK) return st;
   }
 
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
-  if (r)
-    HIP_TRY(c, hipMemcpyAsync(r, c->r_work, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (r) {
+    // the one-bit form keeps its FP32 r in the first half; the others in the
+    // half the state names
+    const float* rs = c->r_work + (c->storage != MP_SIGN1 && c->h_st->r_sel ? c->ld : 0);
+    HIP_TRY(c, hipMemcpyAsync(r, rs, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
   HIP_TRY(c, hipStreamSynchronize(s));
   return finish_result(c, res);
 }

@@ -67,9 +67,11 @@ hipError_t launch_norms(const float* psi, int64_t ld, int64_t n, int64_t m, doub
                         int* nonfinite, hipStream_t s);
 hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t m, float* r,
                        DevState* st, double eps, long long max_iters, hipStream_t s);
-hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* r,
-                              const CorrGeom& g, uint64_t* keys, float* x, DevState* st,
-                              mp_trace tr, hipStream_t s);
+// Launch k of an FP32 decode: step k (k >= 1) and pass k+1.  rbuf: 2 x ld
+// floats (r in half k mod 2); keys: 2 halves x one per workgroup.
+hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
+                              const CorrGeom& g, uint64_t* keys, long long k, long long max_iters,
+                              double thr, float* x, DevState* st, mp_trace tr, hipStream_t s);
 
 // ---- kernels of the FP64 single-signal path (k_f64.hip) ---------------------
 hipError_t launch_norms_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* norm2,
