@@ -25,15 +25,29 @@ import json
 import os
 
 
-def _mean_counter(path: str, kernel_substr: str) -> tuple:
+def _counter(path: str, kernel_substr: str) -> list:
+    """The counter's value for each dispatch of the kernel, in dispatch order."""
     vals = []
     with open(path) as f:
         for row in csv.DictReader(f):
             if kernel_substr in row["Kernel_Name"]:
-                vals.append(float(row["Counter_Value"]))
+                vals.append((int(row["Dispatch_Id"]), float(row["Counter_Value"])))
     if not vals:
         raise SystemExit(f"no dispatch of {kernel_substr} in {path}")
-    return sum(vals) / len(vals), len(vals)
+    return [v for _, v in sorted(vals)]
+
+
+def _mean(vals) -> float:
+    return sum(vals) / len(vals)
+
+
+def pass_positions(fetch, min_fraction):
+    """Dispatch positions kept when launches without a correlation pass are
+    dropped: those whose FETCH_SIZE is at least min_fraction of the largest.
+    (A decode that carries each step into the next launch ends with a launch
+    that only applies the last step.)"""
+    top = max(fetch)
+    return [i for i, v in enumerate(fetch) if v >= min_fraction * top]
 
 
 def source_sha(paths) -> str:
@@ -58,24 +72,35 @@ def main():
     ap.add_argument("--copy-prefix", default="copy")
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--algorithmic-bytes", type=float, default=None)
+    ap.add_argument("--pass-only", type=float, default=None, metavar="FRACTION",
+                    help="drop dispatches whose FETCH_SIZE is below FRACTION of the largest "
+                         "(launches that ran no correlation pass) from both runs")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
 
-    f_k, nf = _mean_counter(os.path.join(a.fetch, f"{a.bench_prefix}_counter_collection.csv"),
-                            a.kernel)
-    w_k, nw = _mean_counter(os.path.join(a.write, f"{a.bench_prefix}_counter_collection.csv"),
-                            a.kernel)
-    f_c, _ = _mean_counter(os.path.join(a.fetch, f"{a.copy_prefix}_counter_collection.csv"),
-                           "k_copy")
-    w_c, _ = _mean_counter(os.path.join(a.write, f"{a.copy_prefix}_counter_collection.csv"),
-                           "k_copy")
+    fv = _counter(os.path.join(a.fetch, f"{a.bench_prefix}_counter_collection.csv"), a.kernel)
+    wv = _counter(os.path.join(a.write, f"{a.bench_prefix}_counter_collection.csv"), a.kernel)
+    dropped = 0
+    if a.pass_only is not None:
+        if len(fv) != len(wv):
+            raise SystemExit("FETCH and WRITE runs hold different dispatch counts")
+        keep = pass_positions(fv, a.pass_only)
+        dropped = len(fv) - len(keep)
+        fv = [fv[i] for i in keep]
+        wv = [wv[i] for i in keep]
+    f_k, nf = _mean(fv), len(fv)
+    w_k, nw = _mean(wv), len(wv)
+    f_c = _mean(_counter(os.path.join(a.fetch, f"{a.copy_prefix}_counter_collection.csv"),
+                         "k_copy"))
+    w_c = _mean(_counter(os.path.join(a.write, f"{a.copy_prefix}_counter_collection.csv"),
+                         "k_copy"))
     f_scale = a.copy_bytes / (f_c * 1024.0)
     w_scale = a.copy_bytes / (w_c * 1024.0)
     fetch = f_k * 1024.0 * f_scale
     write = w_k * 1024.0 * w_scale
     out = dict(kernel=a.kernel, kernel_sha=source_sha(a.source), n=a.n, m=a.m,
                fetch_kib_per_dispatch=f_k, write_kib_per_dispatch=w_k,
-               dispatches=dict(fetch=nf, write=nw),
+               dispatches=dict(fetch=nf, write=nw, dropped_without_pass=dropped),
                copy_fetch_kib=f_c, copy_write_kib=w_c, copy_bytes=a.copy_bytes,
                fetch_scale=f_scale, write_scale=w_scale,
                fetch_bytes_per_launch=round(fetch), write_bytes_per_launch=round(write),
