@@ -373,6 +373,9 @@ def main():
                     help="skip the Orthogonal Matching Pursuit decode added to the line")
     ap.add_argument("--no-phase", action="store_true",
                     help="skip the Fig. 1 experiment (reconstruction error grid) added to the line")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched leg: skip the FP32 comparison that decodes the same signals "
+                         "one by one")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every k-th iteration's kernel launch with HIP events")
     ap.add_argument("--max-iters", type=int, default=None,
@@ -463,7 +466,7 @@ def main():
     dec.close()
     if not args.no_batched:
         log("[bench] batched form (256 signals, shared dictionary)")
-        line["batched"] = bench_batched(args.seed)
+        line["batched"] = bench_batched(args.seed, sequential=not args.no_sequential)
     if not args.no_ragged:
         log("[bench] ragged instances (512 problems of uneven size)")
         line["ragged"] = bench_ragged(args.seed)

@@ -46,3 +46,15 @@ def test_tool_scales_and_filters(tmp_path):
     assert d["write_bytes_per_launch"] == 3 * 1024
     assert d["traffic_over_algorithmic"] == 1.0
     assert d["kernel_sha"] == traffic.source_sha([str(src)])
+
+
+def test_pmc_summary_means_per_dispatch(tmp_path):
+    from paper_0809_1833_amd.probe import pmc_summary
+    p = tmp_path / "b_counter_collection.csv"
+    p.write_text("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+                 "1,void mp::k_a<4>(int),X,10\n1,void mp::k_a<4>(int),Y,2\n"
+                 "2,void mp::k_a<4>(int),X,30\n2,void mp::k_a<4>(int),Y,4\n"
+                 "3,mp::k_b(int),X,5\n")
+    d = pmc_summary.summarize(str(p), ["k_a"])
+    assert list(d) == ["void mp::k_a<4>"]
+    assert d["void mp::k_a<4>"] == {"dispatches": 2, "mean_per_dispatch": {"X": 20.0, "Y": 3.0}}
