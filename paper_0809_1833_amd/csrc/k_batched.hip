@@ -15,9 +15,13 @@
 // workgroup per active signal, merges those into the signal's 8 best
 // candidates, re-scores them against the FP32 columns and the FP32 residual,
 // takes the best (smallest index on ties, eq. 16) and updates x~, r and the
-// FP64 stopping test for that signal.  Signals stop at their own iteration;
-// the last workgroup of each round compacts the list of active signals, so
-// the next round's product covers only those.
+// FP64 stopping test for that signal, and stores whether the signal goes on.
+// Signals stop at their own iteration.  The list of active signals is
+// compacted one round behind: an extra workgroup of round r's select drops
+// the signals that stopped in round r-1 (their flags, written before the
+// kernel boundary), so round r+1 covers at most the signals that stop in
+// round r, which its select skips.  No workgroup waits for another and no
+// atomics are used.
 #include "k_common.h"
 #include "k_lowp.h"
 #include "mp_internal.h"
@@ -95,30 +99,33 @@ __global__ __launch_bounds__(256) void k_tile_bf16(const float* __restrict__ psi
   }
 }
 
-// Stable compaction of the slots that are still running into act[1 - cur]
-// (one workgroup; `alive(j)` tells whether position j of the current list
-// stays).  Used once after init (from all slots) and by the last workgroup
-// of every select round.
-template <int NT, typename Alive>
-__device__ void compact_active(const int* __restrict__ act_cur, int nact, bool from_all,
-                               int* __restrict__ act_next, BState* __restrict__ bs, int cur,
-                               Alive alive) {
+// Stable compaction (one workgroup of NT threads): the positions j < n_in
+// with keep(j) go, in order, to list_out (their slot list_in[j], or j itself
+// when list_in is null) and src_out (j, when not null); returns the count in
+// every thread.
+template <int NT, typename Keep>
+__device__ int compact_list(const int* __restrict__ list_in, int n_in, Keep keep,
+                            int* __restrict__ list_out, int* __restrict__ src_out) {
   __shared__ int wsum[NT / kWave];
   __shared__ int base_s;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   if (threadIdx.x == 0) base_s = 0;
   __syncthreads();
-  for (int j0 = 0; j0 < nact; j0 += NT) {
+  for (int j0 = 0; j0 < n_in; j0 += NT) {
     const int j = j0 + threadIdx.x;
-    const int slot = j < nact ? (from_all ? j : act_cur[j]) : -1;
-    const bool keep = j < nact && alive(j, slot);
-    const unsigned long long bal = __ballot(keep);
+    const int jc = j < n_in ? j : 0;  // both loads issued together, in bounds
+    const int slot = list_in ? list_in[jc] : j;
+    const bool k = j < n_in && keep(jc);
+    const unsigned long long bal = __ballot(k);
     const int before = __popcll(bal & ((1ull << lane) - 1ull));
     if (lane == 0) wsum[wave] = __popcll(bal);
     __syncthreads();
     int off = base_s;
     for (int w = 0; w < wave; ++w) off += wsum[w];
-    if (keep) act_next[off + before] = slot;
+    if (k) {
+      list_out[off + before] = slot;
+      if (src_out) src_out[off + before] = j;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       int tot = 0;
@@ -127,20 +134,23 @@ __device__ void compact_active(const int* __restrict__ act_cur, int nact, bool f
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    bs->n_active[1 - cur] = base_s;
-    bs->cur = 1 - cur;
-  }
+  return base_s;
 }
 
+// After init: the running slots into list 0 (round 0's), their source
+// positions the identity and the flags "running before round 0" set.
+// keep holds four arrays of cap ints: flags of rounds with parity 0 and 1,
+// then source positions of lists 0 and 1.
 __global__ __launch_bounds__(kBThreads) void k_bcompact_init(int nslots, const BSlot* slots,
-                                                             int* act0, int* act1, BState* bs) {
-  // initial list into act[1 - 0]; then cur flips to 1 ... keep the convention
-  // "current list = act[cur]" by compacting from "all slots" into act1.
-  (void)act0;
-  compact_active<kBThreads>(nullptr, nslots, true, act1, bs, 0,
-                 [&](int, int slot) { return slots[slot].done == 0; });
-  if (threadIdx.x == 0) bs->arrive = 0u;
+                                                             int* act, int* keep, int64_t cap,
+                                                             BState* bs) {
+  const int n = compact_list<kBThreads>(nullptr, nslots,
+                                        [&](int j) { return slots[j].done == 0; }, act, nullptr);
+  for (int j = threadIdx.x; j < n; j += kBThreads) {
+    keep[cap + j] = 1;      // flags of "round -1"
+    keep[2 * cap + j] = j;  // list 0's source positions
+  }
+  if (threadIdx.x == 0) bs->n_active[0] = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -172,20 +182,18 @@ template <int TI>
 __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr(const uint16_t* __restrict__ psit,
                                                          int64_t ld, int64_t m,
                                                          const uint16_t* __restrict__ Rq,
-                                                         int64_t ldq,
-                                                         const int* __restrict__ act0,
-                                                         const int* __restrict__ act1,
+                                                         int64_t ldq, const int* __restrict__ acts,
+                                                         int64_t cap,
                                                          const BState* __restrict__ bs,
                                                          uint64_t* __restrict__ partials,
-                                                         int mtiles) {
+                                                         int mtiles, int par) {
   constexpr int TM = 16 * TI;
-  const int cur = bs->cur;
-  const int nact = bs->n_active[cur];
+  const int nact = bs->n_active[par];
+  const int* act = acts + par * cap;
   const int j0 = blockIdx.y * kBCorrTileB;
   if (j0 >= nact) return;  // workgroup-uniform
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const int* act = cur ? act1 : act0;
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * TM;
   const int koff = 8 * (lane / 16);
 
@@ -339,23 +347,47 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // ---------------------------------------------------------------------------
-// Per-signal selection, FP32 re-scoring and update; one workgroup per active
-// signal (position j of the current list).  The workgroup that arrives last
-// compacts the list for the next round.
+// Per-signal selection, FP32 re-scoring and update; one workgroup per
+// position j of the round's list (list par, the product's), and one more,
+// the grid's last, that compacts the list for the next round.  A signal that
+// stopped in the previous round (still on this list) is skipped.  Stores
+// the round's flag for position j: whether the signal goes on.
 __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m,
     float* __restrict__ R32, uint16_t* __restrict__ Rq, int64_t ldq, float* __restrict__ X,
-    int64_t ldx,
-    BSlot* __restrict__ slots, int* __restrict__ act0, int* __restrict__ act1,
-    BState* __restrict__ bs, const uint64_t* __restrict__ partials, int mtiles,
-    uint64_t* __restrict__ alive, int rescore_k, mp_trace tr) {
-  const int cur = bs->cur;
-  const int nact = bs->n_active[cur];
+    int64_t ldx, BSlot* __restrict__ slots, int* __restrict__ acts, int* __restrict__ keep,
+    int64_t cap, BState* __restrict__ bs, const uint64_t* __restrict__ partials, int mtiles,
+    int par, int rescore_k, mp_trace tr) {
+  const int nact = bs->n_active[par];
+  int* flags_now = keep + par * cap;
+  if (blockIdx.x == gridDim.x - 1) {
+    // next round's list: the positions whose signal was still running after
+    // the previous round (that round's flags, by the source position of each
+    // entry in the previous list), with their source positions
+    const int* flags_prev = keep + (par ^ 1) * cap;
+    const int* src_now = keep + (2 + par) * cap;
+    const int cnt = compact_list<kBSelThreads>(
+        acts + par * cap, nact, [&](int jj) { return flags_prev[src_now[jj]] != 0; },
+        acts + (par ^ 1) * cap, keep + (2 + (par ^ 1)) * cap);
+    if (threadIdx.x == 0) bs->n_active[par ^ 1] = cnt;
+    return;
+  }
   const int j = blockIdx.x;
   if (j >= nact) return;
-  const int* act = cur ? act1 : act0;
-  int* act_next = cur ? act0 : act1;
-  const int b = act[j];
+  const int b = acts[par * cap + j];
+  BSlot* sl = slots + b;
+  if (sl->done) {  // stopped in the previous round; the same value in every thread
+    if (threadIdx.x == 0) flags_now[j] = 0;
+    return;
+  }
+  // the signal's state, requested now rather than after the update
+  long long t0 = 0, tmax = 0;
+  double thr = 0.0;
+  if (threadIdx.x == 0) {
+    t0 = sl->t;
+    tmax = sl->max_iters;
+    thr = sl->thr;
+  }
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t wl[kBSelWaves][kBTopK];
   __shared__ uint64_t cand[kBTopK];
@@ -408,7 +440,6 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
   for (int q = 0; q < rescore_k; ++q) best = resc[q] > best ? resc[q] : best;
   const int idx = key_index(best);
   const float c = key_value(best);
-  BSlot* sl = slots + b;
   bool stop_now = false;
   if (best == 0 || idx < 0 || idx >= m) {
     stop_now = true;
@@ -446,7 +477,7 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     const double rr = block_sum<kBSelThreads>(s, dred);
     if (threadIdx.x == 0) {
       X[static_cast<int64_t>(b) * ldx + idx] += c;
-      const long long t = sl->t;
+      const long long t = t0;
       if (t < tr.cap) {
         const int64_t o = static_cast<int64_t>(b) * tr.cap + t;
         if (tr.idx) tr.idx[o] = idx;
@@ -455,38 +486,18 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
       }
       sl->t = t + 1;
       sl->rr = rr;
-      if (!(rr > sl->thr)) {
+      if (!(rr > thr)) {
         sl->done = 1;
         sl->reason = MP_STOP_CONVERGED;
-      } else if (t + 1 >= sl->max_iters) {
+        stop_now = true;
+      } else if (t + 1 >= tmax) {
         sl->done = 1;
         sl->reason = MP_STOP_MAX_ITERS;
+        stop_now = true;
       }
     }
   }
-  __syncthreads();
-  // publish whether this signal stays, count in; the last workgroup compacts
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    const uint64_t keep = sl->done ? 0ull : 1ull;
-    const uint64_t old = __hip_atomic_exchange(alive + j, keep + 2ull, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned inc = 1u + static_cast<unsigned>(old >> 63);
-    const unsigned prev =
-        __hip_atomic_fetch_add(&bs->arrive, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == static_cast<unsigned>(nact - 1);
-    if (s_last)
-      (void)__hip_atomic_exchange(&bs->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  // alive[j] = 2 + keep for every position of this round (set by the RMW
-  // above in each workgroup); read back with RMWs that also clear it
-  compact_active<kBSelThreads>(act, nact, false, act_next, bs, cur, [&](int jj, int) {
-    const uint64_t v = __hip_atomic_exchange(alive + jj, uint64_t{0}, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    return v == 3ull;
-  });
+  if (threadIdx.x == 0) flags_now[j] = stop_now ? 0 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -500,12 +511,12 @@ hipError_t launch_tile_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* o
 hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, float* X,
                         int64_t ldx, int64_t m, float* R32, uint16_t* Rq, int64_t ldq, BSlot* slots,
                         const long long* tcap, long long tcap_all, double eps, int nslots,
-                        int* act0, int* act1, BState* bs, hipStream_t s) {
+                        int* act, int* keep, int64_t cap, BState* bs, hipStream_t s) {
   k_binit<<<dim3(nslots), dim3(kBThreads), 0, s>>>(Y, ldy, n, ld, X, ldx, m, R32, Rq, ldq, slots,
                                                    tcap, tcap_all, eps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_bcompact_init<<<dim3(1), dim3(kBThreads), 0, s>>>(nslots, slots, act0, act1, bs);
+  k_bcompact_init<<<dim3(1), dim3(kBThreads), 0, s>>>(nslots, slots, act, keep, cap, bs);
   return hipGetLastError();
 }
 
@@ -516,20 +527,22 @@ int bcorr_mtiles(int64_t m, int tile_m) { return static_cast<int>((m + tile_m - 
 
 hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, int64_t n,
                          int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
-                         BSlot* slots, int* act0, int* act1, BState* bs, uint64_t* partials,
-                         uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
-                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                         BSlot* slots, int* act, int* keep, int64_t cap, BState* bs,
+                         uint64_t* partials, long long round, int nact_hint, int rescore_k,
+                         mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int tile_m = bcorr_tile_m(nact_hint);
   const int mtiles = bcorr_mtiles(m, tile_m);
   const int btiles = (nact_hint + kBCorrTileB - 1) / kBCorrTileB;  // >= the round's tiles
+  const int par = static_cast<int>(round & 1);
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+  const dim3 grid(mtiles, btiles > 0 ? btiles : 1);
   if (tile_m == 64)
-    k_bcorr<4><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act0, act1,
-                                                                    bs, partials, mtiles);
+    k_bcorr<4><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
+                                                     mtiles, par);
   else
-    k_bcorr<2><<<dim3(mtiles, btiles), dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act0, act1,
-                                                                    bs, partials, mtiles);
+    k_bcorr<2><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
+                                                     mtiles, par);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
   const size_t lds = static_cast<size_t>(ld) * sizeof(float);
@@ -540,9 +553,10 @@ hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, i
     if (e != hipSuccess) return e;
     big_lds = true;
   }
-  k_bselect<<<dim3(nact_hint), dim3(kBSelThreads), lds, s>>>(psi32, ld, n, m, R32, Rq, ldq, X, ldx,
-                                                             slots, act0, act1, bs, partials,
-                                                             mtiles, alive, rescore_k, tr);
+  // one workgroup per list position, and the compacting one last
+  k_bselect<<<dim3(nact_hint + 1), dim3(kBSelThreads), lds, s>>>(
+      psi32, ld, n, m, R32, Rq, ldq, X, ldx, slots, act, keep, cap, bs, partials, mtiles, par,
+      rescore_k, tr);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ void free_batched(mp_ctx* c) {
   (void)hipFree(c->b_act);
   (void)hipFree(c->b_state);
   (void)hipFree(c->b_partials);
-  (void)hipFree(c->b_alive);
+  (void)hipFree(c->b_keep);
   (void)hipFree(c->b_tcap);
   if (c->h_slots) (void)hipHostFree(c->h_slots);
   if (c->h_bstate) (void)hipHostFree(c->h_bstate);
@@ -54,7 +54,7 @@ void free_batched(mp_ctx* c) {
   c->b_act = nullptr;
   c->b_state = nullptr;
   c->b_partials = nullptr;
-  c->b_alive = nullptr;
+  c->b_keep = nullptr;
   c->b_tcap = nullptr;
   c->h_slots = nullptr;
   c->h_bstate = nullptr;
@@ -764,7 +764,7 @@ static mp_status ensure_batched(mp_ctx* c, int64_t B, hipStream_t s) {
             hipMalloc(&c->b_act, sizeof(int) * 2 * cap) == hipSuccess &&
             hipMalloc(&c->b_state, sizeof(mp::BState)) == hipSuccess &&
             hipMalloc(&c->b_partials, sizeof(uint64_t) * cap * mtiles * 8) == hipSuccess &&
-            hipMalloc(&c->b_alive, sizeof(uint64_t) * cap) == hipSuccess &&
+            hipMalloc(&c->b_keep, sizeof(int) * 4 * cap) == hipSuccess &&
             hipMalloc(&c->b_tcap, sizeof(long long) * cap) == hipSuccess &&
             hipHostMalloc(&c->h_slots, sizeof(mp::BSlot) * cap, hipHostMallocDefault) ==
                 hipSuccess &&
@@ -774,7 +774,7 @@ static mp_status ensure_batched(mp_ctx* c, int64_t B, hipStream_t s) {
     free_batched(c);
     return fail(c, MP_ENOMEM, "batched work buffers");
   }
-  HIP_TRY(c, hipMemsetAsync(c->b_alive, 0, sizeof(uint64_t) * cap, s));
+  HIP_TRY(c, hipMemsetAsync(c->b_keep, 0, sizeof(int) * 4 * cap, s));
   HIP_TRY(c, hipMemsetAsync(c->b_state, 0, sizeof(mp::BState), s));
   c->bcap = cap;
   return MP_OK;
@@ -825,12 +825,10 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
   if (max_iters_b)
     HIP_TRY(c, hipMemcpyAsync(c->b_tcap, max_iters_b, sizeof(long long) * B,
                               hipMemcpyHostToDevice, s));
-  int* act0 = c->b_act;
-  int* act1 = c->b_act + c->bcap;
   HIP_TRY(c, mp::launch_binit(Y, ldy, c->n, c->ld, X, ldx, c->m, c->b_r32, c->b_rq, c->ldq,
                               c->b_slots,
                               max_iters_b ? c->b_tcap : nullptr, opts->max_iters, opts->eps,
-                              static_cast<int>(B), act0, act1, c->b_state, s));
+                              static_cast<int>(B), c->b_act, c->b_keep, c->bcap, c->b_state, s));
 
   // Rounds in chunks, two chunks in flight; the kernels stop doing work once
   // the active list is empty.  No signal runs more than tmax rounds.
@@ -870,10 +868,9 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
           e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
         }
         hipError_t e = mp::launch_bround(c->psibt, c->psi32, c->ld, c->n, c->m, c->b_r32,
-                                         c->b_rq, c->ldq, X, ldx, c->b_slots, act0, act1,
-                                         c->b_state,
-                                         c->b_partials, c->b_alive, static_cast<int>(B),
-                                         nact_hint, rk, tr, s, e0, e1);
+                                         c->b_rq, c->ldq, X, ldx, c->b_slots, c->b_act,
+                                         c->b_keep, c->bcap, c->b_state, c->b_partials,
+                                         issued + j, nact_hint, rk, tr, s, e0, e1);
         if (e != hipSuccess) {
           status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
           break;
@@ -902,8 +899,12 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
       break;
     }
     --inflight;
+    // the length of the list the chunk's last round r left for round r+1
+    // (the signals still running after round r-1): an upper bound for every
+    // later round, zero once all have stopped
     const mp::BState& hb = c->h_bstate[old];
-    const int n_after = hb.n_active[hb.cur & 1];
+    const long long r_last = slot_base[old] + slot_len[old] - 1;
+    const int n_after = hb.n_active[(r_last + 1) & 1];
     account(old, n_after);
     // rounds already in flight were sized with the older hint, which is also
     // an upper bound; the count never increases

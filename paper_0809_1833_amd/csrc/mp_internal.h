@@ -133,11 +133,12 @@ struct BSlot {
   long long t, max_iters;
   int done, reason;
 };
-// Round state: the current active list is act[cur] with n_active[cur] entries.
+// Round state.  Round r's product and select run over active list r mod 2
+// (n_active[r mod 2] positions); the select also writes list (r+1) mod 2 for
+// the next round.
 struct BState {
-  int cur;
   int n_active[2];
-  unsigned arrive;  // workgroups of the current select launch that have counted in
+  int pad[2];
 };
 // The BF16 dictionary in the product's 16-atom x 32-element tiles
 // (round_up(m, 16) x ld elements).
@@ -146,16 +147,19 @@ hipError_t launch_tile_bf16(const float* psi, int64_t ld, int64_t m, uint16_t* o
 hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, float* X,
                         int64_t ldx, int64_t m, float* R32, uint16_t* Rq, int64_t ldq, BSlot* slots,
                         const long long* tcap, long long tcap_all, double eps, int nslots,
-                        int* act0, int* act1, BState* bs, hipStream_t s);
+                        int* act, int* keep, int64_t cap, BState* bs, hipStream_t s);
 int bcorr_tile_m(int nact_hint);
 int bcorr_mtiles(int64_t m, int tile_m);
-// One round.  nact_hint >= the number of active signals (the host's last
-// reading; the count only decreases): it sizes the grids and picks the tile.
+// Round `round` (0, 1, ...).  nact_hint >= the number of active signals (the
+// host's last reading; the count only decreases): it sizes the grids and
+// picks the tile.  act: two lists of cap slots; keep: 4 x cap ints (the
+// flags of rounds of parity 0 and 1, then the source positions of lists 0
+// and 1).
 hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, int64_t n,
                          int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
-                         BSlot* slots, int* act0, int* act1, BState* bs, uint64_t* partials,
-                         uint64_t* alive, int nslots, int nact_hint, int rescore_k, mp_trace tr,
-                         hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                         BSlot* slots, int* act, int* keep, int64_t cap, BState* bs,
+                         uint64_t* partials, long long round, int nact_hint, int rescore_k,
+                         mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // ---- many independent instances (k_ragged.hip) -------------------------------
 struct RInst {             // one instance, device-resident descriptor
@@ -241,7 +245,7 @@ struct mp_ctx {
   mp::BState* b_state = nullptr;
   mp::BState* h_bstate = nullptr;  // pinned, 2 entries
   uint64_t* b_partials = nullptr;  // bcap x mtiles x 8
-  uint64_t* b_alive = nullptr;     // bcap
+  int* b_keep = nullptr;           // 4 x bcap: round flags (2 x), list source positions (2 x)
   long long* b_tcap = nullptr;     // bcap
   // ragged contexts (mp_create_ragged): many instances, each its own dictionary
   bool ragged = false;
