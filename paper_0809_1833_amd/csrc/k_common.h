@@ -288,6 +288,96 @@ __device__ inline uint64_t take_slot(uint64_t* slot) {
   return __hip_atomic_exchange(slot, uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---- balanced column shares of the carried FP32 pass ---------------------
+//
+// Launch k takes its group shares from launch k-1's shares and pass
+// durations (both written before the kernel boundary): each group's rate
+// (columns per tick per workgroup), the count that would make every group
+// finish together, then a step of kBalStep from the old count toward it,
+// clamped to [cpw/2, 3 cpw/2] and rounded down, with one column added to
+// groups in turn until the shares cover all m columns.  Every workgroup computes the same
+// integers from the same inputs.  Workgroup b = 8q + g takes
+// [q * S + sum_{h<g} s_h, + s_g) clipped to m, S = sum_h s_h, so the ranges
+// tile [0, m) in blockIdx order.  Launch 0, grids that are not a multiple
+// of 8 and workgroups of fewer than four columns per wave use cpw each.
+//
+// dur_prev: this thread's workgroup-indexed duration of launch k-1 (thread
+// t < grid), sh_prev: share[par ^ 1][t] (t < 8); both requested by the
+// caller with its other loads.  Every thread calls; there are barriers.
+constexpr float kBalStep = 0.5f;
+
+template <int NT>
+__device__ void balanced_range(BalState* __restrict__ bal, int par, bool adapt, int grid,
+                               int64_t m, int cpw, unsigned dur_prev, int sh_prev,
+                               int64_t& col0, int64_t& col1) {
+  static_assert(NT >= kBalMaxGrid, "one duration per thread");
+  __shared__ unsigned s_dur[kBalMaxGrid];
+  __shared__ float s_rate[kBalGroups];
+  __shared__ int s_sh[kBalGroups];
+  const int t = threadIdx.x;
+  const int ngr = grid / kBalGroups;  // workgroups per group
+  adapt = adapt && grid % kBalGroups == 0 && cpw >= 64 && grid <= kBalMaxGrid;
+  if (adapt) {
+    if (t < grid) s_dur[t] = dur_prev;  // grid <= kBalMaxGrid <= NT
+    __syncthreads();
+    if (t < kBalGroups) {
+      float sum = 0.0f;
+      for (int q = 0; q < ngr; ++q) sum += static_cast<float>(s_dur[q * kBalGroups + t]);
+      const float mean = sum / static_cast<float>(ngr);
+      s_rate[t] = sh_prev > 0 && mean > 0.0f ? static_cast<float>(sh_prev) / mean : 0.0f;
+      s_sh[t] = sh_prev;
+    }
+    __syncthreads();
+    if (t == 0) {
+      bool ok = true;
+      float tot = 0.0f;
+      for (int g = 0; g < kBalGroups; ++g) {
+        ok = ok && s_rate[g] > 0.0f;
+        tot += s_rate[g];
+      }
+      int sh[kBalGroups];
+      int64_t cover = 0;
+      for (int g = 0; g < kBalGroups; ++g) {
+        float target = ok ? static_cast<float>(m) / static_cast<float>(ngr) * (s_rate[g] / tot)
+                          : static_cast<float>(cpw);
+        float v = ok ? (1.0f - kBalStep) * static_cast<float>(s_sh[g]) + kBalStep * target
+                     : target;
+        v = v < 0.5f * cpw ? 0.5f * cpw : (v > 1.5f * cpw ? 1.5f * cpw : v);
+        sh[g] = static_cast<int>(v);
+        cover += static_cast<int64_t>(ngr) * sh[g];
+      }
+      for (int g = 0; cover < m; g = (g + 1) % kBalGroups) {
+        ++sh[g];
+        cover += ngr;
+      }
+      for (int g = 0; g < kBalGroups; ++g) s_sh[g] = sh[g];
+    }
+    __syncthreads();
+  } else if (t < kBalGroups) {
+    s_sh[t] = cpw;
+  }
+  if (!adapt) __syncthreads();
+  int S = 0, before = 0;
+  const int g = static_cast<int>(blockIdx.x) % kBalGroups;
+  for (int h = 0; h < kBalGroups; ++h) {
+    S += s_sh[h];
+    before += h < g ? s_sh[h] : 0;
+  }
+  const int64_t q = static_cast<int64_t>(blockIdx.x) / kBalGroups;
+  col0 = adapt ? q * S + before : static_cast<int64_t>(blockIdx.x) * cpw;
+  col1 = col0 + (adapt ? s_sh[g] : cpw);
+  if (col0 > m) col0 = m;
+  if (col1 > m) col1 = m;
+  if (blockIdx.x == 0 && t < kBalGroups) bal->share[par][t] = adapt ? s_sh[t] : cpw;
+}
+
+// The workgroup's pass duration for the next launch (thread 0).
+__device__ inline void record_pass_time(BalState* __restrict__ bal, int par,
+                                        unsigned long long t_begin) {
+  if (threadIdx.x == 0 && blockIdx.x < kBalMaxGrid)
+    bal->dur[par][blockIdx.x] = static_cast<unsigned>(wall_clock64() - t_begin);
+}
+
 // ---- steps carried into the next launch ------------------------------------
 //
 // The FP32 and reduced-precision forms finish step k at the start of launch

@@ -105,8 +105,9 @@ hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t 
 // smallest index, eq. 16), apply step k to their LDS copy of r and compute
 // ||r_k||^2 in FP64 (carried_update: workgroup 0 also stores r_k in the
 // other half and keeps x~, the trace and the state); unless the run stops
-// there, each runs pass k+1: wave w of workgroup b takes columns
-// b*cpw + w, + 16, ... and streams each column with 16-byte non-temporal
+// there, each runs pass k+1 over its share of the columns (balanced between
+// the XCDs from the previous launch's timings): wave w takes columns
+// col0 + w, + 16, ... and streams each column with 16-byte non-temporal
 // loads (two per-lane FP32 FMA chains over the column halves, then a
 // butterfly sum across the wave), keys are max-reduced per wave and across
 // the 16 waves, and the workgroup stores its key for launch k+1.  Launch 0
@@ -115,8 +116,9 @@ constexpr int kCorrThreads = 1024;
 
 __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
     const float* __restrict__ psi, int64_t ld, int64_t n, int64_t m, float* __restrict__ rbuf,
-    int cols_per_wg, uint64_t* __restrict__ keys, long long k, long long max_iters, double thr,
-    float* __restrict__ x, DevState* __restrict__ st, mp_trace tr) {
+    int cols_per_wg, uint64_t* __restrict__ keys, BalState* __restrict__ bal, long long k,
+    long long max_iters, double thr, float* __restrict__ x, DevState* __restrict__ st,
+    mp_trace tr) {
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t kred[kCorrThreads / kWave];
   __shared__ double dred[kCorrThreads / kWave];
@@ -143,6 +145,8 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   }
   uint64_t kp = k_in[static_cast<int>(threadIdx.x) < nk ? static_cast<int>(threadIdx.x) : nk - 1];
   if (first || static_cast<int>(threadIdx.x) >= nk) kp = 0;
+  const unsigned dur_prev = bal->dur[par ^ 1][static_cast<int>(threadIdx.x) < nk ? threadIdx.x : 0];
+  const int sh_prev = bal->share[par ^ 1][threadIdx.x % kBalGroups];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
     const int i = threadIdx.x + u * kCorrThreads;
@@ -151,6 +155,9 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   if (threadIdx.x == 0) s_done = done_v;  // one value for the whole workgroup
   __syncthreads();
   if (s_done) return;
+  int64_t col0, col1;
+  balanced_range<kCorrThreads>(bal, par, !first, nk, m, cols_per_wg, dur_prev, sh_prev, col0,
+                               col1);
 
   if (!first) {
     const uint64_t win = block_max<kCorrThreads>(kp, kred);
@@ -166,9 +173,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   }
 
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
-  int64_t col1 = col0 + cols_per_wg;
-  if (col1 > m) col1 = m;
+  const unsigned long long t_begin = wall_clock64();
   uint64_t best = 0;
   for (int64_t col = col0 + wave; col < col1; col += kCorrThreads / kWave) {
     const float c = dot_column_f32(reinterpret_cast<const v4f*>(psi + col * ld), r_lds, ld4, lane);
@@ -177,6 +182,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   }
   best = block_max<kCorrThreads>(best, kred);
   if (threadIdx.x == 0) k_out[blockIdx.x] = best;
+  record_pass_time(bal, par, t_begin);
 }
 
 CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
@@ -194,8 +200,9 @@ CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
 }
 
 hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
-                              const CorrGeom& g, uint64_t* keys, long long k, long long max_iters,
-                              double thr, float* x, DevState* st, mp_trace tr, hipStream_t s) {
+                              const CorrGeom& g, uint64_t* keys, BalState* bal, long long k,
+                              long long max_iters, double thr, float* x, DevState* st, mp_trace tr,
+                              hipStream_t s) {
   const size_t lds = static_cast<size_t>(ld) * sizeof(float);
   static bool big_lds = false;  // residuals above 60 KB need the opt-in limit
   if (!big_lds && lds > 60 * 1024) {
@@ -204,8 +211,8 @@ hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m
     if (e != hipSuccess) return e;
     big_lds = true;
   }
-  k_mp_step_f32<<<dim3(g.grid), dim3(kCorrThreads), lds, s>>>(psi, ld, n, m, rbuf, g.cols_per_wg,
-                                                              keys, k, max_iters, thr, x, st, tr);
+  k_mp_step_f32<<<dim3(g.grid), dim3(kCorrThreads), lds, s>>>(
+      psi, ld, n, m, rbuf, g.cols_per_wg, keys, bal, k, max_iters, thr, x, st, tr);
   return hipGetLastError();
 }
 

@@ -107,6 +107,7 @@ void free_ctx(mp_ctx* c) {
   (void)hipFree(c->r_work);
   (void)hipFree(c->st);
   (void)hipFree(c->partials);
+  (void)hipFree(c->bal);
   if (c->h_st) (void)hipHostFree(c->h_st);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
@@ -342,6 +343,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   const size_t nkeys = 2 * static_cast<size_t>(c->geom.grid) * mp::kLpTopK;
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
+  if (hipMalloc(&c->bal, sizeof(mp::BalState)) != hipSuccess) return bail(MP_ENOMEM, "shares");
   if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
     return bail(MP_ENOMEM, "pinned state");
 
@@ -351,6 +353,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
                          n * sizeof(float), m, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, 2 * c->ld * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->bal, 0, sizeof(mp::BalState), s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
 
   // Column norms in FP64 (eq. 4): finiteness always, unit norm unless skipped.
@@ -490,7 +493,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
       if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
       if (c->storage == MP_F32)
         e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials,
-                                   k, T, thr, x, c->st, tr, s);
+                                   c->bal, k, T, thr, x, c->st, tr, s);
       else
         e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
                                   c->r_work, c->geom, c->rescore_k, c->partials, k, T, thr, x,

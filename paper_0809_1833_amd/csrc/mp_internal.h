@@ -55,6 +55,19 @@ __host__ __device__ inline float key_value(uint64_t k) {
   return __builtin_bit_cast(float, ab | (sg << 31));
 }
 
+// Column shares of the carried FP32 pass.  The workgroups with the same
+// blockIdx mod kBalGroups form a group (one XCD when workgroups go to the
+// XCDs in turn) and take the same number of columns; each launch moves the
+// groups' counts toward the column rates measured in the previous launch's
+// pass.  Which workgroup streams a column does not change its correlation,
+// so results do not depend on the shares.
+constexpr int kBalGroups = 8;
+constexpr int kBalMaxGrid = 1024;
+struct BalState {  // device memory, per context, zeroed at creation
+  int share[2][kBalGroups];      // columns per workgroup of each group, by launch parity
+  unsigned dur[2][kBalMaxGrid];  // pass durations (wall-clock ticks), by launch parity
+};
+
 // Launch geometry of the FP32 correlation pass.
 struct CorrGeom {
   int cols_per_wg;  // columns handled by one workgroup
@@ -70,8 +83,9 @@ hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t 
 // Launch k of an FP32 decode: step k (k >= 1) and pass k+1.  rbuf: 2 x ld
 // floats (r in half k mod 2); keys: 2 halves x one per workgroup.
 hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
-                              const CorrGeom& g, uint64_t* keys, long long k, long long max_iters,
-                              double thr, float* x, DevState* st, mp_trace tr, hipStream_t s);
+                              const CorrGeom& g, uint64_t* keys, BalState* bal, long long k,
+                              long long max_iters, double thr, float* x, DevState* st, mp_trace tr,
+                              hipStream_t s);
 
 // ---- kernels of the FP64 single-signal path (k_f64.hip) ---------------------
 hipError_t launch_norms_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* norm2,
@@ -224,6 +238,7 @@ struct mp_ctx {
   mp::DevState* st = nullptr;    // device state
   mp::DevState* h_st = nullptr;  // pinned host mirror
   uint64_t* partials = nullptr;  // key slots: kLpTopK per correlation workgroup
+  mp::BalState* bal = nullptr;   // column shares and pass timings of the FP32 pass
   mp::CorrGeom geom{};
   // profiling of the correlation kernel
   bool profiling = false;

@@ -88,3 +88,41 @@ def test_parity_large_m(storage, n, m):
         rep = run_parity(psi, y, 1e-6, 60, solve)
     print(rep, flush=True)
     assert rep.prefix >= min(rep.iters_ora, 10), rep
+
+
+@pytest.mark.parametrize("n,m", [(256, 24576), (64, 16384)])
+def test_parity_balanced_shares(n, m):
+    """FP32 decodes whose passes split the columns by measured workgroup
+    speed (256 workgroups of 96 and 64 columns on average): every pass after
+    the first uses shares computed from the previous pass's timings, so a
+    gap or overlap between workgroups' ranges would surface as a different
+    selection over the 150 steps."""
+    from paper_0809_1833_amd.mp import Decoder
+    rng = np.random.default_rng(3 * m + n)
+    psi = mpgen.gaussian_unit_dictionary(rng, n, m)
+    x, sup = mpgen.sparse_signal(rng, rng, m, max(4, n // 16))
+    y = mpgen.encode(psi, x, sup)
+    yd = torch.from_numpy(np.asarray(y, dtype=np.float32)).cuda()
+    print(f"[balanced {n}x{m}]", flush=True)
+    with Decoder(_dev(psi), storage="f32") as dec:
+        def solve(eps, max_iters, cap):
+            out = dec.solve(yd, eps, max_iters, trace_cap=cap)
+            torch.cuda.synchronize()
+            res = dict(x=_np(out["x"]), r=_np(out["r"]), iters=out["iters"], stop=out["stop"],
+                       rr=out["rr"], yy=out["yy"])
+            if cap:
+                res.update(idx=_np(out["idx"]), coef=_np(out["coef"]),
+                           rr_trace=_np(out["rr_trace"]))
+            else:
+                res.update(idx=np.zeros(0, np.int32), coef=np.zeros(0, np.float32),
+                           rr_trace=np.zeros(0))
+            return res
+        rep = run_parity(psi, y, 1e-6, 150, solve)
+        # decodes on the same context split their passes by their own
+        # timings, which differ run to run; the results must not
+        first = solve(1e-6, 150, 150)
+        again = solve(1e-6, 150, 150)
+    print(rep, flush=True)
+    assert rep.prefix >= min(rep.iters_ora, 40), rep
+    assert np.array_equal(first["idx"], again["idx"]) and np.array_equal(first["x"], again["x"])
+    assert np.array_equal(first["r"], again["r"])
