@@ -9,10 +9,10 @@
 // then across the wave.  A candidate is a pair of 64-bit words so that the
 // exact FP64 coefficient survives the argmax: the |c| bits (a non-negative
 // double orders like its bit pattern), then (0x7FFFFFFF - index) and the
-// sign; the pair order is "larger |c|, then smaller index" (eq. 16).  Each
-// workgroup hands its pair to the last workgroup to arrive through the same
-// RMW-only protocol as the FP32 form, and that workgroup updates x~ and r and
-// applies the FP64 stopping test.
+// sign; the pair order is "larger |c|, then smaller index" (eq. 16).  The
+// selection is carried into the next launch, where every workgroup takes the
+// winner from the stored pairs, updates its copy of r and applies the FP64
+// stopping test.
 #include "k_common.h"
 #include "k_key2.h"
 #include "mp_internal.h"
@@ -124,26 +124,127 @@ __global__ __launch_bounds__(256) void k_init_f64(const double* __restrict__ y, 
 }
 
 // ---------------------------------------------------------------------------
-// One MP iteration in one launch (eqs. 9-12).  Wave w of workgroup b takes
-// columns b*cpw + w, + 16, ...; the workgroup's best pair is handed to the
-// last workgroup, which selects, updates and tests.
+// One MP step per launch (eqs. 9-12), the selection carried into the next
+// launch as in the FP32 form.  Launch k (k >= 1): every workgroup stages
+// r_{k-1} (half k mod 2 of the residual buffer) in LDS and reads the pairs
+// the workgroups of launch k-1 stored; all take the same winner, apply step
+// k to their LDS copy (r -= c psi_idx, FP64 FMAs) and reduce ||r_k||^2 in the
+// same order, so all reach the same stop decision; workgroup 0 stores r_k in
+// the other half and keeps x~, the trace and the state.  Unless the run
+// stops, each runs pass k+1 over its share of the columns (balanced between
+// the XCDs from the previous launch's pass times, as in the FP32 form) and
+// stores its best pair.  Launch 0 runs the first pass on r = y; T steps take
+// T+1 launches.
 __global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
-    const double* __restrict__ psi, int64_t ld, int64_t n, int64_t m, double* __restrict__ r,
-    int cols_per_wg, uint64_t* __restrict__ keys, double* __restrict__ x,
-    DevState* __restrict__ st, mp_trace_f64 tr) {
-  if (st->done) return;
+    const double* __restrict__ psi, int64_t ld, int64_t n, int64_t m, double* __restrict__ rbuf,
+    int cols_per_wg, uint64_t* __restrict__ keys, BalState* __restrict__ bal, long long k,
+    long long max_iters, double thr, double* __restrict__ x, DevState* __restrict__ st,
+    mp_trace_f64 tr) {
   extern __shared__ v2d r2_lds[];
   __shared__ Key2 kred[kF64Waves];
   __shared__ double dred[kF64Waves];
+  __shared__ int s_done;
+  constexpr int RPT = 16384 / 2 / kF64Threads;  // 16-byte chunks of r per thread (ld <= 16384)
   const int ld2 = static_cast<int>(ld / 2);
-  const v2d* r2 = reinterpret_cast<const v2d*>(r);
-  for (int i = threadIdx.x; i < ld2; i += kF64Threads) r2_lds[i] = r2[i];
-  __syncthreads();
+  const int par = static_cast<int>(k & 1);
+  const bool first = k == 0;
+  const v2d* r_in = reinterpret_cast<const v2d*>(rbuf + (par ? ld : 0));
+  v2d* r_out = reinterpret_cast<v2d*>(rbuf + (par ? 0 : ld));
+  const int nk = static_cast<int>(gridDim.x);  // <= kF64Threads (host-checked)
+  const uint64_t* k_in = keys + (par ? 2 * nk : 0);
+  uint64_t* k_out = keys + (par ? 0 : 2 * nk);
+  const int t = static_cast<int>(threadIdx.x);
 
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
-  int64_t col1 = col0 + cols_per_wg;
-  if (col1 > m) col1 = m;
+  // requests first, all unconditional (clamped indices into valid memory)
+  int done_v = 0;
+  if (t == 0) done_v = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v2d rq[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = t + u * kF64Threads;
+    rq[u] = r_in[i < ld2 ? i : ld2 - 1];
+  }
+  const int tc = t < nk ? t : nk - 1;
+  Key2 kp{k_in[2 * tc], k_in[2 * tc + 1]};
+  if (first || t >= nk) kp = Key2{0, 0};
+  const unsigned dur_prev = bal->dur[par ^ 1][tc];
+  const int sh_prev = bal->share[par ^ 1][t % kBalGroups];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int i = t + u * kF64Threads;
+    if (i < ld2) r2_lds[i] = rq[u];
+  }
+  if (t == 0) s_done = done_v;  // one value for the whole workgroup
+  __syncthreads();
+  if (s_done) return;
+  int64_t col0, col1;
+  balanced_range<kF64Threads>(bal, par, !first, nk, m, cols_per_wg, dur_prev, sh_prev, col0,
+                              col1);
+
+  if (!first) {
+    const Key2 w = block_max_key2<kF64Threads>(kp, kred);
+    const int idx = key2_index(w);
+    const double c = key2_value(w);
+    const bool bad = w.lo == 0 || idx < 0 || idx >= m;  // no published pair is
+    if (bad || c == 0.0) {  // c = 0: no atom correlates with r
+      if (blockIdx.x == 0 && t == 0) {
+        st->reason = bad ? kStopInternal : MP_STOP_STALLED;
+        st->done = 1;
+      }
+      return;
+    }
+    // r <- r - c psi_idx on the LDS copy, all column loads first; padding
+    // rows stay +0
+    const v2d* colp = reinterpret_cast<const v2d*>(psi + static_cast<int64_t>(idx) * ld);
+    v2d a[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = t + u * kF64Threads;
+      a[u] = colp[i < ld2 ? i : ld2 - 1];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = t + u * kF64Threads;
+      if (i < ld2) {
+        const v2d rv = r2_lds[i];
+        v2d o;
+        o.x = __builtin_fma(-c, a[u].x, rv.x);
+        o.y = __builtin_fma(-c, a[u].y, rv.y);
+        r2_lds[i] = o;
+        if (blockIdx.x == 0) r_out[i] = o;
+        s = __builtin_fma(o.x, o.x, s);
+        s = __builtin_fma(o.y, o.y, s);
+      }
+    }
+    const double rr = block_sum<kF64Threads>(s, dred);  // its barriers order the LDS writes
+    if (blockIdx.x == 0 && t == 0) {
+      x[idx] += c;
+      const long long tt = k - 1;
+      if (tt < tr.cap) {
+        if (tr.idx) tr.idx[tt] = idx;
+        if (tr.coef) tr.coef[tt] = c;
+        if (tr.rr) tr.rr[tt] = rr;
+      }
+      st->t = k;
+      st->rr = rr;
+      st->r_sel = par ^ 1;
+      if (!(rr > thr)) {
+        st->reason = MP_STOP_CONVERGED;
+        st->done = 1;
+      } else if (k >= max_iters) {
+        st->reason = MP_STOP_MAX_ITERS;
+        st->done = 1;
+      }
+    }
+    if (!(rr > thr) || k >= max_iters) return;
+  } else if (blockIdx.x == 0) {
+    for (int i = t; i < ld2; i += kF64Threads) r_out[i] = r2_lds[i];
+    if (t == 0) st->r_sel = par ^ 1;
+  }
+
+  const int lane = t % kWave, wave = t / kWave;
+  const unsigned long long t_begin = wall_clock64();
   Key2 best{0, 0};
   for (int64_t col = col0 + wave; col < col1; col += kF64Waves) {
     const double c =
@@ -151,76 +252,9 @@ __global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
     best = key2_max(best, make_key2(c, static_cast<int>(col)));
   }
   best = block_max_key2<kF64Threads>(best, kred);
-  // lane 0 of wave 0 publishes the |c| word, lane 1 the index word
-  if (!publish_arrive<2>(lane == 0 ? best.hi : best.lo, keys, st)) return;
-
-  // ---- last workgroup: the launch's winner ----
-  Key2 w{0, 0};
-  for (int i = threadIdx.x; i < static_cast<int>(gridDim.x); i += kF64Threads) {
-    const Key2 k{take_slot(keys + 2 * i), take_slot(keys + 2 * i + 1)};
-    w = key2_max(w, k);
-  }
-  w = block_max_key2<kF64Threads>(w, kred);
-  const int idx = key2_index(w);
-  const double c = key2_value(w);
-  if (w.lo == 0 || idx < 0 || idx >= m) {  // cannot happen for a published pair
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = kStopInternal;
-    }
-    return;
-  }
-  if (c == 0.0) {  // no atom correlates with r
-    if (threadIdx.x == 0) {
-      st->done = 1;
-      st->reason = MP_STOP_STALLED;
-    }
-    return;
-  }
-  // r <- r - c psi_idx from the LDS copy of r; all column loads first (ld <=
-  // 16384 gives at most P chunks per thread), padding rows stay +0
-  constexpr int P = 16384 / 2 / kF64Threads;
-  const v2d* colp = reinterpret_cast<const v2d*>(psi + static_cast<int64_t>(idx) * ld);
-  v2d* rw = reinterpret_cast<v2d*>(r);
-  v2d a[P];
-#pragma unroll
-  for (int u = 0; u < P; ++u) {
-    const int i = threadIdx.x + u * kF64Threads;
-    if (i < ld2) a[u] = colp[i];
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int u = 0; u < P; ++u) {
-    const int i = threadIdx.x + u * kF64Threads;
-    if (i < ld2) {
-      const v2d rv = r2_lds[i];
-      v2d o;
-      o.x = __builtin_fma(-c, a[u].x, rv.x);
-      o.y = __builtin_fma(-c, a[u].y, rv.y);
-      rw[i] = o;
-      s = __builtin_fma(o.x, o.x, s);
-      s = __builtin_fma(o.y, o.y, s);
-    }
-  }
-  const double rr = block_sum<kF64Threads>(s, dred);
-  if (threadIdx.x == 0) {
-    x[idx] += c;
-    const long long t = st->t;
-    if (t < tr.cap) {
-      if (tr.idx) tr.idx[t] = idx;
-      if (tr.coef) tr.coef[t] = c;
-      if (tr.rr) tr.rr[t] = rr;
-    }
-    st->t = t + 1;
-    st->rr = rr;
-    if (!(rr > st->thr)) {
-      st->done = 1;
-      st->reason = MP_STOP_CONVERGED;
-    } else if (t + 1 >= st->max_iters) {
-      st->done = 1;
-      st->reason = MP_STOP_MAX_ITERS;
-    }
-  }
+  if (t == 0) k_out[2 * blockIdx.x] = best.hi;
+  if (t == 1) k_out[2 * blockIdx.x + 1] = best.lo;
+  record_pass_time(bal, par, t_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,8 +277,9 @@ hipError_t launch_init_f64(const double* y, int64_t n, int64_t ld, double* x, in
   return hipGetLastError();
 }
 
-hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* r,
-                              const CorrGeom& g, uint64_t* keys, double* x, DevState* st,
+hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* rbuf,
+                              const CorrGeom& g, uint64_t* keys, BalState* bal, long long k,
+                              long long max_iters, double thr, double* x, DevState* st,
                               mp_trace_f64 tr, hipStream_t s) {
   const size_t lds = static_cast<size_t>(ld) * sizeof(double);
   static size_t lds_set = 60 * 1024;  // above the default limit the opt-in is raised
@@ -255,8 +290,8 @@ hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t 
     if (e != hipSuccess) return e;
     lds_set = lds;
   }
-  k_mp_step_f64<<<dim3(g.grid), dim3(kF64Threads), lds, s>>>(psi, ld, n, m, r, g.cols_per_wg,
-                                                              keys, x, st, tr);
+  k_mp_step_f64<<<dim3(g.grid), dim3(kF64Threads), lds, s>>>(
+      psi, ld, n, m, rbuf, g.cols_per_wg, keys, bal, k, max_iters, thr, x, st, tr);
   return hipGetLastError();
 }
 

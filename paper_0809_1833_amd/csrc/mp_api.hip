@@ -612,13 +612,17 @@ mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, i
   };
   const size_t psi_bytes = static_cast<size_t>(c->ld) * static_cast<size_t>(m) * sizeof(double);
   if (hipMalloc(&c->psi64, psi_bytes) != hipSuccess) return bail(MP_ENOMEM, "dictionary copy");
-  if (hipMalloc(&c->r64_work, c->ld * sizeof(double)) != hipSuccess) return bail(MP_ENOMEM, "r");
+  // r in two halves that alternate by launch parity
+  if (hipMalloc(&c->r64_work, 2 * c->ld * sizeof(double)) != hipSuccess)
+    return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
   if (c->geom.grid * 2 > 2 * 1024)
     return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
-  const size_t nkeys = static_cast<size_t>(c->geom.grid) * 2;  // two words per workgroup
+  // two words per workgroup, in two halves that alternate by launch parity
+  const size_t nkeys = static_cast<size_t>(c->geom.grid) * 4;
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
+  if (hipMalloc(&c->bal, sizeof(mp::BalState)) != hipSuccess) return bail(MP_ENOMEM, "shares");
   if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
     return bail(MP_ENOMEM, "pinned state");
 
@@ -626,7 +630,8 @@ mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, i
   if (e == hipSuccess)
     e = hipMemcpy2DAsync(c->psi64, c->ld * sizeof(double), psi, ld * sizeof(double),
                          n * sizeof(double), m, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(c->r64_work, 0, c->ld * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->r64_work, 0, 2 * c->ld * sizeof(double), s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->bal, 0, sizeof(mp::BalState), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
 
@@ -726,11 +731,17 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
                                  static_cast<long long>(opts->max_iters), s));
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  const mp_status st = run_iterations(c, opts->max_iters, s, [&](hipEvent_t e0, hipEvent_t e1) {
+  // launch k takes step k (k >= 1) and runs pass k+1: T steps take T+1
+  // launches; r ends in the half the state names
+  long long k = 0;
+  const long long T = opts->max_iters;
+  const double thr = c->h_st->thr;
+  const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
     e = mp::launch_mp_step_f64(c->psi64, c->ld, c->n, c->m, c->r64_work, c->geom, c->partials,
-                               x, c->st, tr, s);
+                               c->bal, k, T, thr, x, c->st, tr, s);
+    ++k;
     if (e != hipSuccess) return e;
     if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
     return hipSuccess;
@@ -738,8 +749,10 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
   if (st != MP_OK) return st;
 
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
   if (r)
-    HIP_TRY(c, hipMemcpyAsync(r, c->r64_work, c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(r, c->r64_work + (c->h_st->r_sel ? c->ld : 0),
+                              c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   return finish_result(c, res);
 }

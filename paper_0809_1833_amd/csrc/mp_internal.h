@@ -55,7 +55,7 @@ __host__ __device__ inline float key_value(uint64_t k) {
   return __builtin_bit_cast(float, ab | (sg << 31));
 }
 
-// Column shares of the carried FP32 pass.  The workgroups with the same
+// Column shares of the carried FP32 and FP64 passes.  The workgroups with the same
 // blockIdx mod kBalGroups form a group (one XCD when workgroups go to the
 // XCDs in turn) and take the same number of columns; each launch moves the
 // groups' counts toward the column rates measured in the previous launch's
@@ -93,8 +93,11 @@ hipError_t launch_norms_f64(const double* psi, int64_t ld, int64_t n, int64_t m,
 hipError_t launch_init_f64(const double* y, int64_t n, int64_t ld, double* x, int64_t m,
                            double* r, DevState* st, double eps, long long max_iters,
                            hipStream_t s);
-hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* r,
-                              const CorrGeom& g, uint64_t* keys, double* x, DevState* st,
+// Launch k of an FP64 decode: step k (k >= 1) and pass k+1.  rbuf: 2 x ld
+// doubles (r in half k mod 2); keys: 2 halves x two words per workgroup.
+hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t m, double* rbuf,
+                              const CorrGeom& g, uint64_t* keys, BalState* bal, long long k,
+                              long long max_iters, double thr, double* x, DevState* st,
                               mp_trace_f64 tr, hipStream_t s);
 
 // ---- sign-bit Bernoulli dictionary (k_sign.hip) ------------------------------
@@ -238,7 +241,7 @@ struct mp_ctx {
   mp::DevState* st = nullptr;    // device state
   mp::DevState* h_st = nullptr;  // pinned host mirror
   uint64_t* partials = nullptr;  // key slots: kLpTopK per correlation workgroup
-  mp::BalState* bal = nullptr;   // column shares and pass timings of the FP32 pass
+  mp::BalState* bal = nullptr;   // column shares and pass timings (FP32, FP64 passes)
   mp::CorrGeom geom{};
   // profiling of the correlation kernel
   bool profiling = false;
