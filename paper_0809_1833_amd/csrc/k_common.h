@@ -236,7 +236,7 @@ __device__ inline float dot_chain_f32(const v4f* __restrict__ p, const v4f* __re
   return acc;
 }
 
-// ---- hand-off from all workgroups of a launch to the last one ---------------
+// ---- hand-off from all workgroups of a launch to the last one (OMP) ---------
 //
 // Each workgroup publishes K keys into its own K slots of `keys` and counts
 // itself in; publish_arrive returns true (in every thread) only in the

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
 }
 
 CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
-  // One 16-wave workgroup per CU (one LDS copy of r per CU, few arrivals);
+  // One 16-wave workgroup per CU (one LDS copy of r per CU, few keys);
   // a workgroup takes at least one column per wave.
   constexpr int64_t kWaves = kCorrThreads / kWave;
   const int64_t target = num_cus > 0 ? num_cus : 256;

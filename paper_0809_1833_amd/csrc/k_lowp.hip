@@ -4,10 +4,10 @@
 // FP8 (OCP E4M3, "e4m3fn") copy with one FP32 scale per column, and
 // accumulates in FP32 against the FP32 residual.  Because the reduced
 // precision can reorder near-equal correlations, each pass keeps the 8 best
-// candidates rather than 1; the last workgroup re-scores up to 8 of them
-// against the FP32 columns (the same FP32 inner product the FP32 form
-// computes, each column's two chains on two waves) and takes the best of
-// those, smallest index on ties (eq. 16).
+// candidates rather than 1; at the start of the next launch every workgroup
+// re-scores up to 8 of them against the FP32 columns (the same FP32 inner
+// product the FP32 form computes, each column's two chains on two waves) and
+// takes the best of those, smallest index on ties (eq. 16).
 // The coefficient and residual updates (eqs. 10-11) and the FP64 stopping
 // test then use the FP32 column and the re-scored FP32 coefficient.
 //

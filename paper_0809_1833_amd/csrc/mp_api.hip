@@ -339,7 +339,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
     return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
   if (c->geom.grid * mp::kLpTopK > 2 * 1024)
-    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
+    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key slots hold");
   const size_t nkeys = 2 * static_cast<size_t>(c->geom.grid) * mp::kLpTopK;
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
@@ -617,7 +617,7 @@ mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, i
     return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
   if (c->geom.grid * 2 > 2 * 1024)
-    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
+    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key slots hold");
   // two words per workgroup, in two halves that alternate by launch parity
   const size_t nkeys = static_cast<size_t>(c->geom.grid) * 4;
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
@@ -692,7 +692,7 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
   if (hipMalloc(&c->r_work, c->ld * sizeof(float)) != hipSuccess) return bail(MP_ENOMEM, "r");
   if (hipMalloc(&c->st, sizeof(mp::DevState)) != hipSuccess) return bail(MP_ENOMEM, "state");
   if (c->geom.grid > 1024)
-    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key hand-off holds");
+    return bail(MP_EUNSUPPORTED, "more correlation workgroups than the key slots hold");
   // pair keys, one per workgroup, in two halves alternating by launch parity
   const size_t nkeys = 4 * static_cast<size_t>(c->geom.grid);
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)

@@ -18,7 +18,8 @@ constexpr int kStopNonFinite = -1;
 constexpr int kStopInternal = -2;
 
 // Solver state of one decode, resident in device memory for the whole run.
-// Written by k_init and by the last workgroup of each iteration's launch.
+// Written by k_init and by one workgroup of each step launch (workgroup 0 in
+// the carried forms, the last to arrive in the OMP selection).
 struct alignas(64) DevState {
   double yy;            // ||y||^2
   double rr;            // ||r||^2 of the current residual
@@ -27,7 +28,7 @@ struct alignas(64) DevState {
   long long max_iters;  // cap T
   int done;             // 1 once the run has stopped
   int reason;           // MP_STOP_* or kStopNonFinite
-  unsigned arrive;      // workgroups of the current launch that have published a key
+  unsigned arrive;      // OMP selection: workgroups of the launch that have published a key
   int r_sel;            // reduced-precision decode: half of the residual buffer holding r
   int pad[4];
 };
