@@ -22,6 +22,8 @@
 // kernel boundary), so round r+1 covers at most the signals that stop in
 // round r, which its select skips.  No workgroup waits for another and no
 // atomics are used.
+#include <type_traits>
+
 #include "k_common.h"
 #include "k_lowp.h"
 #include "mp_internal.h"
@@ -178,6 +180,66 @@ constexpr int kBCorrWaves = kBCorrThreads / kWave;   // K split
 constexpr int kBCorrTileB = 64;                      // signals per workgroup
 constexpr int kBPre = 4;                             // K-steps in flight per wave
 
+// Each signal's 8 best atoms of a product tile (the epilogue of both product
+// kernels): `ct` holds the tile's TM x 64 correlations; thread (wave, lane)
+// sorts the keys of rows [wave * TM/4, (wave + 1) * TM/4) of signal column
+// `lane` with sorting networks, and the four sorted lists are merged pairwise
+// into the signal's 8 best atoms (descending), written to `partials`.
+template <int TM>
+__device__ void tile_top8(const float (*ct)[kBCorrTileB + 1],
+                          uint64_t (&lists)[2][kBTopK][kBCorrTileB], int64_t m0, int64_t m,
+                          int nact, int j0, int lane, int wave, uint64_t* __restrict__ partials,
+                          int mtiles) {
+  constexpr int RP = TM / 4;  // rows per thread: 16 or 8
+  static_assert(RP == 16 || RP == 8, "tile height");
+  uint64_t L[kBTopK];
+  {
+    uint64_t v[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+      const int rr = wave * RP + i;
+      const int64_t atom = m0 + rr;
+      v[i] = atom < m ? make_key(ct[rr][lane], static_cast<int>(atom)) : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) L[q] = v[q];
+    sort8_keys(L);
+    if constexpr (RP == 16) {
+      uint64_t h[kBTopK];
+#pragma unroll
+      for (int q = 0; q < kBTopK; ++q) h[q] = v[kBTopK + q];
+      sort8_keys(h);
+      merge8_keys(L, h);
+    }
+  }
+  // waves 2, 3 hand their lists to waves 0, 1; then wave 1 to wave 0
+  if (wave >= 2)
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) lists[wave - 2][q][lane] = L[q];
+  __syncthreads();
+  if (wave < 2) {
+    uint64_t o[kBTopK];
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) o[q] = lists[wave][q][lane];
+    merge8_keys(L, o);
+  }
+  __syncthreads();
+  if (wave == 1)
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) lists[1][q][lane] = L[q];
+  __syncthreads();
+  if (wave == 0 && j0 + lane < nact) {
+    uint64_t o[kBTopK];
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) o[q] = lists[1][q][lane];
+    merge8_keys(L, o);
+    uint64_t* out = partials + (static_cast<int64_t>(j0 + lane) * mtiles + blockIdx.x) * kBTopK;
+#pragma unroll
+    for (int q = 0; q < kBTopK; ++q) out[q] = L[q];
+  }
+}
+
+
 template <int TI>
 __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr(const uint16_t* __restrict__ psit,
                                                          int64_t ld, int64_t m,
@@ -296,54 +358,135 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
   }
   __syncthreads();
 
-  // each signal's 8 best atoms of the tile
-  constexpr int RP = TM / 4;  // rows per thread: 16 or 8
-  static_assert(RP == 16 || RP == 8, "tile height");
-  uint64_t L[kBTopK];
-  {
-    uint64_t v[RP];
+  tile_top8<TM>(ctile[1], lists, m0, m, nact, j0, lane, wave, partials, mtiles);
+}
+
+// ---------------------------------------------------------------------------
+// Product tile of 64 atoms x 64 signals with the residual operand staged in
+// LDS (the form used while many signals are active).  Wave w owns atom rows
+// 16w .. 16w + 15 over all of K (4 MFMA 16x16 blocks per K-step, no
+// reduction across waves); its dictionary operand comes straight from the
+// tiled BF16 copy (1 KB per K-step, two register sets of one chunk each).
+// The workgroup stages the 64 signals' residual rows chunk by chunk (kSChunk
+// K elements, full 128-byte lines: 16 threads per row) into one of two LDS
+// buffers while the MFMAs read the other; one barrier per chunk.  Used when
+// ld is a multiple of 2 kSChunk.  Rows are
+// padded by 16 bytes so that the 16 signal rows one operand read touches
+// fall on distinct banks.  The epilogue is k_bcorr's.
+constexpr int kSChunk = 128;                  // K elements per staged chunk (4 K-steps)
+constexpr int kSRow = kSChunk + 8;            // LDS row stride in BF16 elements
+constexpr int kSLoads = kBCorrTileB * kSChunk / 8 / kBCorrThreads;  // 16-byte loads per thread
+
+__global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr_s(
+    const uint16_t* __restrict__ psit, int64_t ld, int64_t m, const uint16_t* Rq, int64_t ldq,
+    const int* __restrict__ acts, int64_t cap, const BState* __restrict__ bs,
+    uint64_t* __restrict__ partials, int mtiles, int par) {
+  // Rq without __restrict__: its loads then stay where the memory clobber
+  // below puts them (restrict-qualified loads count as invariant and move)
+  constexpr int TM = 64;
+  const int nact = bs->n_active[par];
+  const int* act = acts + par * cap;
+  const int j0 = blockIdx.y * kBCorrTileB;
+  if (j0 >= nact) return;  // workgroup-uniform
+  const int t = threadIdx.x;
+  const int lane = t % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(t / kWave);  // wave-uniform
+  const int64_t m0 = static_cast<int64_t>(blockIdx.x) * TM;
+  const int koff = 8 * (lane / 16);
+
+  __shared__ uint16_t bst[2][kBCorrTileB * kSRow];
+  __shared__ float ctile[TM][kBCorrTileB + 1];
+  __shared__ uint64_t lists[2][kBTopK][kBCorrTileB];
+
+  // this wave's dictionary rows (rows past the last atom read the last one;
+  // the epilogue skips them)
+  int64_t row = m0 + 16 * wave + (lane % 16);
+  if (row > m - 1) row = m - 1;
+  const uint16_t* arow = psit + (row / 16) * 16 * ld + (row % 16) * 32 + koff;
+  // this thread's share of the staging: row sig[q], 16 bytes at K offset soff
+  const uint16_t* srow[kSLoads];
+  int sdst[kSLoads];
 #pragma unroll
-    for (int i = 0; i < RP; ++i) {
-      const int rr = wave * RP + i;
-      const int64_t atom = m0 + rr;
-      v[i] = atom < m ? make_key(ctile[1][rr][lane], static_cast<int>(atom)) : 0ull;
+  for (int q = 0; q < kSLoads; ++q) {
+    const int f = t + q * kBCorrThreads;
+    const int sg = f / (kSChunk / 8);
+    const int part = f % (kSChunk / 8);
+    int j = j0 + sg;
+    if (j > nact - 1) j = nact - 1;
+    srow[q] = Rq + static_cast<int64_t>(act[j]) * ldq + 8 * part;
+    sdst[q] = sg * kSRow + 8 * part;
+  }
+  const int nchunks = static_cast<int>(ld / kSChunk);
+
+  v4f acc[4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) acc[tj] = v4f{0.f, 0.f, 0.f, 0.f};
+  constexpr int KS = kSChunk / 32;  // K-steps per chunk
+  // two register sets of the dictionary operand, one chunk each
+  v8bf ra[2][KS];
+  auto load_a = [&](auto setc, int chunk) {
+    constexpr int set = decltype(setc)::value;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+      ra[set][kk] = *reinterpret_cast<const v8bf*>(
+          arow + static_cast<int64_t>(chunk * KS + kk) * 32 * 16);
+  };
+  v4u sreg[kSLoads];
+  auto load_b = [&](int chunk) {
+    const int64_t k0 = static_cast<int64_t>(chunk) * kSChunk;
+#pragma unroll
+    for (int q = 0; q < kSLoads; ++q) sreg[q] = *reinterpret_cast<const v4u*>(srow[q] + k0);
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kSLoads; ++q) *reinterpret_cast<v4u*>(&bst[buf][sdst[q]]) = sreg[q];
+  };
+  // Chunk c (buffer and register set b = c mod 2): first request chunk c+1
+  // (residual rows, then the dictionary operand into the other set), then
+  // the MFMAs of chunk c from LDS and registers filled one chunk earlier, so
+  // that no wait of chunk c covers a request of chunk c+1 made before it.
+  auto chunk = [&](auto bc, int c) {
+    constexpr int b = decltype(bc)::value;
+    // unconditional (the last chunk requests itself again, unused): loads
+    // under a branch would make the waits at the join cover them
+    const int cn = c + 1 < nchunks ? c + 1 : c;
+    load_b(cn);
+    load_a(std::integral_constant<int, 1 - b>{}, cn);
+    // keeps the requests here: without it the compiler moves the residual
+    // loads down to their LDS store, where they would be waited for at once
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      v8bf rb[4];
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+        rb[tj] = *reinterpret_cast<const v8bf*>(
+            &bst[b][(16 * tj + (lane % 16)) * kSRow + 32 * kk + koff]);
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+        acc[tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ra[b][kk], rb[tj], acc[tj], 0, 0, 0);
     }
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) L[q] = v[q];
-    sort8_keys(L);
-    if constexpr (RP == 16) {
-      uint64_t h[kBTopK];
-#pragma unroll
-      for (int q = 0; q < kBTopK; ++q) h[q] = v[kBTopK + q];
-      sort8_keys(h);
-      merge8_keys(L, h);
-    }
-  }
-  // waves 2, 3 hand their lists to waves 0, 1; then wave 1 to wave 0
-  if (wave >= 2)
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) lists[wave - 2][q][lane] = L[q];
+    if (c + 1 < nchunks) store_b(1 - b);
+    __syncthreads();
+  };
+
+  load_b(0);
+  load_a(std::integral_constant<int, 0>{}, 0);
+  store_b(0);
   __syncthreads();
-  if (wave < 2) {
-    uint64_t o[kBTopK];
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) o[q] = lists[wave][q][lane];
-    merge8_keys(L, o);
+  for (int c = 0; c < nchunks; c += 2) {  // nchunks is even (ld % 256 == 0)
+    chunk(std::integral_constant<int, 0>{}, c);
+    chunk(std::integral_constant<int, 1>{}, c + 1);
   }
+
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      ctile[16 * wave + 4 * (lane / 16) + i][16 * tj + (lane % 16)] = acc[tj][i];
   __syncthreads();
-  if (wave == 1)
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) lists[1][q][lane] = L[q];
-  __syncthreads();
-  if (wave == 0 && j0 + lane < nact) {
-    uint64_t o[kBTopK];
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) o[q] = lists[1][q][lane];
-    merge8_keys(L, o);
-    uint64_t* out = partials + (static_cast<int64_t>(j0 + lane) * mtiles + blockIdx.x) * kBTopK;
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) out[q] = L[q];
-  }
+  tile_top8<TM>(ctile, lists, m0, m, nact, j0, lane, wave, partials, mtiles);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,7 +680,10 @@ hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, i
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
   const dim3 grid(mtiles, btiles > 0 ? btiles : 1);
-  if (tile_m == 64)
+  if (tile_m == 64 && ld % (2 * kSChunk) == 0)
+    k_bcorr_s<<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
+                                                    mtiles, par);
+  else if (tile_m == 64)
     k_bcorr<4><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
                                                      mtiles, par);
   else

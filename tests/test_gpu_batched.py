@@ -120,8 +120,13 @@ def test_mixed_stops_and_caps():
         assert g["idx"][b, :k].tolist() == ora.idx[:k].tolist()
 
 
-@pytest.mark.parametrize("n,m,b", [(3, 5, 2), (64, 130, 70), (16384, 64, 3), (520, 300, 5)])
+@pytest.mark.parametrize("n,m,b", [(3, 5, 2), (64, 130, 70), (16384, 64, 3), (520, 300, 5),
+                                   (256, 1000, 130), (512, 4096, 100)])
 def test_batched_shapes(n, m, b):
+    """Ragged and extreme shapes; the last two keep more than 96 signals
+    active with column lengths a multiple of 256, so their early rounds run
+    the product with the residual operand staged in LDS (the first with a
+    ragged last atom tile)."""
     rng = np.random.default_rng(n + m + b)
     psi = mpgen.gaussian_unit_dictionary(rng, n, m)
     Y = np.zeros((n, b), np.float32, order="F")
