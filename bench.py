@@ -105,7 +105,8 @@ def step_bytes(n, m, storage):
 
 def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None, omp=False):
     """Warm up, then time `steps` whole decodes; the step kernel's launches are
-    timed with HIP events on the decode stream (every profile_every-th).
+    timed with HIP events on the decode stream, over windows of profile_every
+    consecutive launches (OMP: every profile_every-th selection launch).
     ``omp``: decode with Orthogonal Matching Pursuit (the selection pass is
     the timed kernel)."""
     import torch
@@ -377,7 +378,8 @@ def main():
                     help="batched leg: skip the FP32 comparison that decodes the same signals "
                          "one by one")
     ap.add_argument("--profile-every", type=int, default=16,
-                    help="time every k-th iteration's kernel launch with HIP events")
+                    help="time the step kernel with HIP events over windows of k consecutive "
+                         "launches (OMP: every k-th selection launch)")
     ap.add_argument("--max-iters", type=int, default=None,
                     help="cap each decode at this many iterations (short profiling runs)")
     args = ap.parse_args()

@@ -390,17 +390,22 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
 /*
  * mp_set_profiling / mp_kernel_time -- per-launch timing of the kernel that
  * makes one MP iteration (the pass over the whole dictionary, eq. 9, with the
- * selection and update of eqs. 10-12 at its tail) during the last mp_solve,
- * or of the matrix-product kernel (the correlations of all active signals)
- * during the last mp_solve_batched, or of the whole persistent launch of the
- * last mp_solve_ragged, measured with HIP events recorded around the launch
- * on the decode stream.
+ * step of eqs. 10-12 carried into it) during the last mp_solve, or of the
+ * matrix-product kernel (the correlations of all active signals) during the
+ * last mp_solve_batched, or of the whole persistent launch of the last
+ * mp_solve_ragged, measured with HIP events on the decode stream.
  *
- *   every     0: off.  k > 0: time every k-th iteration's launch (events
- *             around every launch add a little time between launches).
+ *   every     0: off.  k > 0: mp_solve in FP32, BF16, FP8, FP64 and the sign
+ *             form (one launch per iteration) times windows of k consecutive
+ *             launches (at most 64) with one event before each window and one
+ *             after it, so the timed launches run as untimed ones do and the
+ *             average includes the gaps between consecutive launches; OMP
+ *             times every k-th selection launch on its own; mp_solve_batched
+ *             every k-th round's product launch.
  *   avg_ms    host: mean duration of one timed launch in milliseconds
  *   launches  host: number of launches averaged (only launches that performed
- *             an iteration are counted; 0 when profiling is off)
+ *             an iteration are counted, a window only when all its launches
+ *             did; 0 when profiling is off)
  * Errors: MP_EINVAL (NULL ctx or outputs, every < 0), MP_EDEVICE.
  */
 mp_status mp_set_profiling(mp_ctx* ctx, int every);

@@ -158,14 +158,22 @@ mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
 }
 
 // The single-signal iteration driver: after init (state already copied to
-// c->h_st), enqueue chunks of iterations with `enqueue(e0, e1)`; the kernels
+// c->h_st), enqueue chunks of iterations with `enqueue(e0, e1)` (record e0,
+// when not null, before the iteration's launch and e1 after it); the kernels
 // stop doing work once the device state says the run is over.  Two chunks
 // stay in flight: after enqueuing chunk k the host waits for the state copy
-// that follows chunk k-1.  With profiling on, the launches of every
-// prof_every-th iteration are timed (only those that performed an iteration
-// are counted).
+// that follows chunk k-1.
+//
+// Timing, with profiling on.  `windowed` (one kernel launch per iteration):
+// each chunk is cut from its start into windows of prof_every consecutive
+// launches (at most a chunk), timed by one event before the window's first
+// launch and one after its last, so the launches inside run as untimed ones
+// do and the average per launch includes the gaps between them.  Otherwise
+// (OMP: several kernels per iteration, `enqueue` brackets the selection
+// launch) every prof_every-th iteration is timed on its own.  Only launches
+// that performed an iteration are counted: a window, all its launches.
 template <typename Enqueue>
-mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, Enqueue enqueue) {
+mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, Enqueue enqueue) {
   c->prof_ms = 0.0;
   c->prof_launches = 0;
   long long issued = 0;
@@ -193,14 +201,15 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, Enqueue enqueue)
     const bool late = c->storage == MP_SIGN1 ||
                       (sl.reason != MP_STOP_CONVERGED && sl.reason != MP_STOP_MAX_ITERS);
     const long long stop_launch = sl.done ? sl.t + (late ? 1 : 0) : LLONG_MAX;
-    for (int j = 0; j < slot_len[k]; ++j) {
-      if (slot_base[k] + j >= stop_launch) break;
-      if ((slot_base[k] + j) % c->prof_every != 0) continue;
+    const int w = windowed ? std::min(c->prof_every, kMaxChunk) : 1;
+    for (int j = 0; j + w <= slot_len[k]; j += w) {
+      if (slot_base[k] + j + w > stop_launch) break;
+      if (!windowed && (slot_base[k] + j) % c->prof_every != 0) continue;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, c->ev[(k * kMaxChunk + j) * 2],
                               c->ev[(k * kMaxChunk + j) * 2 + 1]) == hipSuccess) {
         c->prof_ms += ms;
-        c->prof_launches += 1;
+        c->prof_launches += w;
       }
     }
   };
@@ -211,11 +220,14 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, Enqueue enqueue)
     while (inflight < 2 && issued < T && status == MP_OK) {
       const int k = next;
       const int len = static_cast<int>(std::min<long long>(chunk, T - issued));
+      const int w = windowed ? std::min(c->prof_every, kMaxChunk) : 1;
       for (int j = 0; j < len; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->profiling && (issued + j) % c->prof_every == 0) {
-          e0 = c->ev[(k * kMaxChunk + j) * 2];
-          e1 = c->ev[(k * kMaxChunk + j) * 2 + 1];
+        const int j0 = j - j % w;  // first launch of j's window
+        if (c->profiling && j0 + w <= len &&
+            (windowed || (issued + j) % c->prof_every == 0)) {
+          if (j == j0) e0 = c->ev[(k * kMaxChunk + j0) * 2];
+          if (j == j0 + w - 1) e1 = c->ev[(k * kMaxChunk + j0) * 2 + 1];
         }
         hipError_t e = enqueue(e0, e1);
         if (e != hipSuccess) {
@@ -470,7 +482,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     long long k = 0;
     const long long T = opts->max_iters;
     const double thr = c->h_st->thr;
-    const mp_status st = run_iterations(c, T > 0 ? T + 2 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    const mp_status st = run_iterations(c, T > 0 ? T + 2 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
       hipError_t e;
       if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
       e = mp::launch_mp_step_sign(c->psis, c->sign_ws, c->n, c->m, c->ld, c->sign_c64,
@@ -488,7 +500,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     long long k = 0;
     const long long T = opts->max_iters;
     const double thr = c->h_st->thr;
-    const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+    const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
       hipError_t e;
       if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
       if (c->storage == MP_F32)
@@ -566,7 +578,7 @@ mp_status mp_solve_omp(mp_ctx* ctx, const float* y, float* x, float* r, const mp
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   long long it = 0;  // iterations enqueued so far: a bound on the atoms selected
-  const mp_status st = run_iterations(c, T, s, [&](hipEvent_t e0, hipEvent_t e1) {
+  const mp_status st = run_iterations(c, T, s, false, [&](hipEvent_t e0, hipEvent_t e1) {
     const hipError_t e = mp::launch_omp_iteration(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom,
                                                   c->partials, c->st, b, it, tr, s, e0, e1);
     ++it;
@@ -736,7 +748,7 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
   long long k = 0;
   const long long T = opts->max_iters;
   const double thr = c->h_st->thr;
-  const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, [&](hipEvent_t e0, hipEvent_t e1) {
+  const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
     e = mp::launch_mp_step_f64(c->psi64, c->ld, c->n, c->m, c->r64_work, c->geom, c->partials,

@@ -451,7 +451,9 @@ class Decoder:
         return codes.t(), scales
 
     def set_profiling(self, every: int = 1):
-        """Time every ``every``-th iteration's launch (0 = off)."""
+        """Time the step kernel's launches with HIP events (0 = off): windows of
+        ``every`` consecutive launches (at most 64), OMP every ``every``-th
+        selection launch on its own."""
         mp_set_profiling(self._ctx, int(every))
 
     def kernel_time(self):

@@ -223,10 +223,12 @@ def test_profiling_counts_real_launches():
         out = dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
         ms, n = dec.kernel_time()
         assert n == out["iters"] and ms > 0
+        # windows of 4 consecutive launches: only the window that holds the
+        # stop launch (no pass) is left out
         dec.set_profiling(4)
         out = dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
         ms, n = dec.kernel_time()
-        assert n == (out["iters"] + 3) // 4 and ms > 0
+        assert n % 4 == 0 and out["iters"] - 3 <= n <= out["iters"] and ms > 0
         dec.set_profiling(0)
         dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
         assert dec.kernel_time()[1] == 0
