@@ -89,10 +89,12 @@ def test_parity_8192x32768_sampled():
 
 
 @pytest.mark.parametrize("n,m", [(250, 1000), (1, 1), (3, 5), (64, 4), (100, 7), (520, 300),
-                                 (16384, 64), (4096, 2049), (16384, 16384)])
+                                 (16384, 64), (4096, 2049), (4160, 3001), (4100, 700),
+                                 (16384, 16384)])
 def test_ragged_and_extreme_shapes(n, m):
     """Column lengths that are not multiples of the tile, tiny and maximum N
-    (at M = 16384 with the balanced column shares active)."""
+    (at M = 16384 with the balanced column shares active); N = 4160 and 4100
+    (padded to 4160) end each column in a ragged block after two full ones."""
     rng = np.random.default_rng(n * 7919 + m)
     psi = mpgen.gaussian_unit_dictionary(rng, n, m)
     k = max(1, min(m // 8, n // 4, 6))
