@@ -253,7 +253,9 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
  *   signs    device: packed bits, column m in words [m ldw, m ldw + ldw);
  *            bit q of word w is b_nm for row n = 32 w + q (1: -1/sqrt(N),
  *            0: +1/sqrt(N)); bits of rows n >= N are ignored
- *   n, m     1 <= N <= 16384, 1 <= M < 2^31
+ *   n, m     1 <= N <= 16384; 1 <= M <= 131072 for N <= 8192, M <= 65536
+ *            above (MP_EUNSUPPORTED beyond: a workgroup scores at most 128,
+ *            or 64, columns and a launch holds at most 1024 workgroups)
  *   ldw      words per column, ldw >= ceil(N / 32)
  *   flags    0 or MP_SKIP_NORM_CHECK (no effect: the columns have unit norm
  *            by construction)
@@ -263,7 +265,7 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
  * the call returns.  mp_get_storage returns the bits in the packed form above
  * with ldw = ceil(N / 32).  Errors: MP_EINVAL (NULL, n or m out of range, ldw
  * too small, unknown flags), MP_ENOMEM, MP_EDEVICE, MP_EUNSUPPORTED (not a
- * gfx950 device).
+ * gfx950 device, or M above the limit for N).
  */
 mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_t m, int64_t ldw,
                           uint32_t flags, void* stream);

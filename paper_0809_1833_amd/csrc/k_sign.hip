@@ -318,6 +318,20 @@ __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
 
 int sign_chunks_per_lane(int64_t n) { return n <= 8192 ? 1 : 2; }
 
+// The FP32 form's column shares, capped at the columns one workgroup scores
+// (kSignWaves x kSignBatch: 128 columns with one chunk per lane, 64 with
+// two), with more workgroups when M needs them.
+CorrGeom sign_geometry(int64_t n, int64_t m, int num_cus) {
+  CorrGeom g = corr_f32_geometry(m, num_cus);
+  const int cap = sign_chunks_per_lane(n) == 1 ? kSignWaves * kSignBatch<1>
+                                               : kSignWaves * kSignBatch<2>;
+  if (g.cols_per_wg > cap) {
+    g.cols_per_wg = cap;
+    g.grid = static_cast<int>((m + cap - 1) / cap);
+  }
+  return g;
+}
+
 hipError_t launch_copy_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int64_t ws,
                              uint32_t* out, hipStream_t s) {
   const int64_t total = m * ws;
@@ -350,6 +364,11 @@ hipError_t launch_mp_step_sign(const uint32_t* bits, int64_t ws, int64_t n, int6
   const double inv_n = 1.0 / static_cast<double>(n);
   const double inv_sqrt_n = 1.0 / sqrt(static_cast<double>(n));
   const int rows_per_wg = static_cast<int>((ld + g.grid - 1) / g.grid);
+  // a workgroup scores kSignWaves x kSignBatch columns: a larger share
+  // would leave columns unscored
+  const int cap = sign_chunks_per_lane(n) == 1 ? kSignWaves * kSignBatch<1>
+                                               : kSignWaves * kSignBatch<2>;
+  if (g.cols_per_wg > cap || g.grid > kSignThreads) return hipErrorInvalidValue;
   if (sign_chunks_per_lane(n) == 1)
     k_mp_step_sign<1><<<dim3(g.grid), dim3(kSignThreads), 0, s>>>(
         bits, ws, static_cast<int>(n), m, ld, c64, r64, r32, rrp, inv_n, inv_sqrt_n,

@@ -689,7 +689,7 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
   c->ld = round_up(n, kLdAlign);
   c->storage = MP_SIGN1;
   c->sign_ws = round_up((n + 31) / 32, 4);
-  c->geom = mp::corr_f32_geometry(m, c->num_cus);
+  c->geom = mp::sign_geometry(n, m, c->num_cus);
 
   auto bail = [&](mp_status st, const std::string& msg) {
     free_ctx(c);

@@ -104,6 +104,7 @@ hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t 
 // ---- sign-bit Bernoulli dictionary (k_sign.hip) ------------------------------
 // 16-byte chunks of a column each lane reads (1 for n <= 8192, 2 above).
 int sign_chunks_per_lane(int64_t n);
+CorrGeom sign_geometry(int64_t n, int64_t m, int num_cus);
 // Packed input (ldw words per column) -> ws words per column, rows >= n cleared.
 hipError_t launch_copy_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int64_t ws,
                              uint32_t* out, hipStream_t s);

@@ -114,6 +114,31 @@ def test_parity_ragged_shapes(n, m):
     assert rep.prefix >= min(rep.iters_ora, 5), rep
 
 
+@pytest.mark.parametrize("n,m,planted", [(8192, 33000, [130, 855, 28940]),
+                                         (8200, 16500, [70, 8075, 16479])])
+def test_parity_many_columns(n, m, planted):
+    """M above 256 workgroups' worth of columns: a workgroup scores at most
+    128 columns (64 for N > 8192), so the decode takes more workgroups.  The
+    largest atoms sit where a share of 144 (80) columns per workgroup would
+    have left columns unscored."""
+    rng = np.random.default_rng(n + m)
+    s = mpgen.bernoulli_signs(rng, n, m)
+    sup = np.sort(np.array(planted + [5, m // 2, m - 1], dtype=np.int64))
+    x = np.zeros(m, np.float32)
+    x[sup] = rng.standard_normal(sup.size).astype(np.float32) * 0.1
+    x[planted] = np.array([4.0, -3.0, 2.5], np.float32)
+    y = mpgen.encode_signs(s, x, sup)
+    bits = mpgen.pack_signs(s)
+    del s
+    print(f"[sign many columns {n}x{m}]", flush=True)
+    psi = osigns.unpack(bits, n)
+    with _decoder(bits, n) as dec:
+        out = _gpu_solver(dec, y)(1e-6, 40, 8)
+        assert list(out["idx"][:3]) == planted, out["idx"][:8]
+        rep = run_parity(psi, y, 1e-6, 40, _gpu_solver(dec, y))
+    assert rep.prefix >= min(rep.iters_ora, 5), rep
+
+
 @pytest.mark.parametrize("n", [64, 256, 4096])
 def test_hadamard_exact_with_ties(n):
     """Sylvester columns (orthonormal, 1/sqrt(N) a power of two) and dyadic
