@@ -103,7 +103,8 @@ def step_bytes(n, m, storage):
     return b
 
 
-def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None, omp=False):
+def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None, omp=False,
+                 **solve_kw):
     """Warm up, then time `steps` whole decodes; the step kernel's launches are
     timed with HIP events on the decode stream, over windows of profile_every
     consecutive launches (OMP: every profile_every-th selection launch).
@@ -111,14 +112,16 @@ def time_decodes(dec, y, p, steps, warmup, profile_every, x, r, stream=None, omp
     the timed kernel)."""
     import torch
     for _ in range(warmup):
-        dec.solve(y, p.eps, p.max_iters, x=x, r=r, omp=omp)
+        dec.solve(y, p.eps, p.max_iters, x=x, r=r, omp=omp, **solve_kw)
     dec.set_profiling(profile_every)
     torch.cuda.synchronize()
     iters, kt_ms, kt_n, stops = 0, 0.0, 0, set()
     t0 = time.perf_counter()
     for _ in range(steps):
-        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream, omp=omp)
+        out = dec.solve(y, p.eps, p.max_iters, x=x, r=r, stream=stream, omp=omp, **solve_kw)
         iters += out["iters"]
+        if out.get("persistent"):
+            stops.add("persistent")
         ms, cnt = dec.kernel_time()
         kt_ms += ms * cnt
         kt_n += cnt
@@ -171,13 +174,21 @@ def sign_step_bytes(n, m):
     return n * m / 8.0 + 16.0 * m + 20.0 * n
 
 
+# LDS bandwidth of the chip: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
+
+
 def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 16,
                max_iters=None):
     """Decode on the Bernoulli dictionary of eq. 13 held as sign bits
     (mp_create_signs): N=8192, M=32768 (32 MiB of bits), K=512, eps=1e-5,
     T=10240.  The correlations are carried by exact Gram updates (XOR and
-    bit count), so a launch streams the bits once: achieved = algorithmic
-    bytes per launch over the step kernel's mean launch time, against HBM."""
+    bit count).  Where the decode runs as one persistent launch with the bits
+    held in LDS, its roofline is the time per step (bound by the exchange of
+    the workgroups' records) with the LDS rate of the bits beside it; the
+    same decode with one launch per step is timed too, each launch streaming
+    the bits once from HBM (algorithmic bytes per launch over its mean launch
+    time)."""
     import torch
 
     import mpgen
@@ -195,19 +206,39 @@ def bench_sign(seed: int, steps: int = 3, warmup: int = 1, profile_every: int = 
         r = torch.empty(n, dtype=torch.float32, device="cuda")
         iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
                                                       x, r)
+        # the same decode with one launch per step, for comparison
+        s_it, s_dt, s_ms, s_n, s_stops = time_decodes(dec, y, p, steps, warmup, profile_every,
+                                                      x, r, step_launches=True)
+    persistent = "persistent" in stops
+    stops.discard("persistent")
+    bits = n * m / 8.0
     b = sign_step_bytes(n, m)
-    achieved = b / (avg_ms * 1e-3) / 1e9 if kt_n else None
-    return {"workload": f"N={n}, M={m}, Bernoulli dictionary (eq. 13) as sign bits "
-                        "(32 MiB), K=512, eps=1e-5, T=10240, single signal",
-            "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
-            "iters_per_decode": iters // max(steps, 1), "stop": sorted(stops),
-            "roofline": {"bound": "hbm", "kernel": "k_mp_step_sign",
-                         "achieved": round(achieved, 2) if achieved else None,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                         "traffic": traffic_from_counters(n, m, "sign"),
-                         "bytes_per_launch": b,
-                         "avg_launch_us": round(avg_ms * 1e3, 3), "launches": kt_n}}
+    s_ach = b / (s_ms * 1e-3) / 1e9 if s_n else None
+    lds = bits / (avg_ms * 1e-3) / 1e9 if kt_n else None
+    step = {"bound": "hbm", "kernel": "k_mp_step_sign",
+            "iters_per_s": round(s_it / s_dt, 3),
+            "achieved": round(s_ach, 2) if s_ach else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(s_ach / HBM_PEAK_GBS, 4) if s_ach else None,
+            "traffic": traffic_from_counters(n, m, "sign"), "bytes_per_launch": b,
+            "avg_launch_us": round(s_ms * 1e3, 3), "launches": s_n}
+    out = {"workload": f"N={n}, M={m}, Bernoulli dictionary (eq. 13) as sign bits "
+                       "(32 MiB), K=512, eps=1e-5, T=10240, single signal",
+           "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
+           "iters_per_decode": iters // max(steps, 1), "stop": sorted(stops),
+           "persistent": persistent}
+    if persistent:
+        # the bits stay in LDS for the whole decode: a step reads them from
+        # LDS, and waits for every workgroup's record of the step before
+        out["roofline"] = {"bound": "exchange", "kernel": "k_sign_persist",
+                           "avg_step_us": round(avg_ms * 1e3, 3), "steps": kt_n,
+                           "lds": {"achieved": round(lds, 2) if lds else None,
+                                   "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(lds / LDS_PEAK_GBS, 4) if lds else None,
+                                   "bytes_per_step": bits}}
+        out["step_launches"] = step
+    else:
+        out["roofline"] = step
+    return out
 
 
 def bench_phase(seed: int):

@@ -87,15 +87,21 @@ typedef struct mp_opts {
     int32_t rescore_k;    /* reduced-precision storage: how many best candidates of
                              each pass are re-scored against the FP32 columns (1..8;
                              0 means 8).  Ignored for MP_F32 storage. */
-    uint32_t flags;       /* reserved, must be 0 */
+    uint32_t flags;       /* 0 or MP_SOLVE_STEP_LAUNCHES (mp_solve, mp_solve_f64 and
+                             mp_solve_omp; 0 for the others) */
 } mp_opts;
+
+/* mp_opts.flags: decode the one-bit form (MP_SIGN1) with one kernel launch
+   per step even where the whole decode fits one persistent launch (the same
+   results bit for bit; no effect on the other forms). */
+#define MP_SOLVE_STEP_LAUNCHES 0x1u
 
 typedef struct mp_result {
     int64_t iters;        /* updates performed */
     double yy;            /* ||y||^2, FP64 */
     double rr;            /* ||r||^2 at exit, FP64 (from the FP32 residual) */
     int32_t stop_reason;  /* MP_STOP_* */
-    int32_t reserved;
+    int32_t persistent;   /* 1: the decode ran as one persistent launch (one-bit form) */
 } mp_result;
 
 /* Optional per-step record, all arrays device memory of `cap` entries.
@@ -246,8 +252,15 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
  * to eq. 11's r).  The correlations and r are kept in FP64 (c at the start is
  * Psi^T y in FP64), so the selections follow the exact iteration closely;
  * x~ accumulates fp32(c*) and r is returned rounded to FP32.  A pass reads
- * N/8 bytes per column instead of 4N.  The context has storage MP_SIGN1;
- * mp_solve_batched and mp_solve_omp return MP_EINVAL for it.
+ * N/8 bytes per column instead of 4N.  Where the device can keep one
+ * workgroup per compute unit resident with its share of the bits in LDS
+ * (the share at most 150 KB, e.g. N = 8192 with M up to 32768 on 256 CUs),
+ * mp_solve runs the whole decode as one cooperative launch that keeps the
+ * bits on chip and exchanges each step's candidates between workgroups
+ * through device memory; otherwise, or with MP_SOLVE_STEP_LAUNCHES, one
+ * launch per step.  Both give the same results bit for bit.  The context has
+ * storage MP_SIGN1; mp_solve_batched and mp_solve_omp return MP_EINVAL for
+ * it.
  *
  *   out      host: receives the new context (set to NULL on failure)
  *   signs    device: packed bits, column m in words [m ldw, m ldw + ldw);
@@ -401,7 +414,8 @@ mp_status mp_get_storage(const mp_ctx* ctx, void* codes, float* scales, void* st
  *             form (one launch per iteration) times windows of k consecutive
  *             launches (at most 64) with one event before each window and one
  *             after it, so the timed launches run as untimed ones do and the
- *             average includes the gaps between consecutive launches; OMP
+ *             average includes the gaps between consecutive launches (the
+ *             persistent one-bit decode: its launch, over its t + 2 steps); OMP
  *             times every k-th selection launch on its own; mp_solve_batched
  *             every k-th round's product launch.
  *   avg_ms    host: mean duration of one timed launch in milliseconds

@@ -316,6 +316,262 @@ __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form: the whole decode in one cooperative launch, one workgroup
+// per compute unit.  Each workgroup copies its columns' bits into LDS once
+// (128 KB for 128 columns of N = 8192: the 32 MiB dictionary stays on chip
+// across the 256 CUs for the whole decode), keeps its columns' c in
+// registers and its rows of r (at most 64 kSignPersistRows) in registers of
+// wave 0, so a step reads no dictionary bytes from memory.
+//
+// Step j does what launch j of k_mp_step_sign does, with the same arithmetic
+// in the same order (bit-identical results).  In place of the kernel
+// boundary between steps, each workgroup publishes its best key and partial
+// ||r||^2 as kSignSlotWords words of the step's half of `slots`, each word
+// carrying the step's tag beside 32 bits of the record, and reads every
+// workgroup's words of the step before it goes on.
+//
+// The words are written and read with relaxed device-scope atomics (single
+// 64-bit accesses, coherent across the XCDs); a reader takes a record once
+// all its words carry the awaited tag, so no ordering between the words and
+// no cache write-back or invalidation is needed.  Steps alternate between
+// the two halves: a workgroup overwrites its words of step j - 2 only after
+// reading every record of step j - 1, each of which its owner published
+// after reading every record of step j - 2, so every reader of the old
+// contents is done with them.  The epoch, new for every decode, keeps a
+// word left by an earlier decode from matching.
+//
+// Every wait ends: the launch is cooperative (all workgroups resident, or the
+// launch fails and the caller steps with k_mp_step_sign); every workgroup
+// runs the same steps and stops at the same one (the decision is taken from
+// the same gathered values); a poll that exceeds `spin_limit` tries marks the
+// run failed (kStopInternal) and its workgroup leaves, after which every
+// other workgroup's next poll times out too.
+constexpr int kSignPersistRows = 4;            // rows of r per lane of wave 0
+constexpr int kSignPersistLds = 150 * 1024;    // dynamic LDS for the bits, at most
+
+template <int CPL>
+__global__ __launch_bounds__(kSignThreads) void k_sign_persist(
+    const uint32_t* __restrict__ bits, int64_t ws, int n, int64_t m, int64_t ld,
+    const double* __restrict__ c64, double* __restrict__ r64, float* __restrict__ r32,
+    double inv_n, double inv_sqrt_n, int cols_per_wg, int rows_per_wg,
+    unsigned long long* slots, unsigned epoch, long long spin_limit, long long max_iters, double thr,
+    float* __restrict__ x, DevState* __restrict__ st, mp_trace tr) {
+  extern __shared__ v4u s_bits[];  // this workgroup's columns, nch chunks each
+  __shared__ Key2 kred[kSignWaves];
+  __shared__ double dred[kSignWaves];
+  __shared__ v4u s_win[kWave * CPL];  // the winning column's chunks
+  __shared__ int s_fail;
+  constexpr int B = kSignBatch<CPL>;
+  constexpr int RPL = kSignPersistRows;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const int grid = static_cast<int>(gridDim.x);
+  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
+  const int64_t col1 = col0 + cols_per_wg < m ? col0 + cols_per_wg : m;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
+  const int64_t row1 = row0 + rows_per_wg < ld ? row0 + rows_per_wg : ld;
+  const int nch = static_cast<int>(ws / 4);
+  const unsigned ep = (epoch % kSignEpochMod) << 20;  // the tag's epoch field
+
+  // the columns' bits (contiguous: columns col0 .. col1-1) into LDS
+  {
+    const v4u* src = reinterpret_cast<const v4u*>(bits + col0 * ws);
+    const int total = static_cast<int>(col1 - col0) * nch;
+    for (int i = static_cast<int>(threadIdx.x); i < total; i += kSignThreads) s_bits[i] = src[i];
+  }
+  double cm[B];
+  int colu[B];  // column index, clamped into the share as in k_mp_step_sign
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int64_t col = col0 + wave + u * kSignWaves;
+    colu[u] = static_cast<int>(col < col1 ? col : col1 - 1);
+    cm[u] = c64[colu[u]];
+  }
+  double rq[RPL];  // wave 0: rows row0 + lane + 64 q
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t i = row0 + lane + kWave * q;
+    rq[q] = (wave == 0 && i < row1) ? r64[i] : 0.0;
+  }
+  if (threadIdx.x == 0) s_fail = 0;
+  __syncthreads();
+
+  int idx = -1;
+  double cs = 0.0;
+  int x_pending = -1;  // workgroup 0: x~_idx += c* of the step, applied after publishing
+  float x_add = 0.0f;
+  for (long long j = 0;; ++j) {
+    if (j > 0) {
+      // every workgroup's key and partial norm of step j - 1
+      Key2 kp{0, 0};
+      double rrq = 0.0;
+      if (static_cast<int>(threadIdx.x) < grid) {
+        const unsigned want = ep | (static_cast<unsigned>(j) & 0xFFFFFu);  // step j - 1
+        unsigned long long* w0 = slots + ((j - 1) & 1) * grid + threadIdx.x;
+        unsigned long long w[kSignSlotWords];
+        long long spins = 0;
+        // poll the record's last word (stored last) alone, then read the
+        // others: every workgroup polls every record, so one word per try
+        // keeps the polling traffic down
+        constexpr int L = kSignSlotWords - 1;
+        for (;;) {
+          w[L] = __hip_atomic_load(w0 + L * 2 * grid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (static_cast<unsigned>(w[L] >> 32) == want) {
+            bool all = true;
+#pragma unroll
+            for (int q = 0; q < L; ++q) {
+              w[q] = __hip_atomic_load(w0 + q * 2 * grid, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+              all = all && static_cast<unsigned>(w[q] >> 32) == want;
+            }
+            if (all) break;
+          }
+          if (++spins > spin_limit) {
+            s_fail = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        kp.hi = (w[0] << 32) | (w[1] & 0xFFFFFFFFull);
+        kp.lo = w[2] & 0xFFFFFFFFull;
+        rrq = __builtin_bit_cast(double, (w[3] << 32) | (w[4] & 0xFFFFFFFFull));
+      }
+      __syncthreads();
+      if (s_fail) {
+        if (threadIdx.x == 0) {
+          __hip_atomic_store(&st->reason, kStopInternal, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+      }
+      // the stop test for the j - 1 steps taken, then step j's atom
+      const double rr = block_sum<kSignThreads>(rrq, dred);
+      const long long t = j - 1;
+      const Key2 win = block_max_key2<kSignThreads>(kp, kred);
+      idx = key2_index(win);
+      cs = key2_value(win);
+      int stop = -1;
+      if (t > 0 && !(rr > thr)) stop = MP_STOP_CONVERGED;
+      else if (t >= max_iters) stop = MP_STOP_MAX_ITERS;
+      else if (idx < 0 || idx >= m) stop = kStopInternal;
+      else if (cs == 0.0) stop = MP_STOP_STALLED;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (t > 0) {
+          if (t - 1 < tr.cap && tr.rr) tr.rr[t - 1] = rr;
+          st->rr = rr;
+        }
+        st->t = t;
+        if (stop != -1) {
+          st->reason = stop;
+          st->done = 1;
+        } else {
+          x_pending = idx;
+          x_add = static_cast<float>(cs);
+          if (t < tr.cap) {
+            if (tr.idx) tr.idx[t] = idx;
+            if (tr.coef) tr.coef[t] = static_cast<float>(cs);
+          }
+        }
+      }
+      if (stop != -1) break;
+
+      // the winning column's chunks, once per workgroup (chunks past the
+      // column zero)
+      if (static_cast<int>(threadIdx.x) < kWave * CPL) {
+        const int ch = static_cast<int>(threadIdx.x);
+        const v4u* pw = reinterpret_cast<const v4u*>(bits + static_cast<int64_t>(idx) * ws);
+        const v4u w = pw[ch < nch ? ch : nch - 1];
+        s_win[ch] = ch < nch ? w : v4u{0u, 0u, 0u, 0u};
+      }
+      __syncthreads();
+      v4u wv[CPL];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) wv[cc] = s_win[lane + kWave * cc];
+
+      // c_m -= c* (N - 2 p_m) / N, p_m = popcount(b_idx XOR b_m)
+      const double a = cs * inv_n;
+#pragma unroll
+      for (int u = 0; u < B; u += 2) {
+        uint32_t pa = 0, pb = 0;
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          const int ch = lane + kWave * cc;
+          const v4u za{0u, 0u, 0u, 0u};
+          const v4u ba = ch < nch ? s_bits[(colu[u] - col0) * nch + ch] : za;
+          const v4u bb = ch < nch ? s_bits[(colu[u + 1] - col0) * nch + ch] : za;
+          pa += disagree(ba, wv[cc]);
+          pb += disagree(bb, wv[cc]);
+        }
+        const uint32_t sum = wave_sum_u32(pa | (pb << 16));
+        cm[u] = __builtin_fma(-a, static_cast<double>(n - 2 * static_cast<int>(sum & 0xFFFFu)),
+                              cm[u]);
+        cm[u + 1] = __builtin_fma(
+            -a, static_cast<double>(n - 2 * static_cast<int>(sum >> 16)), cm[u + 1]);
+      }
+    }
+
+    // wave 0: this workgroup's rows of r (r_j = r_{j-1} -/+ c* / sqrt(N) in
+    // FP64, rows with a set bit get +) and their partial ||r_j||^2
+    double part = 0.0;
+    if (wave == 0) {
+      const double step = cs * inv_sqrt_n;
+      const uint32_t* win_words = reinterpret_cast<const uint32_t*>(s_win);
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int64_t i = row0 + lane + kWave * q;
+        if (i < row1) {
+          double v = rq[q];
+          if (j > 0 && i < n) {
+            const uint32_t w = win_words[i >> 5];
+            v = ((w >> (i & 31)) & 1u) ? v + step : v - step;
+            rq[q] = v;
+          }
+          s += v * v;
+        }
+      }
+      part = wave_sum(s);
+    }
+
+    // this workgroup's best key; publish step j
+    Key2 best{0, 0};
+#pragma unroll
+    for (int u = 0; u < B; ++u) best = key2_max(best, make_key2(cm[u], colu[u]));
+    best = block_max_key2<kSignThreads>(best, kred);
+    if (threadIdx.x == 0) {
+      const unsigned long long tag =
+          static_cast<unsigned long long>(ep | (static_cast<unsigned>(j + 1) & 0xFFFFFu)) << 32;
+      const unsigned long long pr = __builtin_bit_cast(unsigned long long, part);
+      const unsigned long long rec[kSignSlotWords] = {best.hi >> 32, best.hi & 0xFFFFFFFFull,
+                                                      best.lo & 0xFFFFFFFFull, pr >> 32,
+                                                      pr & 0xFFFFFFFFull};
+      unsigned long long* w0 = slots + (j & 1) * grid + blockIdx.x;
+#pragma unroll
+      for (int q = 0; q < kSignSlotWords; ++q)
+        __hip_atomic_store(w0 + q * 2 * grid, tag | rec[q], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      if (x_pending >= 0) {
+        x[x_pending] += x_add;
+        x_pending = -1;
+      }
+    }
+  }
+
+  // r after the last step taken, rows below N
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t i = row0 + lane + kWave * q;
+      if (i < row1 && i < n) {
+        r64[i] = rq[q];
+        r32[i] = static_cast<float>(rq[q]);
+      }
+    }
+  }
+}
+
 int sign_chunks_per_lane(int64_t n) { return n <= 8192 ? 1 : 2; }
 
 // The FP32 form's column shares, capped at the columns one workgroup scores
@@ -355,6 +611,67 @@ hipError_t launch_sign_c0(const uint32_t* bits, int64_t ws, int64_t n, int64_t m
   k_sign_c0<<<dim3(static_cast<unsigned>(blocks)), dim3(kC0Threads), lds, s>>>(
       bits, ws, static_cast<int>(n), m, y, 1.0 / sqrt(static_cast<double>(n)), ld, c64, r64);
   return hipGetLastError();
+}
+
+bool sign_persist_fits(int64_t n, int64_t m, int64_t ld, int64_t ws, const CorrGeom& g,
+                       int num_cus) {
+  (void)m;
+  const int64_t rows = (ld + g.grid - 1) / g.grid;
+  const int64_t lds = static_cast<int64_t>(g.cols_per_wg) * ws * 4;
+  return g.grid <= num_cus && g.grid <= kSignThreads && rows <= kWave * kSignPersistRows &&
+         lds <= kSignPersistLds && n >= 1;
+}
+
+// The persistent kernel's LDS limit, set once per variant (the bits of a
+// share need more than the default 64 KB).
+static hipError_t sign_persist_attr(int which, const void* fn) {
+  static bool attr_set[2] = {false, false};
+  if (attr_set[which]) return hipSuccess;
+  const hipError_t e =
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kSignPersistLds);
+  if (e == hipSuccess) attr_set[which] = true;
+  return e;
+}
+
+static const void* sign_persist_fn(int64_t n) {
+  return sign_chunks_per_lane(n) == 1 ? reinterpret_cast<const void*>(k_sign_persist<1>)
+                                      : reinterpret_cast<const void*>(k_sign_persist<2>);
+}
+
+bool sign_persist_resident(int64_t n, int64_t ws, const CorrGeom& g, int num_cus) {
+  const void* fn = sign_persist_fn(n);
+  if (sign_persist_attr(sign_chunks_per_lane(n) == 1 ? 0 : 1, fn) != hipSuccess) return false;
+  int per_cu = 0;
+  const size_t lds = static_cast<size_t>(g.cols_per_wg) * static_cast<size_t>(ws) * 4;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSignThreads, lds) != hipSuccess)
+    return false;
+  return static_cast<int64_t>(per_cu) * num_cus >= g.grid;
+}
+
+hipError_t launch_sign_persist(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, int64_t ld,
+                               const double* c64, double* r64, float* r32, const CorrGeom& g,
+                               unsigned long long* slots, unsigned epoch, long long max_iters,
+                               double thr, float* x, DevState* st, mp_trace tr, hipStream_t s) {
+  const double inv_n = 1.0 / static_cast<double>(n);
+  const double inv_sqrt_n = 1.0 / sqrt(static_cast<double>(n));
+  int rows_per_wg = static_cast<int>((ld + g.grid - 1) / g.grid);
+  int cols_per_wg = g.cols_per_wg;
+  int nn = static_cast<int>(n);
+  long long spin_limit = 1ll << 22;
+  const size_t lds = static_cast<size_t>(g.cols_per_wg) * static_cast<size_t>(ws) * 4;
+  const int cap = sign_chunks_per_lane(n) == 1 ? kSignWaves * kSignBatch<1>
+                                               : kSignWaves * kSignBatch<2>;
+  if (g.cols_per_wg > cap || rows_per_wg > kWave * kSignPersistRows ||
+      lds > static_cast<size_t>(kSignPersistLds) || g.grid > kSignThreads)
+    return hipErrorInvalidValue;
+  void* args[] = {&bits, &ws, &nn, &m, &ld, &c64, &r64, &r32, const_cast<double*>(&inv_n),
+                  const_cast<double*>(&inv_sqrt_n), &cols_per_wg, &rows_per_wg, &slots, &epoch,
+                  &spin_limit, &max_iters, &thr, &x, &st, &tr};
+  const void* fn = sign_persist_fn(n);
+  if (hipError_t e = sign_persist_attr(sign_chunks_per_lane(n) == 1 ? 0 : 1, fn); e != hipSuccess)
+    return e;
+  return hipLaunchCooperativeKernel(fn, dim3(g.grid), dim3(kSignThreads), args,
+                                    static_cast<unsigned>(lds), s);
 }
 
 hipError_t launch_mp_step_sign(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, int64_t ld,

@@ -103,6 +103,7 @@ void free_ctx(mp_ctx* c) {
   (void)hipFree(c->sign_c64);
   (void)hipFree(c->sign_r64);
   (void)hipFree(c->sign_rrp);
+  (void)hipFree(c->sign_slots);
   (void)hipFree(c->scales);
   (void)hipFree(c->r_work);
   (void)hipFree(c->st);
@@ -151,7 +152,8 @@ mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
   if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
     return fail(c, MP_EINVAL, "eps must be finite and >= 0");
   if (opts->max_iters < 0) return fail(c, MP_EINVAL, "max_iters must be >= 0");
-  if (opts->flags != 0) return fail(c, MP_EINVAL, "opts.flags must be 0");
+  if (opts->flags & ~static_cast<uint32_t>(MP_SOLVE_STEP_LAUNCHES))
+    return fail(c, MP_EINVAL, "unknown opts.flags");
   if (opts->rescore_k < 0 || opts->rescore_k > 8)
     return fail(c, MP_EINVAL, "rescore_k must be in 0..8");
   return MP_OK;
@@ -282,7 +284,7 @@ mp_status finish_result(mp_ctx* c, mp_result* res) {
     res->yy = d.yy;
     res->rr = d.rr;
     res->stop_reason = d.reason;
-    res->reserved = 0;
+    res->persistent = 0;
   }
   return MP_OK;
 }
@@ -468,6 +470,9 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_ctx* c = ctx;
   c->rescore_k = opts->rescore_k == 0 ? mp::kLpTopK : opts->rescore_k;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  bool persistent = false;  // the one-bit decode ran as one persistent launch
 
   HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, c->r_work, c->st, opts->eps,
                              static_cast<long long>(opts->max_iters), s));
@@ -479,10 +484,35 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     if (!c->h_st->done)
       HIP_TRY(c, mp::launch_sign_c0(c->psis, c->sign_ws, c->n, c->m, y, c->ld, c->sign_c64,
                                     c->sign_r64, s));
-    long long k = 0;
     const long long T = opts->max_iters;
     const double thr = c->h_st->thr;
-    const mp_status st = run_iterations(c, T > 0 ? T + 2 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
+    // the whole decode as one persistent launch when it fits, unless the
+    // caller asks for one launch per step; a launch the device refuses
+    // falls back to stepping
+    if (c->sign_persist && !(opts->flags & MP_SOLVE_STEP_LAUNCHES) && !c->h_st->done) {
+      if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+      // a new tag epoch for every decode (never 0 mod kSignEpochMod: the
+      // zeroed words match no step); when it wraps, clear the words so that
+      // none left from a decode that many decodes ago can match
+      c->sign_epoch = c->sign_epoch % (mp::kSignEpochMod - 1) + 1;
+      if (c->sign_epoch == 1)
+        HIP_TRY(c, hipMemsetAsync(c->sign_slots, 0,
+                                  sizeof(unsigned long long) * mp::kSignSlotWords * 2 *
+                                      static_cast<size_t>(c->geom.grid),
+                                  s));
+      const hipError_t e = mp::launch_sign_persist(
+          c->psis, c->sign_ws, c->n, c->m, c->ld, c->sign_c64, c->sign_r64, c->r_work, c->geom,
+          c->sign_slots, c->sign_epoch, T, thr, x, c->st, tr, s);
+      if (e == hipSuccess) {
+        persistent = true;
+        if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], s));
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    long long k = 0;
+    const mp_status st = persistent ? MP_OK :
+        run_iterations(c, T > 0 ? T + 2 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
       hipError_t e;
       if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
       e = mp::launch_mp_step_sign(c->psis, c->sign_ws, c->n, c->m, c->ld, c->sign_c64,
@@ -520,6 +550,15 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
 
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  if (persistent && c->profiling) {
+    // the persistent launch runs t + 2 steps (step j of it does what launch
+    // j of the stepping form does): the launch time over the steps
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) {
+      c->prof_ms = ms;
+      c->prof_launches = c->h_st->t + 2;
+    }
+  }
   if (r) {
     // the one-bit form keeps its FP32 r in the first half; the others in the
     // half the state names
@@ -527,7 +566,9 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     HIP_TRY(c, hipMemcpyAsync(r, rs, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(c, hipStreamSynchronize(s));
-  return finish_result(c, res);
+  const mp_status fs = finish_result(c, res);
+  if (fs == MP_OK && res) res->persistent = persistent ? 1 : 0;
+  return fs;
 }
 
 static mp_status ensure_omp(mp_ctx* c, int64_t tq) {
@@ -711,11 +752,26 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
     return bail(MP_ENOMEM, "partials");
   if (hipMalloc(&c->sign_rrp, sizeof(double) * 2 * c->geom.grid) != hipSuccess)
     return bail(MP_ENOMEM, "partial norms");
+  // the persistent decode (bits in LDS): one workgroup per CU, all resident,
+  // on a device that launches cooperative kernels
+  {
+    int coop = 0;
+    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    c->sign_persist = coop != 0 &&
+                      mp::sign_persist_fits(n, m, c->ld, c->sign_ws, c->geom, c->num_cus) &&
+                      mp::sign_persist_resident(n, c->sign_ws, c->geom, c->num_cus);
+  }
+  const size_t slot_bytes =
+      sizeof(unsigned long long) * mp::kSignSlotWords * 2 * static_cast<size_t>(c->geom.grid);
+  if (hipMalloc(&c->sign_slots, slot_bytes) != hipSuccess)
+    return bail(MP_ENOMEM, "step records");
   if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
     return bail(MP_ENOMEM, "pinned state");
   hipError_t e = mp::launch_copy_signs(signs, ldw, n, m, c->sign_ws, c->psis, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(c->sign_slots, 0, slot_bytes, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("copy: ") + hipGetErrorString(e));
   *out = c;
@@ -961,7 +1017,7 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
       res[b].yy = d.yy;
       res[b].rr = d.rr;
       res[b].stop_reason = d.reason;
-      res[b].reserved = 0;
+      res[b].persistent = 0;
     }
   }
   if (internal)
@@ -1239,7 +1295,7 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
       res[i].yy = d.yy;
       res[i].rr = d.rr;
       res[i].stop_reason = d.reason;
-      res[i].reserved = 0;
+      res[i].persistent = 0;
     }
   }
   if (internal)

@@ -105,6 +105,26 @@ hipError_t launch_mp_step_f64(const double* psi, int64_t ld, int64_t n, int64_t 
 // 16-byte chunks of a column each lane reads (1 for n <= 8192, 2 above).
 int sign_chunks_per_lane(int64_t n);
 CorrGeom sign_geometry(int64_t n, int64_t m, int num_cus);
+
+// Step records of the persistent one-bit decode: kSignSlotWords arrays of
+// 2 x grid 64-bit words (word q of workgroup g for steps of parity p at
+// (q * 2 + p) * grid + g), each word a 32-bit tag over 32 bits of payload
+// (the best key's two high halves, its low word, the partial ||r||^2's two
+// halves); the tag is ((epoch mod 4096) << 20) | ((step + 1) mod 2^20) with
+// epoch mod 4096 never 0, so the zeroed words match no step.
+constexpr int kSignSlotWords = 5;
+constexpr unsigned kSignEpochMod = 4096;
+// Whether the persistent one-bit decode can hold this geometry (one
+// workgroup per CU, the share's bits in LDS, rows of r in registers).
+bool sign_persist_fits(int64_t n, int64_t m, int64_t ld, int64_t ws, const CorrGeom& g,
+                       int num_cus);
+// Whether the device keeps `g.grid` persistent workgroups resident at once
+// (sets the kernel's LDS limit; false if it cannot).
+bool sign_persist_resident(int64_t n, int64_t ws, const CorrGeom& g, int num_cus);
+hipError_t launch_sign_persist(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, int64_t ld,
+                               const double* c64, double* r64, float* r32, const CorrGeom& g,
+                               unsigned long long* slots, unsigned epoch, long long max_iters,
+                               double thr, float* x, DevState* st, mp_trace tr, hipStream_t s);
 // Packed input (ldw words per column) -> ws words per column, rows >= n cleared.
 hipError_t launch_copy_signs(const uint32_t* in, int64_t ldw, int64_t n, int64_t m, int64_t ws,
                              uint32_t* out, hipStream_t s);
@@ -237,6 +257,9 @@ struct mp_ctx {
   double* sign_c64 = nullptr;    // MP_SIGN1: the carried correlations, m doubles
   double* sign_r64 = nullptr;    // MP_SIGN1: r in FP64, ld doubles
   double* sign_rrp = nullptr;    // MP_SIGN1: per-workgroup partial ||r||^2, 2 x grid
+  unsigned long long* sign_slots = nullptr;  // MP_SIGN1 persistent decode: step records
+  unsigned sign_epoch = 0;       // MP_SIGN1 persistent decode: tag epoch of the last decode
+  bool sign_persist = false;     // MP_SIGN1: the persistent decode fits this device
   float* scales = nullptr;       // FP8 per-column scales
   // per-decode work buffers
   float* r_work = nullptr;       // ld floats, rows n..ld-1 stay zero

@@ -26,6 +26,7 @@ MP_F32, MP_BF16, MP_FP8_E4M3, MP_F64, MP_SIGN1 = 0, 1, 2, 3, 4
 STOP_CONVERGED, STOP_MAX_ITERS, STOP_STALLED, STOP_ZERO_INPUT = 0, 1, 2, 3
 STOP_NAMES = {0: "converged", 1: "max_iters", 2: "stalled", 3: "zero_input"}
 MP_SKIP_NORM_CHECK = 0x1
+MP_SOLVE_STEP_LAUNCHES = 0x1  # mp_opts.flags
 DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3, "f64": MP_F64, "sign": MP_SIGN1}
 
 
@@ -36,7 +37,7 @@ class Opts(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("yy", ctypes.c_double), ("rr", ctypes.c_double),
-                ("stop_reason", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("stop_reason", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -357,10 +358,11 @@ class Decoder:
 
     def solve(self, y: torch.Tensor, eps: float, max_iters: int, x: Optional[torch.Tensor] = None,
               r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
-              stream=None, omp: bool = False):
-        """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, trace...).
-        ``omp=True`` decodes with Orthogonal Matching Pursuit (mp_solve_omp;
-        MP_F32 storage)."""
+              stream=None, omp: bool = False, step_launches: bool = False):
+        """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, persistent,
+        trace...).  ``omp=True`` decodes with Orthogonal Matching Pursuit
+        (mp_solve_omp; MP_F32 storage).  ``step_launches=True``: the one-bit
+        form steps with one launch per iteration (MP_SOLVE_STEP_LAUNCHES)."""
         dt = self.dtype
         if not y.is_cuda or y.dtype != dt or y.numel() != self.n:
             raise ValueError(f"y must be a {dt} CUDA tensor of N elements")
@@ -378,14 +380,16 @@ class Decoder:
             trr = torch.zeros(trace_cap, dtype=torch.float64, device=dev)
             tr = (TraceF64 if self.storage == "f64" else Trace)(
                 tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
-        opts = Opts(float(eps), int(max_iters), int(rescore_k), 0)
+        opts = Opts(float(eps), int(max_iters), int(rescore_k),
+                    MP_SOLVE_STEP_LAUNCHES if step_launches else 0)
         if omp and self.storage != "f32":
             raise ValueError("OMP decodes need f32 storage")
         solve = mp_solve_f64 if self.storage == "f64" else (mp_solve_omp if omp else mp_solve)
         res = solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
                     _stream_ptr(stream))
         out = dict(x=x, r=r, iters=res.iters, yy=res.yy, rr=res.rr,
-                   stop=STOP_NAMES.get(res.stop_reason, res.stop_reason))
+                   stop=STOP_NAMES.get(res.stop_reason, res.stop_reason),
+                   persistent=bool(res.persistent))
         if tr is not None:
             k = min(res.iters, trace_cap)
             out.update(idx=tidx[:k], coef=tcoef[:k], rr_trace=trr[:k])

@@ -139,6 +139,38 @@ def test_parity_many_columns(n, m, planted):
     assert rep.prefix >= min(rep.iters_ora, 5), rep
 
 
+@pytest.mark.parametrize("case", ["c0", "c1a", "c1b", "100x1000", "2047x300", "1x5"])
+def test_persistent_matches_step_launches(case):
+    """Where the whole decode fits one persistent launch (every workgroup's
+    share of the bits in LDS), it gives the stepping form's results bit for
+    bit: x~, r, the iteration count and every step's index, coefficient and
+    ||r||^2."""
+    if case.startswith("c"):
+        p = mpgen.make_sign_problem(case, 0)
+        n, m, bits, y, eps, t_cap = p.n, p.m, p.bits, p.y, p.eps, p.max_iters
+    else:
+        n, m = (int(v) for v in case.split("x"))
+        rng = np.random.default_rng(n * 31 + m)
+        s = mpgen.bernoulli_signs(rng, n, m)
+        k = max(1, min(6, n // 8, m // 4))
+        x, sup = mpgen.sparse_signal(rng, rng, m, k)
+        y = mpgen.encode_signs(s, x, sup)
+        bits = mpgen.pack_signs(s)
+        eps, t_cap = 1e-6, 200
+    print(f"[sign persistent {case}]", flush=True)
+    cap = int(min(t_cap, 4096))
+    with _decoder(bits, n) as dec:
+        yd = torch.from_numpy(np.asarray(y, dtype=np.float32)).cuda()
+        a = dec.solve(yd, eps, t_cap, trace_cap=cap)
+        b = dec.solve(yd, eps, t_cap, trace_cap=cap, step_launches=True)
+        torch.cuda.synchronize()
+    assert a["persistent"] and not b["persistent"]
+    assert a["iters"] == b["iters"] and a["stop"] == b["stop"]
+    assert a["rr"] == b["rr"]
+    for key in ("x", "r", "idx", "coef", "rr_trace"):
+        assert np.array_equal(_np(a[key]), _np(b[key])), key
+
+
 @pytest.mark.parametrize("n", [64, 256, 4096])
 def test_hadamard_exact_with_ties(n):
     """Sylvester columns (orthonormal, 1/sqrt(N) a power of two) and dyadic
