@@ -22,7 +22,9 @@ namespace mp {
 constexpr int kOmpThreads = 1024;
 constexpr int kOmpWaves = kOmpThreads / kWave;
 constexpr int kOrthRows = 64;                  // rows of w per workgroup of k_omp_orth
-constexpr int kOrthThreads = 256;              // 4 waves: the sum over j split 4 ways
+constexpr int kOrthWaves = 16;                 // the sum over j split 16 ways
+constexpr int kOrthThreads = kOrthWaves * kWave;
+constexpr int kProjSliceMax = 16384 / 4 / kOmpProjSlices;  // float4s of a slice (ld <= 16384)
 
 // ---------------------------------------------------------------------------
 // Selection: the FP32 correlation pass and argmax of the MP step; the last
@@ -76,52 +78,83 @@ __global__ __launch_bounds__(kOmpThreads) void k_omp_select(
 }
 
 // ---------------------------------------------------------------------------
-// h[j] = <q_j, v> for j < t: wave w of workgroup b takes j = 16 b + w.  v is
-// the selected atom (pass 1) or the partly orthogonalised w (pass 2), staged
-// in LDS; Q is read with caching (the next stage reads it again).
+// The projections <q_j, v>, j < t, by slice of rows: workgroup (b, s) stages
+// slice s of v (ld / kOmpProjSlices rows) in LDS and its wave w stores
+// hp[j * kOmpProjSlices + s] = sum over the slice of q_j[n] v[n] for
+// j = 16 b + w (lane l sums float4s l, l + 64, ... of the slice in order,
+// then the wave sums the lanes).  v is the selected atom (pass 1) or the
+// partly orthogonalised w (pass 2); Q is read with caching (the next stage
+// reads it again).
 __global__ __launch_bounds__(kOmpThreads) void k_omp_proj(
     const float* __restrict__ q, int64_t ld, const float* __restrict__ psi,
-    const float* __restrict__ wv, bool from_atom, float* __restrict__ h,
+    const float* __restrict__ wv, bool from_atom, float* __restrict__ hp,
     const DevState* __restrict__ st, const OmpState* __restrict__ os) {
   if (st->done) return;
   const long long t = st->t;
   const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kOmpWaves;
   if (j0 >= t) return;  // workgroup-uniform
-  extern __shared__ v4f v_lds[];
-  const int ld4 = static_cast<int>(ld / 4);
+  __shared__ v4f v_lds[kProjSliceMax];
+  const int len4 = static_cast<int>(ld / 4) / kOmpProjSlices;  // ld is a multiple of 64
+  const int base = static_cast<int>(blockIdx.y) * len4;
   const float* v = from_atom ? psi + static_cast<int64_t>(os->sel) * ld : wv;
-  const v4f* v4 = reinterpret_cast<const v4f*>(v);
-  for (int i = threadIdx.x; i < ld4; i += kOmpThreads) v_lds[i] = v4[i];
+  const v4f* v4 = reinterpret_cast<const v4f*>(v) + base;
+  for (int i = threadIdx.x; i < len4; i += kOmpThreads) v_lds[i] = v4[i];
   __syncthreads();
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t j = j0 + wave;
   if (j < t) {
-    const float d = dot_column_f32<false>(reinterpret_cast<const v4f*>(q + j * ld), v_lds, ld4, lane);
-    if (lane == 0) h[j] = d;
+    const v4f* qj = reinterpret_cast<const v4f*>(q + j * ld) + base;
+    float acc = 0.0f;
+#pragma unroll 4
+    for (int i = lane; i < len4; i += kWave) {
+      const v4f a = qj[i], c = v_lds[i];
+      acc = __builtin_fmaf(a.x, c.x, acc);
+      acc = __builtin_fmaf(a.y, c.y, acc);
+      acc = __builtin_fmaf(a.z, c.z, acc);
+      acc = __builtin_fmaf(a.w, c.w, acc);
+    }
+    const float d = wave_sum(acc);
+    if (lane == 0) hp[j * kOmpProjSlices + blockIdx.y] = d;
   }
 }
 
-// w[n] = v[n] - sum_{j<t} h[j] q_j[n] for the workgroup's 64 rows; wave w
-// sums the j = w mod 4, the four partial sums are added in a fixed order;
-// the workgroup's FP64 sum of w^2 goes to part[b].
+// w[n] = v[n] - sum_{j<t} h[j] q_j[n] for the workgroup's 64 rows, with
+// h[j] = the sum of j's slice projections (slices in order, staged in LDS;
+// workgroup 0 also stores h for R's column): wave w sums j = w mod 16 in
+// increasing order, one row per lane; the 16 partial sums are added in a
+// fixed tree; the workgroup's FP64 sum of w^2 goes to part[b].
 __global__ __launch_bounds__(kOrthThreads) void k_omp_orth(
     const float* __restrict__ q, int64_t ld, const float* __restrict__ psi,
-    const float* __restrict__ wv_in, bool from_atom, const float* __restrict__ h,
-    float* __restrict__ w_out, double* __restrict__ part, const DevState* __restrict__ st,
-    const OmpState* __restrict__ os) {
+    const float* __restrict__ wv_in, bool from_atom, const float* __restrict__ hp,
+    float* __restrict__ h_out, float* __restrict__ w_out, double* __restrict__ part,
+    const DevState* __restrict__ st, const OmpState* __restrict__ os) {
   if (st->done) return;
-  __shared__ float ps[4][kOrthRows];
+  extern __shared__ float h_lds[];  // t floats
+  __shared__ float ps[kOrthWaves][kOrthRows];
   __shared__ double red[1];
   const long long t = st->t;
+  for (long long j = threadIdx.x; j < t; j += kOrthThreads) {
+    float hs = 0.0f;
+#pragma unroll
+    for (int s = 0; s < kOmpProjSlices; ++s) hs += hp[j * kOmpProjSlices + s];
+    h_lds[j] = hs;
+    if (blockIdx.x == 0) h_out[j] = hs;
+  }
+  __syncthreads();
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t nrow = static_cast<int64_t>(blockIdx.x) * kOrthRows + lane;
   float acc = 0.0f;
-  for (long long j = wave; j < t; j += 4) acc = __builtin_fmaf(h[j], q[j * ld + nrow], acc);
+#pragma unroll 4
+  for (long long j = wave; j < t; j += kOrthWaves)
+    acc = __builtin_fmaf(h_lds[j], q[j * ld + nrow], acc);
   ps[wave][lane] = acc;
   __syncthreads();
   if (wave == 0) {
+    float p8[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p8[k] = ps[k][lane] + ps[k + 8][lane];
+    const float s = ((p8[0] + p8[4]) + (p8[2] + p8[6])) + ((p8[1] + p8[5]) + (p8[3] + p8[7]));
     const float* v = from_atom ? psi + static_cast<int64_t>(os->sel) * ld : wv_in;
-    const float s = (ps[0][lane] + ps[2][lane]) + (ps[1][lane] + ps[3][lane]);
     const float wn = v[nrow] - s;
     w_out[nrow] = wn;
     const double sq = wave_sum(static_cast<double>(wn) * wn);
@@ -227,11 +260,9 @@ hipError_t launch_omp_iteration(const float* psi, int64_t ld, int64_t n, int64_t
   static bool big_lds = false;
   hipError_t e;
   if (!big_lds && lds > 60 * 1024) {
-    for (const void* fn : {reinterpret_cast<const void*>(k_omp_select),
-                           reinterpret_cast<const void*>(k_omp_proj)}) {
-      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-      if (e != hipSuccess) return e;
-    }
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_omp_select),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
     big_lds = true;
   }
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
@@ -242,14 +273,25 @@ hipError_t launch_omp_iteration(const float* psi, int64_t ld, int64_t n, int64_t
   // t <= t_bound (one more atom per iteration at most)
   const unsigned pgrid = static_cast<unsigned>(t_bound > 0 ? (t_bound + kOmpWaves - 1) / kOmpWaves : 1);
   const unsigned ogrid = static_cast<unsigned>(ld / kOrthRows);
+  // h staged in LDS: tq <= 16384 floats, beside 4 KB of static LDS
+  const size_t h_lds = static_cast<size_t>(b.tq) * sizeof(float);
+  static bool orth_big_lds = false;
+  if (!orth_big_lds && h_lds > 56 * 1024) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_omp_orth),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+    if (e != hipSuccess) return e;
+    orth_big_lds = true;
+  }
+  if (ld % (4 * kOmpProjSlices) != 0 || ld / 4 / kOmpProjSlices > kProjSliceMax)
+    return hipErrorInvalidValue;
   for (int pass = 0; pass < 2; ++pass) {
     const bool from_atom = pass == 0;
     float* h = pass == 0 ? b.h1 : b.h2;
-    k_omp_proj<<<dim3(pgrid), dim3(kOmpThreads), lds, s>>>(b.q, ld, psi, b.w, from_atom, h, st,
-                                                          b.os);
+    k_omp_proj<<<dim3(pgrid, kOmpProjSlices), dim3(kOmpThreads), 0, s>>>(b.q, ld, psi, b.w,
+                                                                       from_atom, b.hp, st, b.os);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_omp_orth<<<dim3(ogrid), dim3(kOrthThreads), 0, s>>>(b.q, ld, psi, b.w, from_atom, h, b.w,
-                                                         b.part, st, b.os);
+    k_omp_orth<<<dim3(ogrid), dim3(kOrthThreads), h_lds, s>>>(b.q, ld, psi, b.w, from_atom, b.hp,
+                                                             h, b.w, b.part, st, b.os);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   k_omp_update<<<dim3(1), dim3(kOmpThreads), 0, s>>>(b.q, ld, n, b.tq, b.w, b.h1, b.h2, b.part,

@@ -84,6 +84,7 @@ void free_omp(mp_ctx* c) {
   (void)hipFree(b.w);
   (void)hipFree(b.h1);
   (void)hipFree(b.h2);
+  (void)hipFree(b.hp);
   (void)hipFree(b.part);
   (void)hipFree(b.os);
   b = mp::OmpBufs{};
@@ -584,6 +585,7 @@ static mp_status ensure_omp(mp_ctx* c, int64_t tq) {
             hipMalloc(&b.w, sizeof(float) * ld) == hipSuccess &&
             hipMalloc(&b.h1, sizeof(float) * t) == hipSuccess &&
             hipMalloc(&b.h2, sizeof(float) * t) == hipSuccess &&
+            hipMalloc(&b.hp, sizeof(float) * t * mp::kOmpProjSlices) == hipSuccess &&
             hipMalloc(&b.part, sizeof(double) * (ld / 64)) == hipSuccess &&
             hipMalloc(&b.os, sizeof(mp::OmpState)) == hipSuccess;
   if (!ok) {

@@ -154,9 +154,12 @@ struct OmpBufs {            // work buffers of one OMP decode (context-owned)
   float* w = nullptr;       // ld: the vector being orthogonalised
   float* h1 = nullptr;      // tq: Q^T psi_i (first Gram-Schmidt pass)
   float* h2 = nullptr;      // tq: Q^T w (second pass)
+  float* hp = nullptr;      // tq x kOmpProjSlices: the projections by slice of rows
   double* part = nullptr;   // ld / 64: per-workgroup sums of w^2
   OmpState* os = nullptr;
 };
+// Slices of rows the projections of an OMP iteration are split into.
+constexpr int kOmpProjSlices = 8;
 // One OMP iteration (five launches); t_bound >= the number of atoms selected
 // so far (sizes the projection grid).  e0/e1 time the selection pass.
 hipError_t launch_omp_iteration(const float* psi, int64_t ld, int64_t n, int64_t m, float* r,
