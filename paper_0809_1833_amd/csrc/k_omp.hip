@@ -175,6 +175,17 @@ __global__ __launch_bounds__(kOmpThreads) void k_omp_update(
   if (st->done) return;
   __shared__ double dred[kOmpWaves];
   const long long t = st->t;
+  // w and r in registers for the whole kernel (thread i holds elements
+  // i, i + kOmpThreads, ...: the order of every sum below), requested before
+  // the first reduction
+  constexpr int P = 16384 / kOmpThreads;  // ld <= 16384
+  float wv[P], rv[P];
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int64_t i = threadIdx.x + static_cast<int64_t>(u) * kOmpThreads;
+    wv[u] = i < ld ? w[i] : 0.0f;
+    rv[u] = i < ld ? r[i] : 0.0f;
+  }
   double s = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kOmpThreads) s += part[i];
   const double rho2 = block_sum<kOmpThreads>(s, dred);
@@ -190,19 +201,28 @@ __global__ __launch_bounds__(kOmpThreads) void k_omp_update(
   const float inv = static_cast<float>(1.0 / rho);
   float* qt = q + t * ld;
   double zs = 0.0;
-  for (int64_t i = threadIdx.x; i < ld; i += kOmpThreads) {
-    const float qi = w[i] * inv;
-    qt[i] = qi;
-    zs += static_cast<double>(qi) * r[i];
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int64_t i = threadIdx.x + static_cast<int64_t>(u) * kOmpThreads;
+    if (i < ld) {
+      const float qi = wv[u] * inv;
+      qt[i] = qi;
+      zs += static_cast<double>(qi) * rv[u];
+      wv[u] = qi;
+    }
   }
   for (int64_t j = threadIdx.x; j < t; j += kOmpThreads) rmat[j + t * tq] = h1[j] + h2[j];
   const double zt = block_sum<kOmpThreads>(zs, dred);
   const float zf = static_cast<float>(zt);
   double rs = 0.0;
-  for (int64_t i = threadIdx.x; i < ld; i += kOmpThreads) {
-    const float v = __builtin_fmaf(-zf, qt[i], r[i]);
-    r[i] = v;
-    rs += static_cast<double>(v) * v;
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int64_t i = threadIdx.x + static_cast<int64_t>(u) * kOmpThreads;
+    if (i < ld) {
+      const float v = __builtin_fmaf(-zf, wv[u], rv[u]);
+      r[i] = v;
+      rs += static_cast<double>(v) * v;
+    }
   }
   const double rr = block_sum<kOmpThreads>(rs, dred);
   if (threadIdx.x == 0) {
