@@ -121,3 +121,33 @@ def test_sign_storage_goes_through_its_own_entry_point():
     h = ctypes.c_void_p(123)
     st = mp.library().mp_create(ctypes.byref(h), 0x1000, 4, 4, 4, mp.MP_SIGN1, 0, None)
     assert st == mp.MP_EINVAL and "mp_create_signs" in mp.mp_last_error(None)
+
+
+def _header_text():
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "include", "mp.h")) as f:
+        return f.read()
+
+
+def _struct_fields(text, name):
+    """Member names of `typedef struct name { ... } name;` in declaration order."""
+    import re
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return [m.group(1) for m in re.finditer(r"\b(\w+)\s*;", body)]
+
+
+def test_binding_flags_match_the_header():
+    import re
+    text = _header_text()
+    for name in ("MP_SKIP_NORM_CHECK", "MP_SOLVE_STEP_LAUNCHES"):
+        value = re.search(r"#define %s (0x[0-9a-fA-F]+)u" % name, text).group(1)
+        assert getattr(mp, name) == int(value, 16), name
+
+
+def test_binding_structs_match_the_header():
+    text = _header_text()
+    assert [f[0] for f in mp.Opts._fields_] == _struct_fields(text, "mp_opts")
+    assert [f[0] for f in mp.Result._fields_] == _struct_fields(text, "mp_result")
+    assert ctypes.sizeof(mp.Result) == 32 and ctypes.sizeof(mp.Opts) == 24
