@@ -258,7 +258,10 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
  * mp_solve runs the whole decode as one cooperative launch that keeps the
  * bits on chip and exchanges each step's candidates between workgroups
  * through device memory; otherwise, or with MP_SOLVE_STEP_LAUNCHES, one
- * launch per step.  Both give the same results bit for bit.  The context has
+ * launch per step.  Both give the same results bit for bit.  A wait between
+ * the persistent launch's workgroups that exceeds its poll limit (2^22, or
+ * the positive integer in the environment variable MP_SIGN_SPIN_LIMIT, read
+ * at each decode) ends the decode with MP_EDEVICE.  The context has
  * storage MP_SIGN1; mp_solve_batched and mp_solve_omp return MP_EINVAL for
  * it.
  *

@@ -33,6 +33,8 @@
 // Keys and partial norms alternate between two halves by launch parity.  The
 // first launch of a decode publishes the keys of c(0) and the norms of r = y;
 // T steps take T+2 launches.  After the stop every launch returns at once.
+#include <cstdlib>
+
 #include "k_common.h"
 #include "k_key2.h"
 #include "mp_internal.h"
@@ -657,7 +659,13 @@ hipError_t launch_sign_persist(const uint32_t* bits, int64_t ws, int64_t n, int6
   int rows_per_wg = static_cast<int>((ld + g.grid - 1) / g.grid);
   int cols_per_wg = g.cols_per_wg;
   int nn = static_cast<int>(n);
+  // polls per wait before the run is marked failed; MP_SIGN_SPIN_LIMIT (a
+  // positive integer) overrides it, so that tests can drive the failure path
   long long spin_limit = 1ll << 22;
+  if (const char* env = getenv("MP_SIGN_SPIN_LIMIT")) {
+    const long long v = atoll(env);
+    if (v > 0) spin_limit = v;
+  }
   const size_t lds = static_cast<size_t>(g.cols_per_wg) * static_cast<size_t>(ws) * 4;
   const int cap = sign_chunks_per_lane(n) == 1 ? kSignWaves * kSignBatch<1>
                                                : kSignWaves * kSignBatch<2>;

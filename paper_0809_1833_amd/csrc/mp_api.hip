@@ -279,7 +279,9 @@ mp_status finish_result(mp_ctx* c, mp_result* res) {
   const mp::DevState& d = *c->h_st;
   if (d.reason == mp::kStopNonFinite) return fail(c, MP_ENONFINITE, "y holds NaN or Inf");
   if (d.reason == mp::kStopInternal)
-    return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
+    return fail(c, MP_EDEVICE,
+                "internal error: a selected index fell outside the dictionary, or a wait of "
+                "the persistent one-bit decode gave up");
   if (res) {
     res->iters = d.t;
     res->yy = d.yy;

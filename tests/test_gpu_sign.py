@@ -171,6 +171,29 @@ def test_persistent_matches_step_launches(case):
         assert np.array_equal(_np(a[key]), _np(b[key])), key
 
 
+def test_persistent_wait_limit_fails_cleanly(monkeypatch):
+    """The persistent decode's waits cut to two polls (MP_SIGN_SPIN_LIMIT=1,
+    read by the library at each decode): over the decode's thousands of
+    steps some wait gives up, the run is marked failed and every workgroup
+    leaves through its own bounded wait, so the call returns MP_EDEVICE; the
+    context then decodes as before, bit for bit with the stepping form."""
+    from paper_0809_1833_amd import mp
+    p = mpgen.make_sign_problem("c1a", 0)
+    print("[sign persistent wait limit]", flush=True)
+    with _decoder(p.bits, p.n) as dec:
+        yd = torch.from_numpy(np.asarray(p.y, dtype=np.float32)).cuda()
+        monkeypatch.setenv("MP_SIGN_SPIN_LIMIT", "1")
+        with pytest.raises(mp.MPError) as e:
+            dec.solve(yd, p.eps, p.max_iters)
+        assert e.value.status == mp.MP_EDEVICE
+        monkeypatch.delenv("MP_SIGN_SPIN_LIMIT")
+        a = dec.solve(yd, p.eps, p.max_iters)
+        b = dec.solve(yd, p.eps, p.max_iters, step_launches=True)
+        torch.cuda.synchronize()
+    assert a["persistent"] and a["iters"] == b["iters"] and a["stop"] == b["stop"]
+    assert np.array_equal(_np(a["x"]), _np(b["x"])) and np.array_equal(_np(a["r"]), _np(b["r"]))
+
+
 @pytest.mark.parametrize("n", [64, 256, 4096])
 def test_hadamard_exact_with_ties(n):
     """Sylvester columns (orthonormal, 1/sqrt(N) a power of two) and dyadic
