@@ -159,13 +159,15 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
  *   y        device: N floats, not modified
  *   x        device: M floats, overwritten with x~ (FP32)
  *   r        device: N floats or NULL; receives the final residual (FP32)
- *   opts     host: tolerance, cap, re-score count
- *   res      host or NULL: iteration count, norms, stop reason
+ *   opts     host: tolerance, cap, re-score count, flags (0 or
+ *            MP_SOLVE_STEP_LAUNCHES)
+ *   res      host or NULL: iteration count, norms, stop reason, and whether
+ *            the decode ran as one persistent launch (one-bit form)
  *   trace    host struct of device arrays, or NULL (see mp_trace)
  *   stream   hipStream_t as void*
  *
  * y, x and r must not overlap.  Errors: MP_EINVAL (NULL ctx/y/x/opts, eps < 0
- * or not finite, max_iters < 0, flags != 0, rescore_k outside 0..8),
+ * or not finite, max_iters < 0, unknown flags, rescore_k outside 0..8),
  * MP_ENONFINITE (y holds NaN/Inf; x and r are then unspecified), MP_EDEVICE.
  */
 mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
@@ -230,7 +232,8 @@ mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, i
  *   y        device: N doubles, not modified
  *   x        device: M doubles, overwritten with x~
  *   r        device: N doubles or NULL; receives the final residual
- *   opts     host: eps, max_iters (rescore_k is ignored), flags 0
+ *   opts     host: eps, max_iters (rescore_k is ignored), flags 0 (or
+ *            MP_SOLVE_STEP_LAUNCHES, which has no effect here)
  *   res      host or NULL (rr is the FP64 norm of the FP64 residual)
  *   trace    host struct of device arrays, or NULL (see mp_trace_f64)
  *
@@ -299,7 +302,7 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
  *   ctx      from mp_create with MP_F32 storage
  *   y, x, r  as mp_solve (x~ is nonzero only on the selected atoms)
  *   opts     eps, max_iters (at most min(max_iters, N) atoms are selected),
- *            rescore_k ignored, flags 0
+ *            rescore_k ignored, flags 0 (or MP_SOLVE_STEP_LAUNCHES, no effect)
  *   res      host or NULL
  *   trace    host struct of device arrays, or NULL: idx[t] the atom selected
  *            at step t, coef[t] its correlation <r, psi_idx>, rr[t] ||r||^2
