@@ -139,12 +139,14 @@ def test_parity_many_columns(n, m, planted):
     assert rep.prefix >= min(rep.iters_ora, 5), rep
 
 
-@pytest.mark.parametrize("case", ["c0", "c1a", "c1b", "100x1000", "2047x300", "1x5"])
+@pytest.mark.parametrize("case", ["c0", "c1a", "c1b", "100x1000", "2047x300", "1x5",
+                                  "12000x16384"])
 def test_persistent_matches_step_launches(case):
     """Where the whole decode fits one persistent launch (every workgroup's
     share of the bits in LDS), it gives the stepping form's results bit for
     bit: x~, r, the iteration count and every step's index, coefficient and
-    ||r||^2."""
+    ||r||^2.  12000 x 16384 takes the two-chunks-per-lane variant (64
+    columns of 94 chunks per workgroup, 96 KB of LDS)."""
     if case.startswith("c"):
         p = mpgen.make_sign_problem(case, 0)
         n, m, bits, y, eps, t_cap = p.n, p.m, p.bits, p.y, p.eps, p.max_iters
