@@ -9,6 +9,12 @@ Contents
   Section 3 (eqs. 8-12, argmax tie rule of eq. 16), in C (``mp_oracle.c``);
   ``solve`` takes y as FP32 (the FP32 decoder's input), ``solve64`` an FP64
   dictionary and an FP64 y (the FP64 decoder's inputs).
+* :func:`replay` -- the same FP64 iteration following a given index sequence
+  instead of eq. 9's selection (C), optionally with each forced atom's deficit
+  against the FP64 maximum.
+* :func:`correlate_many` / :func:`top_gap` -- eq. 9's correlations of many
+  vectors at once (an FP64 matrix product), and per vector the smallest-index
+  argmax and the top-two gap.
 * :mod:`oracle.omp` -- Orthogonal Matching Pursuit in FP64 (MP's selection,
   least-squares re-fit of all selected atoms).
 * :mod:`oracle.signs` -- the Bernoulli dictionary of eq. 13 held as sign bits,
@@ -43,6 +49,10 @@ def load_library(path: str):
         f = getattr(lib, "mpo_solve_" + name)
         f.restype = ctypes.c_int
         f.argtypes = [p, i64, i64, i64, p, dbl, i64, p, p, p, p, p, p, p, p, p, p, i64]
+    for name in ("f32", "f64", "f64_y64"):
+        f = getattr(lib, "mpo_replay_" + name)
+        f.restype = ctypes.c_int
+        f.argtypes = [p, i64, i64, i64, p, p, i64, ctypes.c_int, p, p, p, p, p, p]
     for suf in ("f32", "f64"):
         g = getattr(lib, "mpo_correlate_" + suf)
         g.restype = None
@@ -169,11 +179,77 @@ def correlate(psi: np.ndarray, r: np.ndarray, lib=None) -> np.ndarray:
     return c
 
 
-def top_two(c: np.ndarray):
-    """(argmax index with smallest-index tie rule, top-two |c| gap)."""
-    a = np.abs(c)
-    i = int(np.argmax(a))  # numpy returns the first occurrence of the maximum
-    if a.size == 1:
-        return i, float(a[0])
-    second = float(np.max(np.delete(a, i)))
-    return i, float(a[i]) - second
+@dataclass
+class Replay:
+    x: np.ndarray          # (M,) float64 estimate after the forced steps
+    r: np.ndarray          # (N,) float64 residual after them
+    coef: np.ndarray       # (steps,) float64 FP64 coefficient of each forced step
+    rr_trace: np.ndarray   # (steps,) float64 ||r||^2 after each step
+    deficit: np.ndarray    # (steps,) max |c| - |c_forced| before each step (0 unchecked)
+    r_trace: Optional[np.ndarray]  # (steps, N) float64 r after each step, if asked
+
+
+def replay(psi: np.ndarray, y: np.ndarray, idx, check_ties: bool = True,
+           r_trace: bool = False, y64: bool = False, lib=None) -> Replay:
+    """The Section 3 iteration in FP64 with step t's atom forced to idx[t]
+    (eq. 9's selection replaced; eqs. 10-11 unchanged).  ``check_ties``: also
+    compute every correlation at every step and record the forced atom's
+    deficit max_m |c_m| - |c_idx|.  ``y64``: y is taken in FP64 (an FP64
+    dictionary only), else rounded to FP32 as :func:`solve` does."""
+    lib = _load() if lib is None else lib
+    base, suf, n, m, ld = _psi_view(psi)
+    if y64:
+        if psi.dtype != np.float64:
+            raise TypeError("an FP64 y needs a float64 dictionary")
+        yv, fname = np.ascontiguousarray(y, dtype=np.float64), "mpo_replay_f64_y64"
+    else:
+        yv, fname = np.ascontiguousarray(y, dtype=np.float32), "mpo_replay_" + suf
+    if yv.shape != (n,):
+        raise ValueError("y must have shape (N,)")
+    ix = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1)
+    steps = ix.size
+    x = np.zeros(m, dtype=np.float64)
+    r = np.zeros(n, dtype=np.float64)
+    coef = np.zeros(max(steps, 1), dtype=np.float64)
+    rr = np.zeros(max(steps, 1), dtype=np.float64)
+    dfc = np.zeros(max(steps, 1), dtype=np.float64)
+    rt = np.zeros((steps, n), dtype=np.float64) if r_trace else None
+    rc = getattr(lib, fname)(_ptr(base), n, m, ld, _ptr(yv), _ptr(ix) if steps else None, steps,
+                             1 if check_ties else 0, _ptr(x), _ptr(r), _ptr(coef), _ptr(rr),
+                             _ptr(dfc), _ptr(rt) if steps else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the replay (code {rc})")
+    return Replay(x, r, coef[:steps].copy(), rr[:steps].copy(), dfc[:steps].copy(), rt)
+
+
+def correlate_many(psi: np.ndarray, R: np.ndarray, chunk: int = 512) -> np.ndarray:
+    """C[:, j] = Psi^T R[:, j] in FP64 for every column of R (N x K): eq. 9's
+    correlations of K vectors, computed as one FP64 matrix product per chunk
+    of columns (torch on the CPU).  The summation order is the library's, so
+    each value differs from :func:`correlate`'s sequential sum only by FP64
+    rounding."""
+    import torch
+    n, m = psi.shape
+    R = np.asarray(R)
+    if R.ndim != 2 or R.shape[0] != n:
+        raise ValueError("R must have shape (N, K)")
+    P = torch.from_numpy(np.asarray(psi, dtype=np.float64).T.copy())  # (M, N), rows = columns
+    out = np.empty((m, R.shape[1]), dtype=np.float64)
+    for j0 in range(0, R.shape[1], chunk):
+        j1 = min(R.shape[1], j0 + chunk)
+        Rc = torch.from_numpy(np.ascontiguousarray(R[:, j0:j1], dtype=np.float64))
+        out[:, j0:j1] = (P @ Rc).numpy()
+    return out
+
+
+def top_gap(C: np.ndarray):
+    """Per column of C (M x K): the argmax of |c| with eq. 16's smallest-index
+    rule, the largest |c| and the gap to the second largest (0 for M = 1:
+    the largest |c| itself)."""
+    a = np.abs(np.asarray(C, dtype=np.float64))
+    best = np.argmax(a, axis=0)  # first occurrence: the smallest index
+    top = a[best, np.arange(a.shape[1])]
+    if a.shape[0] == 1:
+        return best, top, top.copy()
+    second = -np.partition(-a, 1, axis=0)[1]
+    return best, top, top - second

@@ -34,6 +34,17 @@
  *
  * Layout: psi is column-major N x M with leading dimension ld >= N, i.e.
  * psi_nm = psi[n + m*ld].
+ *
+ * Replay mode (mpo_replay_*): the same iteration with the selection of
+ * eq. 9 replaced by a given index sequence, so that another decoder's
+ * choices can be followed exactly in FP64.  Each step still takes its
+ * coefficient as the FP64 inner product <r, psi_i> (eq. 10) and updates r
+ * by eq. 11.  With check_ties set, every step also computes all the
+ * correlations and records the forced atom's deficit max_m |c_m| - |c_i|,
+ * which is 0 when the forced atom is a correct choice of eq. 9 and small
+ * when it is a near tie.  Replaying this file's own free-run sequence gives
+ * its free run back bit for bit (the coefficient is the same sequential sum
+ * in both modes).
  */
 #include <math.h>
 #include <stdint.h>
@@ -167,3 +178,57 @@ MPO_DEFINE_SOLVE(mpo_solve_f32, f32, float, float)
 MPO_DEFINE_SOLVE(mpo_solve_f64, f64, double, float)
 /* FP64 dictionary and FP64 y (the inputs of an FP64 decode) */
 MPO_DEFINE_SOLVE(mpo_solve_f64_y64, f64, double, double)
+
+/*
+ * Replay: x_out (M), r_out (N) as the solver; per step t < steps (each array
+ * may be NULL): the coefficient, sum r^2 after the step, the deficit
+ * max |c| - |c_i| before it (check_ties only, else 0), and r after the step
+ * (tr_r: steps x N doubles, step t at tr_r + t*N).  An index outside
+ * [0, M) is rejected (MPO_BAD_ARGS) before any step is taken.
+ */
+#define MPO_DEFINE_REPLAY(NAME, SUFFIX, T, YT)                                            \
+    int NAME(const T* psi, int64_t n, int64_t m, int64_t ld, const YT* y,                \
+             const int32_t* idx, int64_t steps, int check_ties,                          \
+             double* x_out, double* r_out, double* tr_coef, double* tr_rr,               \
+             double* tr_deficit, double* tr_r) {                                          \
+        if (!psi || !y || !x_out || !r_out || n < 1 || m < 1 || ld < n || steps < 0      \
+            || (steps > 0 && !idx))                                                       \
+            return MPO_BAD_ARGS;                                                          \
+        for (int64_t t = 0; t < steps; ++t)                                               \
+            if (idx[t] < 0 || idx[t] >= m) return MPO_BAD_ARGS;                           \
+        double* c = NULL;                                                                 \
+        if (check_ties) {                                                                 \
+            c = (double*)malloc(sizeof(double) * (size_t)m);                              \
+            if (!c) return MPO_NO_MEMORY;                                                 \
+        }                                                                                 \
+        for (int64_t i = 0; i < n; ++i) r_out[i] = (double)y[i];                          \
+        for (int64_t j = 0; j < m; ++j) x_out[j] = 0.0;                                   \
+        for (int64_t t = 0; t < steps; ++t) {                                             \
+            const int64_t i = idx[t];                                                     \
+            const T* col = psi + i * ld;                                                  \
+            double ci, deficit = 0.0;                                                     \
+            if (check_ties) {                                                             \
+                mpo_correlate_##SUFFIX(psi, n, m, ld, r_out, c);                          \
+                double best, second;                                                      \
+                (void)argmax_abs(c, m, &best, &second);                                   \
+                ci = c[i];                                                                \
+                deficit = best - fabs(ci);                                                \
+            } else {                                                                      \
+                double s = 0.0;                                                           \
+                for (int64_t k = 0; k < n; ++k) s += (double)col[k] * r_out[k];           \
+                ci = s;                                                                   \
+            }                                                                             \
+            x_out[i] += ci;                                                               \
+            for (int64_t k = 0; k < n; ++k) r_out[k] -= ci * (double)col[k];              \
+            if (tr_coef) tr_coef[t] = ci;                                                 \
+            if (tr_rr) tr_rr[t] = sumsq(r_out, n);                                        \
+            if (tr_deficit) tr_deficit[t] = deficit;                                      \
+            if (tr_r) memcpy(tr_r + t * n, r_out, sizeof(double) * (size_t)n);            \
+        }                                                                                 \
+        free(c);                                                                          \
+        return MPO_OK;                                                                    \
+    }
+
+MPO_DEFINE_REPLAY(mpo_replay_f32, f32, float, float)
+MPO_DEFINE_REPLAY(mpo_replay_f64, f64, double, float)
+MPO_DEFINE_REPLAY(mpo_replay_f64_y64, f64, double, double)

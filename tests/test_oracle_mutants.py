@@ -30,6 +30,12 @@ MUTANTS = {
     "dropped_last_term": ("for (int64_t i = 0; i < n; ++i) s += (double)col[i] * r[i];",
                           "for (int64_t i = 0; i + 1 < n; ++i) s += (double)col[i] * r[i];"),
     "stale_norm": ("rr = sumsq(r_out, n);", "rr = rr - ci * ci * 0.5;"),
+    # the replay mode
+    "replay_deficit_signed": ("deficit = best - fabs(ci);", "deficit = best - ci;"),
+    "replay_coef_from_y": ("for (int64_t k = 0; k < n; ++k) s += (double)col[k] * r_out[k];",
+                           "for (int64_t k = 0; k < n; ++k) s += (double)col[k] * (double)y[k];"),
+    "replay_deficit_vs_second": ("(void)argmax_abs(c, m, &best, &second);",
+                                 "(void)argmax_abs(c, m, &second, &best);"),
 }
 
 
@@ -108,6 +114,25 @@ def _run_battery(lib):
     res = oracle.solve64(psi64h, psi64h @ x64, 0.0, 10, lib=lib)
     if res.idx.tolist() != [1, 4, 9] or not np.array_equal(res.x, x64) or res.rr != 0.0:
         failed.append("fp64_dyadic")
+    # 6. replay on an orthonormal dictionary, support forced out of order: the
+    #    coefficients are the x values and the deficits max_remaining |x| - |x_i|
+    rng = np.random.default_rng(11)
+    q = mpgen.qr_orthonormal_dictionary(rng, 24)
+    xo = np.zeros(24)
+    order = [17, 3, 9, 21, 0]
+    xo[order] = [0.3, -1.7, 0.9, -0.2, 1.1]
+    rep = oracle.replay(q, q @ xo, order, check_ties=True, y64=True, lib=lib)
+    want = [max(abs(xo[j]) for j in order[t:]) - abs(xo[i]) for t, i in enumerate(order)]
+    if (np.max(np.abs(rep.coef - xo[order])) > 1e-14
+            or np.max(np.abs(rep.deficit - np.array(want))) > 1e-14):
+        failed.append("replay_orthonormal")
+    # 7. replaying the free run's own sequence gives the free run back
+    res = oracle.solve(p.psi, p.y, p.eps, p.max_iters, lib=lib)
+    for ties in (True, False):
+        rep = oracle.replay(p.psi, p.y, res.idx, check_ties=ties, lib=lib)
+        if not (np.array_equal(rep.x, res.x) and np.array_equal(rep.r, res.r)):
+            failed.append("replay_own_sequence")
+            break
     return failed
 
 
