@@ -107,20 +107,31 @@ typedef struct mp_result {
 /* Optional per-step record, all arrays device memory of `cap` entries.
    Step t (0-based) writes idx[t], coef[t] (the FP32 coefficient added to
    x~), rr[t] (||r||^2 after the step, FP64) while t < cap; any array may be
-   NULL. */
+   NULL.  r, if not NULL, receives the whole residual after each step
+   (eq. 11's r_{t+1}): rows 0..N-1 of step t at r + t * ldr, ldr >= N, so
+   r must hold cap * ldr floats (the batched and ragged decodes: signal or
+   instance b's step t at r + (b * cap + t) * ldr, ldr >= every N).  Rows
+   N..ldr-1 are left unwritten.  The one-bit form stores its FP64 residual
+   rounded to FP32.  Writing it costs N floats of traffic per step; it is
+   meant for checking a decode step by step, not for timing one. */
 typedef struct mp_trace {
     int32_t* idx;
     float* coef;
     double* rr;
     int64_t cap;
+    float* r;
+    int64_t ldr;
 } mp_trace;
 
-/* The same record for an FP64 decode: coef[t] is the FP64 coefficient. */
+/* The same record for an FP64 decode: coef[t] is the FP64 coefficient and
+   r (cap * ldr doubles, or NULL) the FP64 residual after each step. */
 typedef struct mp_trace_f64 {
     int32_t* idx;
     double* coef;
     double* rr;
     int64_t cap;
+    double* r;
+    int64_t ldr;
 } mp_trace_f64;
 
 /*

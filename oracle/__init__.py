@@ -12,9 +12,9 @@ Contents
 * :func:`replay` -- the same FP64 iteration following a given index sequence
   instead of eq. 9's selection (C), optionally with each forced atom's deficit
   against the FP64 maximum.
-* :func:`correlate_many` / :func:`top_gap` -- eq. 9's correlations of many
-  vectors at once (an FP64 matrix product), and per vector the smallest-index
-  argmax and the top-two gap.
+* :func:`correlate_many` / :class:`Correlator` / :func:`top_gap` -- eq. 9's
+  correlations of many vectors at once (an FP64 matrix product), and per
+  vector the smallest-index argmax and the top-two gap.
 * :mod:`oracle.omp` -- Orthogonal Matching Pursuit in FP64 (MP's selection,
   least-squares re-fit of all selected atoms).
 * :mod:`oracle.signs` -- the Bernoulli dictionary of eq. 13 held as sign bits,
@@ -222,24 +222,36 @@ def replay(psi: np.ndarray, y: np.ndarray, idx, check_ties: bool = True,
     return Replay(x, r, coef[:steps].copy(), rr[:steps].copy(), dfc[:steps].copy(), rt)
 
 
+class Correlator:
+    """Eq. 9's correlations of many vectors against one dictionary: keeps the
+    dictionary's FP64 transpose (M x N, one row per atom) so that repeated
+    calls do not convert it again.  ``many(R)`` is :func:`correlate_many`."""
+
+    def __init__(self, psi: np.ndarray):
+        import torch
+        self.n, self.m = psi.shape
+        self._P = torch.from_numpy(np.asarray(psi, dtype=np.float64).T.copy())
+
+    def many(self, R: np.ndarray, chunk: int = 512) -> np.ndarray:
+        import torch
+        R = np.asarray(R)
+        if R.ndim != 2 or R.shape[0] != self.n:
+            raise ValueError("R must have shape (N, K)")
+        out = np.empty((self.m, R.shape[1]), dtype=np.float64)
+        for j0 in range(0, R.shape[1], chunk):
+            j1 = min(R.shape[1], j0 + chunk)
+            Rc = torch.from_numpy(np.ascontiguousarray(R[:, j0:j1], dtype=np.float64))
+            out[:, j0:j1] = (self._P @ Rc).numpy()
+        return out
+
+
 def correlate_many(psi: np.ndarray, R: np.ndarray, chunk: int = 512) -> np.ndarray:
     """C[:, j] = Psi^T R[:, j] in FP64 for every column of R (N x K): eq. 9's
     correlations of K vectors, computed as one FP64 matrix product per chunk
     of columns (torch on the CPU).  The summation order is the library's, so
     each value differs from :func:`correlate`'s sequential sum only by FP64
     rounding."""
-    import torch
-    n, m = psi.shape
-    R = np.asarray(R)
-    if R.ndim != 2 or R.shape[0] != n:
-        raise ValueError("R must have shape (N, K)")
-    P = torch.from_numpy(np.asarray(psi, dtype=np.float64).T.copy())  # (M, N), rows = columns
-    out = np.empty((m, R.shape[1]), dtype=np.float64)
-    for j0 in range(0, R.shape[1], chunk):
-        j1 = min(R.shape[1], j0 + chunk)
-        Rc = torch.from_numpy(np.ascontiguousarray(R[:, j0:j1], dtype=np.float64))
-        out[:, j0:j1] = (P @ Rc).numpy()
-    return out
+    return Correlator(psi).many(R, chunk=chunk)
 
 
 def top_gap(C: np.ndarray):

@@ -603,6 +603,14 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     const v4f* colp = reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld);
     v4f* r4 = reinterpret_cast<v4f*>(r);
     uint2* rq4 = reinterpret_cast<uint2*>(Rq + static_cast<int64_t>(b) * ldq);
+    // this step's residual trace entry, if the trace asks for one (every
+    // thread reads the step count: thread 0 rewrites it only after the
+    // barriers of the norm below)
+    float* rt = nullptr;
+    if (tr.r) {
+      const long long tt = sl->t;
+      if (tt < tr.cap) rt = tr.r + (static_cast<int64_t>(b) * tr.cap + tt) * tr.ldr;
+    }
     double s = 0.0;
     for (int i = threadIdx.x; i < ld4; i += kBSelThreads) {
       const v4f a = colp[i], rv = r_lds[i];
@@ -612,6 +620,7 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
       o.z = __builtin_fmaf(-c, a.z, rv.z);
       o.w = __builtin_fmaf(-c, a.w, rv.w);
       r4[i] = o;
+      if (rt) trace_rows4(rt, i, n, o);
       rq4[i] = uint2{static_cast<uint32_t>(bf16_rne(o.x)) | (static_cast<uint32_t>(bf16_rne(o.y)) << 16),
                      static_cast<uint32_t>(bf16_rne(o.z)) | (static_cast<uint32_t>(bf16_rne(o.w)) << 16)};
       s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +

@@ -399,16 +399,26 @@ __device__ inline bool carried_winner_stops(int idx, float c, int64_t m,
   return true;
 }
 
+// Rows 4i..4i+3 of a residual into a trace entry (rows below n only).
+__device__ inline void trace_rows4(float* __restrict__ dst, int i, int64_t n, const v4f& o) {
+  const int64_t row = 4 * static_cast<int64_t>(i);
+  if (row < n) dst[row] = o.x;
+  if (row + 1 < n) dst[row + 1] = o.y;
+  if (row + 2 < n) dst[row + 2] = o.z;
+  if (row + 3 < n) dst[row + 3] = o.w;
+}
+
 // Step k applied in every workgroup: r -= c psi_idx with the FP32 column (one
 // FMA per element, padding rows stay +0) on the LDS copy and ||r||^2 in FP64
 // (per-thread sums over its float4s in order, then block_sum: the same value
 // in every workgroup); workgroup 0 also stores r in r_out, adds c to x~_idx
-// (eq. 10) and writes the trace entry and the state (t = k, eq. 12, the
-// stop test, `half` = the half of the residual buffer r_out is).  Returns
-// true, in every thread of every workgroup, when the run stops after step k.
+// (eq. 10) and writes the trace entry (with the residual's n rows when the
+// trace asks for them) and the state (t = k, eq. 12, the stop test, `half` =
+// the half of the residual buffer r_out is).  Returns true, in every thread
+// of every workgroup, when the run stops after step k.
 template <int NT>
 __device__ bool carried_update(int idx, float c, const float* __restrict__ psi32, int64_t ld,
-                               v4f* __restrict__ r_lds, v4f* __restrict__ r_out,
+                               int64_t n, v4f* __restrict__ r_lds, v4f* __restrict__ r_out,
                                float* __restrict__ x, DevState* __restrict__ st,
                                const mp_trace& tr, long long k, long long max_iters, double thr,
                                int half, double* dred) {
@@ -421,6 +431,8 @@ __device__ bool carried_update(int idx, float c, const float* __restrict__ psi32
     const int i = threadIdx.x + u * NT;
     a[u] = col[i < ld4 ? i : ld4 - 1];
   }
+  float* rt = nullptr;  // this step's residual trace entry (workgroup 0 only)
+  if (blockIdx.x == 0 && tr.r && k - 1 < tr.cap) rt = tr.r + (k - 1) * tr.ldr;
   double s = 0.0;
 #pragma unroll
   for (int u = 0; u < P; ++u) {
@@ -434,6 +446,7 @@ __device__ bool carried_update(int idx, float c, const float* __restrict__ psi32
       o.w = __builtin_fmaf(-c, a[u].w, rv.w);
       r_lds[i] = o;
       if (blockIdx.x == 0) r_out[i] = o;
+      if (rt) trace_rows4(rt, i, n, o);
       s += static_cast<double>(o.x) * o.x + static_cast<double>(o.y) * o.y +
            (static_cast<double>(o.z) * o.z + static_cast<double>(o.w) * o.w);
     }

@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
     const int idx = key_index(win);
     const float c = key_value(win);
     if (carried_winner_stops(idx, c, m, st)) return;
-    if (carried_update<kCorrThreads>(idx, c, psi, ld, r_lds, r_out, x, st, tr, k, max_iters, thr,
+    if (carried_update<kCorrThreads>(idx, c, psi, ld, n, r_lds, r_out, x, st, tr, k, max_iters, thr,
                                      par ^ 1, dred))
       return;
   } else if (blockIdx.x == 0) {

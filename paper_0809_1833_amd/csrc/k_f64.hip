@@ -202,6 +202,8 @@ __global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
       const int i = t + u * kF64Threads;
       a[u] = colp[i < ld2 ? i : ld2 - 1];
     }
+    // workgroup 0: this step's residual trace entry, if the trace asks for one
+    double* rt = blockIdx.x == 0 && tr.r && k - 1 < tr.cap ? tr.r + (k - 1) * tr.ldr : nullptr;
     double s = 0.0;
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
@@ -213,6 +215,10 @@ __global__ __launch_bounds__(kF64Threads) void k_mp_step_f64(
         o.y = __builtin_fma(-c, a[u].y, rv.y);
         r2_lds[i] = o;
         if (blockIdx.x == 0) r_out[i] = o;
+        if (rt) {
+          if (2 * i < n) rt[2 * i] = o.x;
+          if (2 * i + 1 < n) rt[2 * i + 1] = o.y;
+        }
         s = __builtin_fma(o.x, o.x, s);
         s = __builtin_fma(o.y, o.y, s);
       }

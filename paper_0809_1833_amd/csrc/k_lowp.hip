@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
     const int idx = key_index(best);
     const float c = key_value(best);
     if (carried_winner_stops(idx, c, m, st)) return;
-    if (carried_update<kLpThreads>(idx, c, psi32, ld, r_lds, r_out, x, st, tr, k, max_iters, thr,
+    if (carried_update<kLpThreads>(idx, c, psi32, ld, n, r_lds, r_out, x, st, tr, k, max_iters, thr,
                                    par ^ 1, dred))
       return;
   } else if (blockIdx.x == 0) {

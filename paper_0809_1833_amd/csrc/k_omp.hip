@@ -214,6 +214,7 @@ __global__ __launch_bounds__(kOmpThreads) void k_omp_update(
   for (int64_t j = threadIdx.x; j < t; j += kOmpThreads) rmat[j + t * tq] = h1[j] + h2[j];
   const double zt = block_sum<kOmpThreads>(zs, dred);
   const float zf = static_cast<float>(zt);
+  float* rt = tr.r && t < tr.cap ? tr.r + t * tr.ldr : nullptr;  // residual trace entry
   double rs = 0.0;
 #pragma unroll
   for (int u = 0; u < P; ++u) {
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(kOmpThreads) void k_omp_update(
     if (i < ld) {
       const float v = __builtin_fmaf(-zf, wv[u], rv[u]);
       r[i] = v;
+      if (rt && i < n) rt[i] = v;
       rs += static_cast<double>(v) * v;
     }
   }

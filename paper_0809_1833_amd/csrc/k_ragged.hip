@@ -196,10 +196,13 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
         }
         // ---- update (eqs. 10-12); every wave is past the pass (barrier above) ----
         const float* colp = d.psi32 + static_cast<int64_t>(idx) * ld;
+        float* rt = tr.r && t < tr.cap
+                        ? tr.r + (static_cast<int64_t>(id) * tr.cap + t) * tr.ldr : nullptr;
         s = 0.0;
         for (int64_t i = threadIdx.x; i < n; i += NT) {
           const float vv = __builtin_fmaf(-c, colp[i], rf[i]);
           rf[i] = vv;
+          if (rt) rt[i] = vv;
           s += static_cast<double>(vv) * vv;
         }
         rr = block_sum<NT>(s, dred);  // its barriers publish the new r to all waves

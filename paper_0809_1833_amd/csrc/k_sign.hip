@@ -289,6 +289,8 @@ __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
   if (wave == 0) {
     const double step = cs * inv_sqrt_n;
     const uint32_t* pw = bits + static_cast<int64_t>(idx < 0 ? 0 : idx) * ws;
+    // the residual trace entry of step k - 1, if the trace asks for one
+    float* rt = !first && tr.r && k - 1 < tr.cap ? tr.r + (k - 1) * tr.ldr : nullptr;
     double s = 0.0;
     for (int64_t i = row0 + lane; i < row1; i += kWave) {
       const bool lead = i == row0 + lane;
@@ -298,6 +300,7 @@ __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
         v = ((w >> (i & 31)) & 1u) ? v + step : v - step;
         r64[i] = v;
         r32[i] = static_cast<float>(v);
+        if (rt) rt[i] = static_cast<float>(v);
       }
       s += v * v;
     }
@@ -520,6 +523,8 @@ __global__ __launch_bounds__(kSignThreads) void k_sign_persist(
     if (wave == 0) {
       const double step = cs * inv_sqrt_n;
       const uint32_t* win_words = reinterpret_cast<const uint32_t*>(s_win);
+      // the residual trace entry of step j - 1, if the trace asks for one
+      float* rt = j > 0 && tr.r && j - 1 < tr.cap ? tr.r + (j - 1) * tr.ldr : nullptr;
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
@@ -530,6 +535,7 @@ __global__ __launch_bounds__(kSignThreads) void k_sign_persist(
             const uint32_t w = win_words[i >> 5];
             v = ((w >> (i & 31)) & 1u) ? v + step : v - step;
             rq[q] = v;
+            if (rt) rt[i] = static_cast<float>(v);
           }
           s += v * v;
         }

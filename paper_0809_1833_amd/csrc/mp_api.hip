@@ -149,6 +149,16 @@ mp_status check_norms(const std::vector<double>& norm2, uint32_t flags, std::str
   return MP_OK;
 }
 
+// The trace's residual rows: ldr must cover the longest residual it receives.
+template <class T>
+mp_status check_trace(mp_ctx* c, const T* trace, int64_t rows) {
+  if (!trace) return MP_OK;
+  if (trace->cap < 0) return fail(c, MP_EINVAL, "trace cap must be >= 0");
+  if (trace->r && trace->ldr < rows)
+    return fail(c, MP_EINVAL, "trace ldr must be >= the residual length");
+  return MP_OK;
+}
+
 mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
   if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
     return fail(c, MP_EINVAL, "eps must be finite and >= 0");
@@ -465,10 +475,8 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
   if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
   mp_trace tr{};
-  if (trace) {
-    if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
-    tr = *trace;
-  }
+  if (mp_status ts = check_trace(ctx, trace, ctx->n); ts != MP_OK) return ts;
+  if (trace) tr = *trace;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_ctx* c = ctx;
@@ -607,10 +615,8 @@ mp_status mp_solve_omp(mp_ctx* ctx, const float* y, float* x, float* r, const mp
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
   if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
   mp_trace tr{};
-  if (trace) {
-    if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
-    tr = *trace;
-  }
+  if (mp_status ts = check_trace(ctx, trace, ctx->n); ts != MP_OK) return ts;
+  if (trace) tr = *trace;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_ctx* c = ctx;
@@ -791,10 +797,8 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
   if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
   mp_trace_f64 tr{};
-  if (trace) {
-    if (trace->cap < 0) return fail(ctx, MP_EINVAL, "trace cap must be >= 0");
-    tr = *trace;
-  }
+  if (mp_status ts = check_trace(ctx, trace, ctx->n); ts != MP_OK) return ts;
+  if (trace) tr = *trace;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_ctx* c = ctx;
@@ -899,10 +903,8 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
     }
   }
   mp_trace tr{};
-  if (trace) {
-    if (trace->cap < 0) return fail(c, MP_EINVAL, "trace cap must be >= 0");
-    tr = *trace;
-  }
+  if (mp_status ts = check_trace(c, trace, c->n); ts != MP_OK) return ts;
+  if (trace) tr = *trace;
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   mp_status st = ensure_batched(c, B, s);
@@ -1218,10 +1220,9 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
     for (int64_t i = 0; i < c->r_count; ++i)
       if (max_iters[i] < 0) return fail(c, MP_EINVAL, "max_iters entries must be >= 0");
   mp_trace tr{};
-  if (trace) {
-    if (trace->cap < 0) return fail(c, MP_EINVAL, "trace cap must be >= 0");
-    tr = *trace;
-  }
+  const int64_t max_n = *std::max_element(c->r_n.begin(), c->r_n.end());
+  if (mp_status ts = check_trace(c, trace, max_n); ts != MP_OK) return ts;
+  if (trace) tr = *trace;
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool lp = c->storage == MP_BF16;
@@ -1236,12 +1237,12 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
 
   // (re)capture the solve as a graph when its arguments change
   struct Key {
-    const void *y, *x, *r, *caps, *ti, *tc, *trr;
+    const void *y, *x, *r, *caps, *ti, *tc, *trr, *tres;
     double eps;
-    long long cap_all, tcap;
+    long long cap_all, tcap, tldr;
     int rk, threads, cc, grid;
-  } key{Y, X, R, caps, tr.idx, tr.coef, tr.rr, opts->eps, opts->max_iters, tr.cap, rk,
-        c->r_cfg.threads, c->r_cfg.cols_per_wave, grid};
+  } key{Y, X, R, caps, tr.idx, tr.coef, tr.rr, tr.r, opts->eps, opts->max_iters, tr.cap, tr.ldr,
+        rk, c->r_cfg.threads, c->r_cfg.cols_per_wave, grid};
   const unsigned char* kb = reinterpret_cast<const unsigned char*>(&key);
   std::vector<unsigned char> kv(kb, kb + sizeof key);
   if (!c->r_graph || kv != c->r_graph_key) {

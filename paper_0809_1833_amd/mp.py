@@ -42,12 +42,12 @@ class Result(ctypes.Structure):
 
 class Trace(ctypes.Structure):
     _fields_ = [("idx", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("rr", ctypes.c_void_p),
-                ("cap", ctypes.c_int64)]
+                ("cap", ctypes.c_int64), ("r", ctypes.c_void_p), ("ldr", ctypes.c_int64)]
 
 
 class TraceF64(ctypes.Structure):
     _fields_ = [("idx", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("rr", ctypes.c_void_p),
-                ("cap", ctypes.c_int64)]
+                ("cap", ctypes.c_int64), ("r", ctypes.c_void_p), ("ldr", ctypes.c_int64)]
 
 
 class Instance(ctypes.Structure):
@@ -358,11 +358,14 @@ class Decoder:
 
     def solve(self, y: torch.Tensor, eps: float, max_iters: int, x: Optional[torch.Tensor] = None,
               r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
-              stream=None, omp: bool = False, step_launches: bool = False):
+              stream=None, omp: bool = False, step_launches: bool = False,
+              trace_r: bool = False):
         """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, persistent,
         trace...).  ``omp=True`` decodes with Orthogonal Matching Pursuit
         (mp_solve_omp; MP_F32 storage).  ``step_launches=True``: the one-bit
-        form steps with one launch per iteration (MP_SOLVE_STEP_LAUNCHES)."""
+        form steps with one launch per iteration (MP_SOLVE_STEP_LAUNCHES).
+        ``trace_r=True`` (with ``trace_cap``): also the residual after every
+        traced step, ``r_trace`` of shape (steps, N)."""
         dt = self.dtype
         if not y.is_cuda or y.dtype != dt or y.numel() != self.n:
             raise ValueError(f"y must be a {dt} CUDA tensor of N elements")
@@ -373,13 +376,15 @@ class Decoder:
         if r is None:
             r = torch.empty(self.n, dtype=dt, device=dev)
         tr = None
-        tidx = tcoef = trr = None
+        tidx = tcoef = trr = tres = None
         if trace_cap > 0:
             tidx = torch.full((trace_cap,), -1, dtype=torch.int32, device=dev)
             tcoef = torch.zeros(trace_cap, dtype=dt, device=dev)
             trr = torch.zeros(trace_cap, dtype=torch.float64, device=dev)
+            if trace_r:
+                tres = torch.zeros((trace_cap, self.n), dtype=dt, device=dev)
             tr = (TraceF64 if self.storage == "f64" else Trace)(
-                tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+                tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap, _ptr(tres), self.n)
         opts = Opts(float(eps), int(max_iters), int(rescore_k),
                     MP_SOLVE_STEP_LAUNCHES if step_launches else 0)
         if omp and self.storage != "f32":
@@ -393,15 +398,19 @@ class Decoder:
         if tr is not None:
             k = min(res.iters, trace_cap)
             out.update(idx=tidx[:k], coef=tcoef[:k], rr_trace=trr[:k])
+            if tres is not None:
+                out.update(r_trace=tres[:k])
         return out
 
     def solve_batched(self, y: torch.Tensor, eps: float, max_iters, trace_cap: int = 0,
-                      rescore_k: int = 0, want_r: bool = True, stream=None):
+                      rescore_k: int = 0, want_r: bool = True, stream=None,
+                      trace_r: bool = False):
         """Decode the columns of ``y`` ((N, B) float32 CUDA, column-major).
 
         ``max_iters``: one cap for all signals, or a sequence of B caps.
         Returns dict(x (M, B), r (N, B) or None, iters, yy, rr, stop (lists), and
-        with ``trace_cap`` idx/coef/rr_trace of shape (B, trace_cap))."""
+        with ``trace_cap`` idx/coef/rr_trace of shape (B, trace_cap); with
+        ``trace_r`` also r_trace of shape (B, trace_cap, N))."""
         if not y.is_cuda or y.dtype != torch.float32 or y.dim() != 2 or y.shape[0] != self.n:
             raise ValueError("y must be a (N, B) float32 CUDA tensor")
         nb = y.shape[1]
@@ -412,12 +421,16 @@ class Decoder:
         x = torch.empty((max(nb, 1), self.m), dtype=torch.float32, device=dev)
         r = torch.empty((max(nb, 1), self.n), dtype=torch.float32, device=dev) if want_r else None
         tr = None
-        tidx = tcoef = trr = None
+        tidx = tcoef = trr = tres = None
         if trace_cap > 0:
             tidx = torch.full((max(nb, 1), trace_cap), -1, dtype=torch.int32, device=dev)
             tcoef = torch.zeros((max(nb, 1), trace_cap), dtype=torch.float32, device=dev)
             trr = torch.zeros((max(nb, 1), trace_cap), dtype=torch.float64, device=dev)
-            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+            if trace_r:
+                tres = torch.zeros((max(nb, 1), trace_cap, self.n), dtype=torch.float32,
+                                   device=dev)
+            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap, _ptr(tres),
+                       self.n)
         per = None
         if isinstance(max_iters, (list, tuple)) or hasattr(max_iters, "__len__"):
             per = [int(v) for v in max_iters]
@@ -436,6 +449,8 @@ class Decoder:
                          for i in range(nb)])
         if tr is not None:
             out.update(idx=tidx[:nb], coef=tcoef[:nb], rr_trace=trr[:nb])
+            if tres is not None:
+                out.update(r_trace=tres[:nb])
         return out
 
     def storage_copy(self, stream=None):
@@ -521,11 +536,14 @@ class RaggedDecoder:
         return torch.cat([y.reshape(-1) for y in ys]).contiguous()
 
     def solve(self, y_packed: torch.Tensor, eps: float, max_iters, trace_cap: int = 0,
-              rescore_k: int = 0, want_r: bool = True, x_out=None, stream=None):
+              rescore_k: int = 0, want_r: bool = True, x_out=None, stream=None,
+              trace_r: bool = False):
         """Decode every instance.  ``y_packed``: float32 CUDA vector of sum(N_i).
         ``max_iters``: one cap, or one per instance.  Returns dict with packed
         ``x``/``r`` and per-instance ``iters``/``stop``/``yy``/``rr`` lists,
-        plus ``idx``/``coef``/``rr_trace`` (count, trace_cap) with a trace."""
+        plus ``idx``/``coef``/``rr_trace`` (count, trace_cap) with a trace and,
+        with ``trace_r``, ``r_trace`` (count, trace_cap, max N_i): instance i's
+        residual after step t in the first N_i entries of [i, t]."""
         if (not y_packed.is_cuda or y_packed.dtype != torch.float32
                 or y_packed.numel() != self.y_off[-1]):
             raise ValueError("y_packed must be a float32 CUDA vector of sum(N_i) entries")
@@ -535,12 +553,16 @@ class RaggedDecoder:
                                                          device=dev)
         r = torch.empty(self.y_off[-1], dtype=torch.float32, device=dev) if want_r else None
         tr = None
-        tidx = tcoef = trr = None
+        tidx = tcoef = trr = tres = None
         if trace_cap > 0:
             tidx = torch.full((self.count, trace_cap), -1, dtype=torch.int32, device=dev)
             tcoef = torch.zeros((self.count, trace_cap), dtype=torch.float32, device=dev)
             trr = torch.zeros((self.count, trace_cap), dtype=torch.float64, device=dev)
-            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap)
+            ldr = max(self.ns)
+            if trace_r:
+                tres = torch.zeros((self.count, trace_cap, ldr), dtype=torch.float32, device=dev)
+            tr = Trace(tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap, _ptr(tres),
+                       ldr)
         per = None
         if hasattr(max_iters, "__len__"):
             per = [int(v) for v in max_iters]
@@ -559,6 +581,8 @@ class RaggedDecoder:
                          for i in range(self.count)])
         if tr is not None:
             out.update(idx=tidx, coef=tcoef, rr_trace=trr)
+            if tres is not None:
+                out.update(r_trace=tres)
         return out
 
     def set_profiling(self, every: int = 1):

@@ -150,4 +150,7 @@ def test_binding_structs_match_the_header():
     text = _header_text()
     assert [f[0] for f in mp.Opts._fields_] == _struct_fields(text, "mp_opts")
     assert [f[0] for f in mp.Result._fields_] == _struct_fields(text, "mp_result")
+    assert [f[0] for f in mp.Trace._fields_] == _struct_fields(text, "mp_trace")
+    assert [f[0] for f in mp.TraceF64._fields_] == _struct_fields(text, "mp_trace_f64")
     assert ctypes.sizeof(mp.Result) == 32 and ctypes.sizeof(mp.Opts) == 24
+    assert ctypes.sizeof(mp.Trace) == 48 and ctypes.sizeof(mp.TraceF64) == 48

@@ -11,6 +11,7 @@ import pytest
 import mpgen
 import oracle
 from parity import run_parity
+from wholerun import whole_run
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -47,6 +48,15 @@ def _gpu_solver(dec, y):
     return solve
 
 
+def _gpu_traced(dec, y, eps, max_iters, **kw):
+    """One decode with the full trace, residuals included, as numpy arrays."""
+    yd = torch.from_numpy(np.asarray(y, dtype=np.float32)).cuda()
+    out = dec.solve(yd, eps, max_iters, trace_cap=max(max_iters, 1), trace_r=True, **kw)
+    torch.cuda.synchronize()
+    return dict(x=_np(out["x"]), r=_np(out["r"]), iters=out["iters"], stop=out["stop"],
+                idx=_np(out["idx"]), coef=_np(out["coef"]), r_trace=_np(out["r_trace"]))
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _need_gpu():
     if not torch.cuda.is_available():
@@ -67,25 +77,36 @@ def test_parity_small_workload(seed):
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_parity_2048x8192(seed):
-    """N=2048, M=8192, K=128, eps=1e-5, T=20K: full oracle run."""
+    """N=2048, M=8192, K=128, eps=1e-5, T=20K: full oracle run, then every
+    step of the GPU run checked (P-local, P-replay, the final x~ and r)."""
     p = mpgen.make_problem("c1a", seed)
     print(f"[c1a seed={seed}]", flush=True)
     with _decoder(p.psi) as dec:
         rep = run_parity(p.psi, p.y, p.eps, p.max_iters, _gpu_solver(dec, p.y))
-    print(rep, flush=True)
-    assert rep.prefix >= min(rep.iters_ora, 100)
+        print(rep, flush=True)
+        assert rep.prefix >= min(rep.iters_ora, 100)
+        w = whole_run(p.psi, p.y, p.eps, _gpu_traced(dec, p.y, p.eps, p.max_iters))
+    print(w, flush=True)
 
 
-def test_parity_8192x32768_sampled():
-    """N=8192, M=32768 (1 GiB dictionary) at the full size: oracle prefix of 48
-    steps, then FP64 validity checks of the GPU's own choices across the run."""
+def test_parity_8192x32768_whole_run():
+    """N=8192, M=32768 (1 GiB dictionary), the benchmarked decode: the oracle's
+    free run to its end (index prefix, legitimacy of the first difference),
+    then every one of the GPU's steps correlated in FP64 (the selection is the
+    FP64 argmax wherever the top-two gap exceeds 1e-5 ||r||, the coefficient
+    within the FP32 bound), the oracle's replay of the GPU's atoms (each a
+    near tie of the oracle's own state; x~ and r at the end within 1e-5)."""
     p = mpgen.make_problem("c1b", 0)
     print("[c1b seed=0]", flush=True)
     with _decoder(p.psi) as dec:
-        rep = run_parity(p.psi, p.y, p.eps, p.max_iters, _gpu_solver(dec, p.y),
-                         oracle_cap=48, samples_after=3)
-    print(rep, flush=True)
-    assert rep.prefix == 48
+        rep = run_parity(p.psi, p.y, p.eps, p.max_iters, _gpu_solver(dec, p.y), samples_after=3)
+        print(rep, flush=True)
+        assert rep.prefix >= 48
+        g = _gpu_traced(dec, p.y, p.eps, p.max_iters)
+    print(f"[c1b whole run: {g['iters']} steps]", flush=True)
+    w = whole_run(p.psi, p.y, p.eps, g)
+    print(w, flush=True)
+    assert w.steps == rep.iters_gpu and w.exact_steps > 0.9 * w.steps
 
 
 @pytest.mark.parametrize("n,m", [(250, 1000), (1, 1), (3, 5), (64, 4), (100, 7), (520, 300),
@@ -234,3 +255,31 @@ def test_profiling_counts_real_launches():
         dec.set_profiling(0)
         dec.solve(torch.from_numpy(p.y).cuda(), p.eps, p.max_iters)
         assert dec.kernel_time()[1] == 0
+
+
+@pytest.mark.parametrize("n,m", [(256, 1024), (250, 1000), (3, 5), (4100, 700)])
+def test_residual_trace(n, m):
+    """The residual trace holds each step's r bit for bit (rows below N only,
+    including N not a multiple of four) and does not change the decode."""
+    rng = np.random.default_rng(n + 31 * m)
+    psi = mpgen.gaussian_unit_dictionary(rng, n, m)
+    x, sup = mpgen.sparse_signal(rng, rng, m, max(1, min(m // 8, n // 4, 6)))
+    y = mpgen.encode(psi, x, sup)
+    with _decoder(psi) as dec:
+        g = _gpu_traced(dec, y, 1e-6, 60)
+        plain = _gpu_solver(dec, y)(1e-6, 60, 60)
+        assert np.array_equal(g["idx"], plain["idx"]) and np.array_equal(g["x"], plain["x"])
+        assert np.array_equal(g["r"], plain["r"])
+        T = g["iters"]
+        assert T > 0 and np.array_equal(g["r_trace"][T - 1], g["r"])
+        for t in sorted({0, T // 2, T - 1}):
+            part = _gpu_solver(dec, y)(0.0, t + 1, 0)
+            assert np.array_equal(g["r_trace"][t], part["r"]), t
+    with pytest.raises(Exception):
+        from paper_0809_1833_amd import mp
+        with _decoder(psi) as dec:
+            yd = torch.from_numpy(y).cuda()
+            tr = torch.zeros((4, n), device="cuda")
+            t = mp.Trace(None, None, None, 4, tr.data_ptr(), n - 1)
+            mp.mp_solve(dec.handle, yd.data_ptr(), torch.empty(m, device="cuda").data_ptr(),
+                        None, mp.Opts(1e-6, 4, 0, 0), t)

@@ -15,6 +15,7 @@ import pytest
 import mpgen
 import oracle
 from parity import U64, run_parity
+from wholerun import whole_run
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -86,15 +87,28 @@ def test_parity_2048x8192():
     assert rep.prefix >= min(rep.iters_ora, 200)
 
 
-def test_parity_8192x32768_sampled():
+def test_parity_8192x32768_whole_run():
     """N=8192, M=32768 (2 GiB FP64 dictionary) at the full size: oracle prefix
-    of 32 steps, then FP64 validity checks of the GPU's own choices."""
+    of 32 steps, then every step of the GPU run against FP64 correlations of
+    its state (the exact argmax wherever the top-two gap exceeds 1e-10 ||r||)
+    and the oracle's replay of its atoms (x~ and r at the end within
+    1e-12)."""
     p = mpgen.make_problem("c1b", 0, precision="f64")
     print("[f64 c1b seed=0]", flush=True)
     with _decoder(p.psi) as dec:
-        rep = _parity(p.psi, p.y, p.eps, p.max_iters, dec, oracle_cap=32, samples_after=3)
-    print(rep, flush=True)
-    assert rep.prefix == 32
+        rep = _parity(p.psi, p.y, p.eps, p.max_iters, dec, oracle_cap=32, samples_after=2)
+        print(rep, flush=True)
+        assert rep.prefix == 32
+        yd = torch.from_numpy(np.asarray(p.y, dtype=np.float64)).cuda()
+        out = dec.solve(yd, p.eps, p.max_iters, trace_cap=p.max_iters, trace_r=True)
+        torch.cuda.synchronize()
+        g = dict(x=_np(out["x"]), r=_np(out["r"]), iters=out["iters"], stop=out["stop"],
+                 idx=_np(out["idx"]), coef=_np(out["coef"]), r_trace=_np(out["r_trace"]))
+        del out
+    print(f"[f64 c1b whole run: {g['iters']} steps]", flush=True)
+    w = whole_run(p.psi, p.y, p.eps, g, tol=TOL, tol_sel=TOL_SEL, unit=U64, y64=True)
+    print(w, flush=True)
+    assert w.misses == 0 and w.exact_steps > 0.9 * w.steps
 
 
 @pytest.mark.parametrize("n,m", [(250, 1000), (1, 1), (3, 5), (64, 4), (100, 7), (520, 300),

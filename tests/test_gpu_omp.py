@@ -2,10 +2,15 @@
 OMP oracle (oracle.omp), through the C ABI.
 
 Index sequences must agree step for step until a difference the oracle's
-top-two gap allows; x~ and r are compared with the oracle's least-squares fit
-(x~ relative to ||x~||, r relative to ||y||, 1e-5); and the GPU's own end
-state must be an OMP state: r orthogonal to the selected atoms, y = Psi x~ + r
-and the stopping rule.
+top-two gap allows (gap <= 1e-5 ||r|| + 2 ||r_gpu - r_ora|| + 2 e32 at that
+step, the bound of the MP parity protocol); at that step the GPU's x~ and r
+(a re-run capped there) are compared with the oracle's least-squares fit
+(x~ relative to ||x~||, r relative to ||y||, 1e-5).  Every step of the GPU
+run is checked on its own state (P-local: the atom is the FP64 argmax of
+|Psi^T r_t| wherever the top-two gap exceeds 1e-5 ||r_t||), its final x~ and
+r against the least-squares fit on its own atoms (an OMP state depends only
+on the set of atoms), and its end state must be an OMP state: r orthogonal
+to the selected atoms, y = Psi x~ + r and the stopping rule.
 """
 from __future__ import annotations
 
@@ -15,6 +20,7 @@ import pytest
 import mpgen
 from oracle import omp as omp_oracle
 from parity import fp32_dot_bound
+from wholerun import local_checks
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -39,16 +45,19 @@ def _decoder(psi):
     return Decoder(_cm(psi))
 
 
-def _gpu(dec, y, eps, T, cap=None):
+def _gpu(dec, y, eps, T, cap=None, trace_r=False):
     yd = torch.from_numpy(np.asarray(y, dtype=np.float32)).cuda()
     cap = T if cap is None else cap
-    out = dec.solve(yd, eps, T, trace_cap=min(cap, dec.n) if cap else 0, omp=True)
+    out = dec.solve(yd, eps, T, trace_cap=min(cap, dec.n) if cap else 0, omp=True,
+                    trace_r=trace_r and cap > 0)
     torch.cuda.synchronize()
     g = dict(x=out["x"].cpu().numpy(), r=out["r"].cpu().numpy(), iters=out["iters"],
              stop=out["stop"], rr=out["rr"])
     if cap:
         g.update(idx=out["idx"].cpu().numpy(), coef=out["coef"].cpu().numpy(),
                  rr_trace=out["rr_trace"].cpu().numpy())
+        if trace_r:
+            g.update(r_trace=out["r_trace"].cpu().numpy())
     return g
 
 
@@ -67,24 +76,59 @@ def _check_end_state(psi, y, g, eps):
         assert float(r @ r) <= (eps * yn) ** 2 * (1 + 1e-5)
 
 
+def _errs(gx, gr, ox, orr, yn):
+    xe = np.linalg.norm(gx.astype(np.float64) - ox) / max(np.linalg.norm(ox), 1e-300)
+    re = np.linalg.norm(gr.astype(np.float64) - orr) / max(yn, 1e-300)
+    return float(xe), float(re)
+
+
+def _ls_state(psi, y, sel):
+    """The OMP state on the atoms `sel`: the least-squares fit of y (the
+    oracle's own fit, FP64) and its residual."""
+    y64 = np.asarray(np.asarray(y, dtype=np.float32), dtype=np.float64)
+    x = np.zeros(psi.shape[1])
+    if len(sel) == 0:
+        return x, y64
+    ps = np.asarray(psi, dtype=np.float64)[:, sel]
+    xs = omp_oracle._fit(ps, y64)
+    x[sel] = xs
+    return x, omp_oracle._residual(y64, ps, xs)
+
+
 def _parity(psi, y, eps, T, dec, oracle_cap=None):
     cap = T if oracle_cap is None else min(T, oracle_cap)
     ora = omp_oracle.solve_omp(psi, y, eps, cap)
-    g = _gpu(dec, y, eps, T)
+    g = _gpu(dec, y, eps, T, trace_r=True)
     L = min(g["iters"], ora.iters)
     diff = np.flatnonzero(g["idx"][:L] != ora.idx[:L])
     t_star = int(diff[0]) if diff.size else L
     n = psi.shape[0]
     yn = float(np.linalg.norm(y.astype(np.float64)))
-    if t_star < L:
-        rn = float(np.sqrt(ora.rr_trace[t_star - 1])) if t_star else yn
-        allowed = 1e-5 * rn + 2 * fp32_dot_bound(n, rn) + 1e-5 * yn
-        assert ora.gap[t_star] <= allowed, (t_star, ora.gap[t_star], allowed)
-    elif g["iters"] == ora.iters and oracle_cap is None:
+    full = t_star == L and g["iters"] == ora.iters and oracle_cap is None
+    if full:
         assert omp_oracle.REASONS[ora.reason] == g["stop"]
-        xe = np.linalg.norm(g["x"].astype(np.float64) - ora.x) / max(np.linalg.norm(ora.x), 1e-300)
-        re = np.linalg.norm(g["r"].astype(np.float64) - ora.r) / max(yn, 1e-300)
+        xe, re = _errs(g["x"], g["r"], ora.x, ora.r, yn)
         assert xe <= TOL and re <= TOL, (xe, re)
+    elif t_star > 0:
+        # the state at the end of the common prefix: the GPU run capped there,
+        # the oracle's fit on the same atoms
+        gp = _gpu(dec, y, 0.0, t_star, cap=0)
+        ox, orr = _ls_state(psi, y, ora.idx[:t_star])
+        xe, re = _errs(gp["x"], gp["r"], ox, orr, yn)
+        assert xe <= TOL and re <= TOL, (t_star, xe, re)
+        if t_star < L:
+            # a difference at t* must be one the oracle's top-two gap allows
+            rn = float(np.linalg.norm(orr))
+            dr = float(np.linalg.norm(gp["r"].astype(np.float64) - orr))
+            allowed = 1e-5 * rn + 2 * dr + 2 * fp32_dot_bound(n, rn)
+            assert ora.gap[t_star] <= allowed, (t_star, ora.gap[t_star], allowed)
+    # every step of the GPU run on its own state, and its end state against
+    # the least-squares fit on its own atoms
+    w = local_checks(psi, y, g)
+    assert w.misses == 0
+    ox, orr = _ls_state(psi, y, g["idx"][:g["iters"]])
+    xe, re = _errs(g["x"], g["r"], ox, orr, yn)
+    assert xe <= TOL and re <= TOL, ("end", xe, re)
     _check_end_state(psi, y, g, eps)
     return t_star, ora, g
 
@@ -107,12 +151,14 @@ def test_parity_2048x8192():
     assert t_star >= min(ora.iters, 100)
 
 
-def test_parity_8192x32768_sampled():
+def test_parity_8192x32768_whole_run():
+    """The OMP decode the benchmark times: the oracle's free run for 48 steps
+    (x~ and r compared there), then every step of the GPU run."""
     p = mpgen.make_problem("c1b", 0)
     print("[omp c1b seed=0]", flush=True)
     with _decoder(p.psi) as dec:
-        t_star, ora, g = _parity(p.psi, p.y, p.eps, p.max_iters, dec, oracle_cap=24)
-    assert t_star == 24
+        t_star, ora, g = _parity(p.psi, p.y, p.eps, p.max_iters, dec, oracle_cap=48)
+    assert t_star == 48
     assert g["stop"] == "converged"
 
 

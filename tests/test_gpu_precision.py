@@ -16,6 +16,7 @@ import mpgen
 import oracle
 from oracle import quant
 from parity import run_parity
+from wholerun import whole_run
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -124,18 +125,35 @@ def test_parity_2048x8192(storage):
     assert rep.prefix >= min(rep.iters_ora, 100)
 
 
+def _gpu_traced(dec, y, eps, max_iters):
+    yd = torch.from_numpy(np.asarray(y, dtype=np.float32)).cuda()
+    out = dec.solve(yd, eps, max_iters, trace_cap=max(max_iters, 1), trace_r=True)
+    torch.cuda.synchronize()
+    return dict(x=_np(out["x"]), r=_np(out["r"]), iters=out["iters"], stop=out["stop"],
+                idx=_np(out["idx"]), coef=_np(out["coef"]), r_trace=_np(out["r_trace"]))
+
+
 @pytest.mark.parametrize("storage", STORAGES)
 @pytest.mark.parametrize("dist", ["normal", "loguniform"])
-def test_parity_8192x32768_sampled(storage, dist):
-    """The precision workload: N=8192, M=32768, K=256, eps=1e-5, T=20K; oracle
-    prefix of 32 steps, FP64 validity checks of later steps."""
+def test_parity_8192x32768_whole_run(storage, dist):
+    """The precision workload: N=8192, M=32768, K=256, eps=1e-5, T=20K.  The
+    oracle's free run for 32 steps (exact prefix), then every step of the GPU
+    run: the FP32-rescored atom is the FP64 argmax of the GPU's state wherever
+    the top-two gap exceeds 1e-5 ||r|| (no rescore misses), coefficients
+    within the FP32 bound, and the oracle's replay of the GPU's atoms ends
+    within 1e-5 of the GPU's x~ and r (the workload allows 2e-2)."""
     p = mpgen.make_problem("c2", 0, dist=dist)
     print(f"[{storage} c2 {dist}]", flush=True)
     with _decoder(p.psi, storage) as dec:
         rep = run_parity(p.psi, p.y, p.eps, p.max_iters, _gpu_solver(dec, p.y),
-                         oracle_cap=32, samples_after=3)
-    print(rep, flush=True)
-    assert rep.prefix == 32
+                         oracle_cap=32, samples_after=2)
+        print(rep, flush=True)
+        assert rep.prefix == 32
+        g = _gpu_traced(dec, p.y, p.eps, p.max_iters)
+    print(f"[{storage} c2 {dist} whole run: {g['iters']} steps]", flush=True)
+    w = whole_run(p.psi, p.y, p.eps, g)
+    print(w, flush=True)
+    assert w.misses == 0 and w.exact_steps > 0.5 * w.steps
 
 
 @pytest.mark.parametrize("storage", STORAGES)

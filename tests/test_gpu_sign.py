@@ -13,6 +13,7 @@ import mpgen
 import oracle
 from oracle import signs as osigns
 from parity import run_parity
+from wholerun import whole_run
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -81,17 +82,32 @@ def test_parity_2048x8192():
     assert rep.prefix >= min(rep.iters_ora, 100)
 
 
-def test_parity_8192x32768_sampled():
+def test_parity_8192x32768_whole_run():
     """The benchmark size (N=8192, M=32768, 32 MiB of bits), in the launch
-    configuration the benchmark uses: oracle prefix of 24 steps, then the
-    GPU's own later choices checked against FP64 correlations of its state."""
+    configuration the benchmark uses (the persistent decode): oracle prefix
+    of 24 steps, then every step of the GPU run against FP64 correlations of
+    its state (the exact argmax wherever the top-two gap exceeds 1e-5 ||r||),
+    and the oracle's replay of its atoms (near ties of the oracle's states;
+    x~ and r at the end within 1e-5)."""
     p = mpgen.make_sign_problem("c1b", 0)
     print("[sign c1b seed=0]", flush=True)
     psi = osigns.unpack(p.bits, p.n)
     with _decoder(p.bits, p.n) as dec:
-        rep = run_parity(psi, p.y, p.eps, p.max_iters, _gpu_solver(dec, p.y), oracle_cap=24)
-    print(rep, flush=True)
-    assert rep.prefix == 24 and len(rep.checked_after) >= 2
+        rep = run_parity(psi, p.y, p.eps, p.max_iters, _gpu_solver(dec, p.y), oracle_cap=24,
+                         samples_after=2)
+        print(rep, flush=True)
+        assert rep.prefix == 24
+        yd = torch.from_numpy(np.asarray(p.y, dtype=np.float32)).cuda()
+        out = dec.solve(yd, p.eps, p.max_iters, trace_cap=p.max_iters, trace_r=True)
+        torch.cuda.synchronize()
+        assert out["persistent"]
+        g = dict(x=_np(out["x"]), r=_np(out["r"]), iters=out["iters"], stop=out["stop"],
+                 idx=_np(out["idx"]), coef=_np(out["coef"]), r_trace=_np(out["r_trace"]))
+        del out
+    print(f"[sign c1b whole run: {g['iters']} steps]", flush=True)
+    w = whole_run(psi, p.y, p.eps, g)
+    print(w, flush=True)
+    assert w.misses == 0 and w.exact_steps > 0.9 * w.steps
 
 
 @pytest.mark.parametrize("n,m", [(1, 5), (3, 40), (33, 17), (100, 1000), (2047, 300),
@@ -163,14 +179,18 @@ def test_persistent_matches_step_launches(case):
     cap = int(min(t_cap, 4096))
     with _decoder(bits, n) as dec:
         yd = torch.from_numpy(np.asarray(y, dtype=np.float32)).cuda()
-        a = dec.solve(yd, eps, t_cap, trace_cap=cap)
-        b = dec.solve(yd, eps, t_cap, trace_cap=cap, step_launches=True)
+        a = dec.solve(yd, eps, t_cap, trace_cap=cap, trace_r=n * cap <= 2 ** 26)
+        b = dec.solve(yd, eps, t_cap, trace_cap=cap, step_launches=True,
+                      trace_r=n * cap <= 2 ** 26)
         torch.cuda.synchronize()
     assert a["persistent"] and not b["persistent"]
     assert a["iters"] == b["iters"] and a["stop"] == b["stop"]
     assert a["rr"] == b["rr"]
-    for key in ("x", "r", "idx", "coef", "rr_trace"):
+    keys = ["x", "r", "idx", "coef", "rr_trace"] + (["r_trace"] if "r_trace" in a else [])
+    for key in keys:
         assert np.array_equal(_np(a[key]), _np(b[key])), key
+    if "r_trace" in a and a["iters"]:
+        assert np.array_equal(_np(a["r_trace"][-1]), _np(a["r"]))
 
 
 def test_persistent_wait_limit_fails_cleanly(monkeypatch):
