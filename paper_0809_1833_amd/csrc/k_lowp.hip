@@ -138,7 +138,6 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   __shared__ uint64_t cand[kTopK];
   __shared__ uint64_t rescored[kTopK];
   __shared__ float chain_b[kTopK][kWave];
-  __shared__ uint64_t kred[kLpWaves];
   __shared__ double dred[kLpWaves];
   __shared__ int s_done;
   constexpr int CC = kLpColsPerWave<S>;
