@@ -269,13 +269,15 @@ mp_status mp_solve_f64(mp_ctx* ctx, const double* y, double* x, double* r, const
  * N/8 bytes per column instead of 4N.  Where the device can keep one
  * workgroup per compute unit resident with its share of the bits in LDS
  * (the share at most 150 KB, e.g. N = 8192 with M up to 32768 on 256 CUs),
- * mp_solve runs the whole decode as one cooperative launch that keeps the
+ * mp_solve runs the whole decode as one persistent launch that keeps the
  * bits on chip and exchanges each step's candidates between workgroups
  * through device memory; otherwise, or with MP_SOLVE_STEP_LAUNCHES, one
- * launch per step.  Both give the same results bit for bit.  A wait between
- * the persistent launch's workgroups that exceeds its poll limit (2^22, or
- * the positive integer in the environment variable MP_SIGN_SPIN_LIMIT, read
- * at each decode) ends the decode with MP_EDEVICE.  The context has
+ * launch per step.  Both give the same results bit for bit.  The persistent
+ * launch needs every workgroup resident at once: run it on a device no other
+ * kernel is holding.  A wait between its workgroups that exceeds the poll
+ * limit (2^22, or the positive integer in the environment variable
+ * MP_SIGN_SPIN_LIMIT, read at each decode) ends the decode with MP_EDEVICE
+ * (r then holds each workgroup's rows as of its last step, x~ is partial).  The context has
  * storage MP_SIGN1; mp_solve_batched and mp_solve_omp return MP_EINVAL for
  * it.
  *

@@ -322,8 +322,8 @@ __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form: the whole decode in one cooperative launch, one workgroup
-// per compute unit.  Each workgroup copies its columns' bits into LDS once
+// Persistent form: the whole decode in one launch, one workgroup per compute
+// unit.  Each workgroup copies its columns' bits into LDS once
 // (128 KB for 128 columns of N = 8192: the 32 MiB dictionary stays on chip
 // across the 256 CUs for the whole decode), keeps its columns' c in
 // registers and its rows of r (at most 64 kSignPersistRows) in registers of
@@ -346,12 +346,18 @@ __global__ __launch_bounds__(kSignThreads) void k_mp_step_sign(
 // contents is done with them.  The epoch, new for every decode, keeps a
 // word left by an earlier decode from matching.
 //
-// Every wait ends: the launch is cooperative (all workgroups resident, or the
-// launch fails and the caller steps with k_mp_step_sign); every workgroup
-// runs the same steps and stops at the same one (the decision is taken from
-// the same gathered values); a poll that exceeds `spin_limit` tries marks the
-// run failed (kStopInternal) and its workgroup leaves, after which every
-// other workgroup's next poll times out too.
+// Every wait ends: the host launches this form only where the occupancy query
+// shows every workgroup resident at once (one per CU, grid <= CUs), so all
+// of them run together on an otherwise idle device; every workgroup runs the
+// same steps and stops at the same one (the decision is taken from the same
+// gathered values); and a poll that exceeds `spin_limit` tries marks the run
+// failed (the sticky DevState::fail word) and its workgroup writes back its
+// rows of r and leaves, after which every other workgroup's next poll times
+// out too.  So a launch whose workgroups are not all resident (another
+// kernel holding CUs) ends with MP_EDEVICE rather than waiting for ever.
+// The launch is an ordinary one: a cooperative launch would add nothing the
+// occupancy check does not give, and profilers have crashed at process exit
+// after one.
 constexpr int kSignPersistRows = 4;            // rows of r per lane of wave 0
 constexpr int kSignPersistLds = 150 * 1024;    // dynamic LDS for the bits, at most
 
@@ -444,12 +450,13 @@ __global__ __launch_bounds__(kSignThreads) void k_sign_persist(
       }
       __syncthreads();
       if (s_fail) {
+        // The failure is sticky: workgroup 0 may still store a regular stop
+        // reason after this, so the host reads the fail word first.
         if (threadIdx.x == 0) {
-          __hip_atomic_store(&st->reason, kStopInternal, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+          (void)__hip_atomic_fetch_or(&st->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        return;
+        break;  // rows of r as of the last step applied, written back below
       }
       // the stop test for the j - 1 steps taken, then step j's atom
       const double rr = block_sum<kSignThreads>(rrq, dred);
@@ -684,8 +691,7 @@ hipError_t launch_sign_persist(const uint32_t* bits, int64_t ws, int64_t n, int6
   const void* fn = sign_persist_fn(n);
   if (hipError_t e = sign_persist_attr(sign_chunks_per_lane(n) == 1 ? 0 : 1, fn); e != hipSuccess)
     return e;
-  return hipLaunchCooperativeKernel(fn, dim3(g.grid), dim3(kSignThreads), args,
-                                    static_cast<unsigned>(lds), s);
+  return hipLaunchKernel(fn, dim3(g.grid), dim3(kSignThreads), args, lds, s);
 }
 
 hipError_t launch_mp_step_sign(const uint32_t* bits, int64_t ws, int64_t n, int64_t m, int64_t ld,

@@ -287,11 +287,12 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, E
 // reasons mapped to errors.
 mp_status finish_result(mp_ctx* c, mp_result* res) {
   const mp::DevState& d = *c->h_st;
+  if (d.fail)
+    return fail(c, MP_EDEVICE, "a wait of the persistent one-bit decode gave up");
   if (d.reason == mp::kStopNonFinite) return fail(c, MP_ENONFINITE, "y holds NaN or Inf");
   if (d.reason == mp::kStopInternal)
     return fail(c, MP_EDEVICE,
-                "internal error: a selected index fell outside the dictionary, or a wait of "
-                "the persistent one-bit decode gave up");
+                "internal error: a selected index fell outside the dictionary");
   if (res) {
     res->iters = d.t;
     res->yy = d.yy;
@@ -762,15 +763,9 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
     return bail(MP_ENOMEM, "partials");
   if (hipMalloc(&c->sign_rrp, sizeof(double) * 2 * c->geom.grid) != hipSuccess)
     return bail(MP_ENOMEM, "partial norms");
-  // the persistent decode (bits in LDS): one workgroup per CU, all resident,
-  // on a device that launches cooperative kernels
-  {
-    int coop = 0;
-    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
-    c->sign_persist = coop != 0 &&
-                      mp::sign_persist_fits(n, m, c->ld, c->sign_ws, c->geom, c->num_cus) &&
-                      mp::sign_persist_resident(n, c->sign_ws, c->geom, c->num_cus);
-  }
+  // the persistent decode (bits in LDS): one workgroup per CU, all resident
+  c->sign_persist = mp::sign_persist_fits(n, m, c->ld, c->sign_ws, c->geom, c->num_cus) &&
+                    mp::sign_persist_resident(n, c->sign_ws, c->geom, c->num_cus);
   const size_t slot_bytes =
       sizeof(unsigned long long) * mp::kSignSlotWords * 2 * static_cast<size_t>(c->geom.grid);
   if (hipMalloc(&c->sign_slots, slot_bytes) != hipSuccess)

@@ -30,7 +30,9 @@ struct alignas(64) DevState {
   int reason;           // MP_STOP_* or kStopNonFinite
   unsigned arrive;      // OMP selection: workgroups of the launch that have published a key
   int r_sel;            // reduced-precision decode: half of the residual buffer holding r
-  int pad[4];
+  int fail;             // persistent one-bit decode: set (atomic OR) by a workgroup whose
+                        // wait gave up; overrides reason whatever was stored after it
+  int pad[3];
 };
 
 // A candidate packed into one 64-bit key so that "larger key" means larger
