@@ -9,12 +9,24 @@ M=32768 (1 GiB FP32 dictionary), K=512, eps=1e-5, T=20K.
 Prints ONE JSON line.  `value` is MP iterations per second over the timed
 steps; `roofline` is the correlation kernel's algorithmic HBM bandwidth
 (dictionary + residual bytes per launch / mean launch time from HIP events on
-the decode stream) against the 8 TB/s peak; `cpu_baseline` is the FP64
-oracle timed on a bounded sample of the same decode on this host.  The line
-also carries the batched form, the ragged instances, the FP64 decode and the
-OMP decode of the same workload, the decode on the sign-bit Bernoulli
-dictionary of the same sizes, and the Fig. 1 error grid (each skippable
-with --no-batched / --no-ragged / --no-f64 / --no-omp / --no-sign / --no-phase).
+the decode stream) against the 8 TB/s peak and against the read rate a plain
+streaming kernel reaches on the same device; `cpu_baseline` is the FP64
+oracle timed on a bounded sample of the same decode on this host, on every
+core and on one.  The line also carries the reduced-precision forms (BF16 and
+FP8 dictionaries, both value laws, N=8192, M=32768, K=256), the small
+single-signal workloads (N=256 and N=2048, cache-resident), the batched form,
+the ragged instances (FP32 and BF16), the FP64 decode and the OMP decode of
+the same workload, the decode on the sign-bit Bernoulli dictionary of the
+same sizes, and the Fig. 1 error grid (each skippable, see --help).
+
+Errors per result: after the GPU legs, the oracle checks what each leg
+decoded (untimed): every step of a single-signal decode is judged against
+the FP64 correlations of the decode's own state (selections that differ from
+the FP64 argmax where the top-two gap exceeds 1e-5 ||r|| are counted as
+misses; for the reduced-precision forms these are re-scoring misses), the
+oracle replays the decode's atoms in FP64 and x~ and r are compared with the
+replay, and the index sequence is compared with the oracle's own free run
+over a sample.
 """
 from __future__ import annotations
 
@@ -22,8 +34,11 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -259,20 +274,198 @@ def bench_phase(seed: int):
                           "sigma1.0_rho0.05": round(float(E[0][-1]), 4)}}
 
 
-def cpu_baseline(p, budget_s=15.0):
+def host_cpu():
+    """(CPU model name, cores this process may run on) of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
+def stream_ceiling():
+    """Read rate (GB/s) of a plain streaming kernel on this device: the probe
+    built beside the library, each workgroup reading one contiguous chunk of a
+    1 GiB buffer with 16-byte non-temporal loads (mean of 10 launches, HIP
+    events).  None when the probe is not built or fails."""
+    exe = os.path.join(ROOT, "paper_0809_1833_amd", "probe", "stream_probe")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe, "chunk", "1024", "10"], capture_output=True, text=True,
+                             timeout=120)
+    except (OSError, subprocess.TimeoutExpired):
+        return None
+    if out.returncode != 0:
+        return None
+    for line in out.stdout.splitlines():
+        try:
+            return float(json.loads(line)["gbps"])
+        except (ValueError, KeyError):
+            continue
+    return None
+
+
+def hbm_roofline(kernel, bytes_per_launch, avg_ms, launches, traffic=None, ceiling=None,
+                 bound="hbm"):
+    """Roofline record of a streaming kernel: algorithmic bytes per launch over
+    its mean launch time, against the 8 TB/s peak and the streaming probe's
+    measured ceiling."""
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
+    d = {"bound": bound, "kernel": kernel,
+         "achieved": round(achieved, 2) if achieved else None,
+         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+         "traffic": traffic, "bytes_per_launch": bytes_per_launch,
+         "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches}
+    if ceiling and achieved:
+        d["stream_ceiling_gbps"] = round(ceiling, 1)
+        d["frac_of_stream_ceiling"] = round(achieved / ceiling, 4)
+    return d
+
+
+def traced_decode(dec, y, p, **kw):
+    """One untimed decode with its whole per-step record (atoms, coefficients,
+    the residual after every step), as numpy arrays for the oracle's checks."""
+    import torch
+    out = dec.solve(y, p.eps, p.max_iters, trace_cap=max(p.max_iters, 1), trace_r=True, **kw)
+    torch.cuda.synchronize()
+    g = {"iters": out["iters"], "stop": out["stop"], "yy": out["yy"], "rr": out["rr"]}
+    for k in ("x", "r", "idx", "coef", "r_trace"):
+        g[k] = out[k].cpu().numpy() if k in out else None
+    return g
+
+
+def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, rescore_k=0):
+    """Time `steps` decodes of problem p with the given dictionary storage,
+    then decode it once more with the whole per-step record.  Returns (the
+    leg's record, the decode to check against the oracle)."""
+    import torch
+
+    from paper_0809_1833_amd.mp import Decoder
+
+    n, m = p.n, p.m
+    psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
+    y = torch.from_numpy(p.y).cuda()
+    with Decoder(psi, storage=storage) as dec:
+        del psi
+        x = torch.empty(m, dtype=torch.float32, device="cuda")
+        r = torch.empty(n, dtype=torch.float32, device="cuda")
+        iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
+                                                      x, r, rescore_k=rescore_k)
+        g = traced_decode(dec, y, p, rescore_k=rescore_k)
+    leg = {"workload": workload, "storage": storage,
+           "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
+           "us_per_iter": round(dt / max(iters, 1) * 1e6, 3),
+           "iters_per_decode": iters // max(steps, 1), "stop": sorted(stops),
+           "roofline": hbm_roofline(KERNEL[storage], step_bytes(n, m, storage), avg_ms, kt_n,
+                                    traffic_from_counters(n, m, storage), ceiling)}
+    return leg, g
+
+
+# ---- the oracle's side: baseline timing and the checks of each decode -------
+
+def cpu_baseline(p, budget_s=12.0, one_thread_s=6.0):
+    """The FP64 oracle on a bounded sample of the same decode: its first
+    iterations on every core, then on one thread.  Returns (the record, the
+    all-core run, whose index sequence the decode is compared with)."""
     import oracle
     solve = oracle.solve64 if p.psi.dtype.itemsize == 8 else oracle.solve
-    t0 = time.perf_counter()
-    solve(p.psi, p.y, p.eps, 2, trace=False)
-    per = max((time.perf_counter() - t0) / 2.0, 1e-6)
-    iters = int(max(3, min(p.max_iters, budget_s / per)))
-    t0 = time.perf_counter()
-    res = solve(p.psi, p.y, p.eps, iters, trace=False)
-    dt = time.perf_counter() - t0
-    return dict(value=round(res.iters / dt, 3), unit="iters/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"first {res.iters} MP iterations of the same decode (FP64, "
-                       f"{dt:.1f} s)")
+    model, avail = host_cpu()
+    threads = oracle.num_threads()
+
+    def sample(budget):
+        t0 = time.perf_counter()
+        solve(p.psi, p.y, p.eps, 2, trace=True)
+        per = max((time.perf_counter() - t0) / 2.0, 1e-6)
+        iters = int(max(3, min(p.max_iters, budget / per)))
+        t0 = time.perf_counter()
+        res = solve(p.psi, p.y, p.eps, iters, trace=True)
+        return res, time.perf_counter() - t0
+
+    res, dt = sample(budget_s)
+    oracle.set_num_threads(1)
+    try:
+        res1, dt1 = sample(one_thread_s)
+    finally:
+        oracle.set_num_threads(threads)
+    rec = dict(value=round(res.iters / dt, 3), unit="iters/s", cores=threads, kind="oracle",
+               sample=f"first {res.iters} MP iterations of the same decode (FP64 correlations, "
+                      f"{dt:.1f} s, per-step trace kept)",
+               cpu_model=model, host_cores=avail,
+               one_thread={"value": round(res1.iters / dt1, 3), "unit": "iters/s", "cores": 1,
+                           "sample": f"first {res1.iters} iterations ({dt1:.1f} s)"})
+    return rec, res
+
+
+def _states(yv, rtrace, a, b):
+    """The decode's states before steps a..b-1 as an (N, b-a) FP64 matrix."""
+    return np.stack([yv if t == 0 else rtrace[t - 1] for t in range(a, b)],
+                    axis=1).astype(np.float64)
+
+
+def oracle_errors(psi, y, g, free=None, y64=False, tol_sel=1e-5, local=True, chunk=512,
+                  corr=None):
+    """Errors of one single-signal decode ``g`` (from traced_decode) against
+    the FP64 oracle:
+      * every step's selection against the FP64 argmax of the decode's own
+        state (misses: a different atom where the top-two gap exceeds
+        tol_sel ||r_t||; near_ties: a different atom at a smaller gap);
+      * x~ and r against the oracle replaying the decode's atoms in FP64
+        (x~ relative to ||x~||, r relative to ||y||), and y - Psi x~ - r;
+      * with ``free`` (the oracle's own run over a sample), the number of
+        leading steps whose atoms agree.
+    ``corr``: an ``oracle.Correlator`` of psi to reuse."""
+    import oracle
+    T = int(g["iters"])
+    idx = np.asarray(g["idx"], dtype=np.int64)[:T]
+    yv = np.asarray(y, dtype=np.float64) if y64 else np.asarray(y, np.float32).astype(np.float64)
+    ynorm = float(np.linalg.norm(yv))
+    out = {"iters": T, "stop": g["stop"],
+           "final_r_over_y": float(np.sqrt(max(g["rr"], 0.0) / g["yy"])) if g["yy"] else 0.0}
+    if local and T and g.get("r_trace") is not None:
+        corr = oracle.Correlator(psi) if corr is None else corr
+        exact = misses = ties = 0
+        for a in range(0, T, chunk):
+            b = min(T, a + chunk)
+            R = _states(yv, g["r_trace"], a, b)
+            best, _, gap = oracle.top_gap(corr.many(R))
+            ex = gap > tol_sel * np.linalg.norm(R, axis=0)
+            differ = idx[a:b] != best
+            exact += int(ex.sum())
+            misses += int((differ & ex).sum())
+            ties += int((differ & ~ex).sum())
+        out.update(steps_judged=T, gap_decided_steps=exact, misses=misses, near_ties=ties)
+    if T:
+        rep = oracle.replay(psi, yv if y64 else np.asarray(y, np.float32), idx.astype(np.int32),
+                            check_ties=False, y64=y64)
+        xg = np.asarray(g["x"], np.float64)
+        rg = np.asarray(g["r"], np.float64)
+        out["x_rel_err_vs_replay"] = float(np.linalg.norm(xg - rep.x) /
+                                           max(np.linalg.norm(rep.x), 1e-300))
+        out["r_err_vs_replay_over_y"] = float(np.linalg.norm(rg - rep.r) / max(ynorm, 1e-300))
+        nz = np.flatnonzero(xg)
+        cols = np.asarray(psi[:, nz], dtype=np.float64)
+        out["defect_over_y"] = float(np.linalg.norm(yv - cols @ xg[nz] - rg) / max(ynorm, 1e-300))
+    if free is not None:
+        k = min(len(free.idx), T)
+        mism = np.flatnonzero(np.asarray(free.idx[:k], np.int64) != idx[:k])
+        out["index_match_steps"] = int(mism[0]) if mism.size else int(k)
+        out["index_compared_steps"] = int(k)
+    return out
+
+
+def _round_errors(d):
+    return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in d.items()}
 
 
 def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = True):
@@ -280,8 +473,8 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
     M=8192 dictionary.  signals/s of mp_solve_batched (BF16 matrix-core
     correlations, FP32 re-scoring) and, for comparison, of FP32 mp_solve run
     signal after signal on the same inputs; MFMA utilisation of the product
-    kernel = 2 N M (sum of per-signal iterations) / (its summed launch time)."""
-    import numpy as np
+    kernel = 2 N M (sum of per-signal iterations) / (its summed launch time).
+    Returns (the record, the traced decode for the oracle's checks)."""
     import torch
 
     import mpgen
@@ -317,6 +510,12 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
                        "peak": 2500.0, "unit": "TFLOP/s",
                        "frac": round(flops / gemm_s / 1e12 / 2500.0, 4),
                        "rounds": cnt, "gemm_ms_per_batch": round(ms * cnt, 3)}
+        # one more decode with every signal's atoms recorded, for the checks
+        tr = dec.solve_batched(Y, bt.eps, caps, trace_cap=max(max(caps), 1))
+        torch.cuda.synchronize()
+        g = {"iters": tr["iters"], "stop": tr["stop"], "rr": tr["rr"], "yy": tr["yy"],
+             "idx": tr["idx"].cpu().numpy(), "x": tr["x"].cpu().numpy(),
+             "r": tr["r"].cpu().numpy()}
     if sequential:
         with Decoder(psi, storage="f32") as dec:
             x = torch.empty(m, dtype=torch.float32, device="cuda")
@@ -331,16 +530,17 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
             dts = time.perf_counter() - t0
         out["signals_per_s_f32_sequential"] = round(nb / dts, 2)
         out["batched_over_sequential"] = round(dts / dt, 2)
-    return out
+    return out, {"psis": [bt.psi], "ys": [bt.y[:, b] for b in range(nb)], "eps": bt.eps,
+                 "dict_of": [0] * nb, "g": g}
 
 
-def bench_ragged(seed: int, storage: str = "f32", reps: int = 3, tune_reps: int = 1):
+def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: int = 1):
     """Ragged workload: 512 independent problems, N_i ~ U{128,256,512,1024},
     M_i = 4 N_i, K_i = N_i / 16, eps = 1e-5, T_i = 20 K_i, each with its own
     dictionary, decoded in one persistent graph-replayed launch whose shape
-    the autotuner picks.  Reports problems/s and the aggregate algorithmic
-    dictionary bandwidth sum_i iters_i * bytes(Psi_i) / time."""
-    import numpy as np
+    the autotuner picks, once per dictionary storage.  Reports problems/s and
+    the aggregate algorithmic dictionary bandwidth sum_i iters_i * bytes(Psi_i)
+    / time.  Returns ({storage: record}, {storage: decode to check})."""
     import torch
 
     import mpgen
@@ -351,24 +551,33 @@ def bench_ragged(seed: int, storage: str = "f32", reps: int = 3, tune_reps: int 
     caps = [p.max_iters for p in probs]
     psis = [torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t() for p in probs]
     yp = torch.from_numpy(np.concatenate([p.y for p in probs]).astype(np.float32)).cuda()
-    esize = 4.0 if storage == "f32" else 2.0
-    out = {"workload": "512 instances, N_i ~ U{128,256,512,1024}, M_i = 4 N_i, K_i = N_i/16, "
-                       f"eps=1e-5, T_i = 20 K_i, own dictionary each, {storage} storage"}
-    with RaggedDecoder(psis, storage=storage) as dec:
-        del psis
-        tuned = tune.tune_ragged(dec, yp, 1e-5, caps, reps=tune_reps, log=log)
-        x = torch.empty(dec.x_off[-1], dtype=torch.float32, device="cuda")
-        dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            res = dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        dec.set_profiling(1)
-        dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
-        kms, _ = dec.kernel_time()
-        dec.set_profiling(0)
+    recs, checks = {}, {}
+    for storage in storages:
+        esize = 4.0 if storage == "f32" else 2.0
+        out = {"workload": "512 instances, N_i ~ U{128,256,512,1024}, M_i = 4 N_i, K_i = N_i/16, "
+                           f"eps=1e-5, T_i = 20 K_i, own dictionary each, {storage} storage"}
+        with RaggedDecoder(psis, storage=storage) as dec:
+            tuned = tune.tune_ragged(dec, yp, 1e-5, caps, reps=tune_reps, log=log)
+            x = torch.empty(dec.x_off[-1], dtype=torch.float32, device="cuda")
+            dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                res = dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            dec.set_profiling(1)
+            dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
+            kms, _ = dec.kernel_time()
+            dec.set_profiling(0)
+            tr = dec.solve(yp, 1e-5, caps, trace_cap=max(caps))
+            torch.cuda.synchronize()
+            xo, yo = dec.x_off, dec.y_off
+            xs, rs = tr["x"].cpu().numpy(), tr["r"].cpu().numpy()
+            ti = tr["idx"].cpu().numpy()
+            g = {"iters": tr["iters"], "stop": tr["stop"], "rr": tr["rr"], "yy": tr["yy"],
+                 "idx": ti, "x": [xs[xo[i]:xo[i + 1]] for i in range(len(probs))],
+                 "r": [rs[yo[i]:yo[i + 1]] for i in range(len(probs))]}
         nbytes = sum(it * esize * p.n * p.m for it, p in zip(res["iters"], probs))
         achieved = nbytes / (kms * 1e-3) / 1e9
         out.update(problems_per_s=round(len(probs) / dt, 2), solve_ms=round(dt * 1e3, 3),
@@ -377,8 +586,53 @@ def bench_ragged(seed: int, storage: str = "f32", reps: int = 3, tune_reps: int 
                    roofline={"bound": "hbm", "kernel": "k_ragged", "achieved": round(achieved, 2),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
-                             "launch_ms": round(kms, 3)})
-    return out
+                             "launch_ms": round(kms, 3),
+                             "note": "algorithmic bytes count every instance's dictionary "
+                                     "once per iteration; small dictionaries (0.25-16 MiB) "
+                                     "may be re-read from L2/MALL"})
+        recs[storage] = out
+        checks[storage] = {"psis": [p.psi for p in probs], "ys": [p.y for p in probs],
+                           "eps": 1e-5, "dict_of": list(range(len(probs))), "g": g}
+    return recs, checks
+
+
+def many_errors(chk, free_every=8, free_cap=400):
+    """Per-signal errors of a batched or ragged decode against the FP64
+    oracle: x~ and r against the oracle replaying each signal's atoms, the
+    final ||r||/||y||, and, for every ``free_every``-th signal, the leading
+    steps (of at most ``free_cap``) whose atoms agree with the oracle's own
+    run."""
+    import oracle
+    g = chk["g"]
+    xe, re_, fr, match, compared = [], [], [], [], []
+    for b, (yb, d) in enumerate(zip(chk["ys"], chk["dict_of"])):
+        psi = chk["psis"][d]
+        T = int(g["iters"][b])
+        idx = np.asarray(g["idx"][b][:T], dtype=np.int32)
+        xg = np.asarray(g["x"][b] if isinstance(g["x"], list) else g["x"][:, b], np.float64)
+        rg = np.asarray(g["r"][b] if isinstance(g["r"], list) else g["r"][:, b], np.float64)
+        yv = np.asarray(yb, np.float32).astype(np.float64)
+        ynorm = float(np.linalg.norm(yv))
+        if T:
+            rep = oracle.replay(psi, np.asarray(yb, np.float32), idx, check_ties=False)
+            xe.append(float(np.linalg.norm(xg - rep.x) / max(np.linalg.norm(rep.x), 1e-300)))
+            re_.append(float(np.linalg.norm(rg - rep.r) / max(ynorm, 1e-300)))
+        fr.append(float(np.sqrt(max(g["rr"][b], 0.0) / g["yy"][b])) if g["yy"][b] else 0.0)
+        if b % free_every == 0:
+            free = oracle.solve(psi, np.asarray(yb, np.float32), chk["eps"], min(free_cap, T))
+            k = min(free.iters, T)
+            mism = np.flatnonzero(free.idx[:k].astype(np.int64) != idx[:k])
+            match.append(int(mism[0]) if mism.size else int(k))
+            compared.append(int(k))
+    return {"signals": len(chk["ys"]),
+            "x_rel_err_vs_replay_max": max(xe, default=0.0),
+            "x_rel_err_vs_replay_median": float(np.median(xe)) if xe else 0.0,
+            "r_err_vs_replay_over_y_max": max(re_, default=0.0),
+            "final_r_over_y_max": max(fr, default=0.0),
+            "index_match": {"signals": len(match), "steps_matched": int(sum(match)),
+                            "steps_compared": int(sum(compared)),
+                            "signals_fully_matched": int(sum(a == c for a, c in
+                                                             zip(match, compared)))}}
 
 
 def main():
@@ -392,7 +646,12 @@ def main():
                     help="dictionary copy the correlation pass streams (f64: the FP64 "
                          "decode, FP64 inputs)")
     ap.add_argument("--dist", default="normal", choices=["normal", "loguniform"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle: no CPU baseline and no error checks")
+    ap.add_argument("--no-reduced", action="store_true",
+                    help="skip the BF16 / FP8 dictionary legs (N=8192, M=32768, K=256)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the N=256 and N=2048 single-signal legs")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form measurement added to the line")
     ap.add_argument("--no-ragged", action="store_true",
@@ -419,14 +678,14 @@ def main():
               "(the decoder is built and measured on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import mpgen
     from paper_0809_1833_amd.mp import Decoder
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log(f"[bench] generating {args.workload} seed {args.seed}")
+    ceiling = stream_ceiling()
+    log(f"[bench] streaming ceiling {ceiling} GB/s; generating {args.workload} seed {args.seed}")
     prec = "f64" if args.storage == "f64" else "f32"
     p = mpgen.make_problem(args.workload, args.seed, dist=args.dist, precision=prec)
     if args.max_iters is not None:
@@ -444,12 +703,12 @@ def main():
     iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, args.steps, args.warmup,
                                                   args.profile_every, x, r, stream)
     log(f"[bench] {iters} iterations in {dt:.3f} s")
+    # the same decode once more, untimed, with its whole per-step record
+    main_g = traced_decode(dec, y, p)
 
     bytes_per_launch = step_bytes(n, m, args.storage)
     rsize = 8.0 if prec == "f64" else 4.0
     bytes_per_iter = bytes_per_launch + 2 * rsize * n  # + residual read and written by the update
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if kt_n else None
-    traffic = traffic_from_counters(n, m, args.storage)
     line = {
         "metric": METRIC,
         "value": round(iters / dt, 3),
@@ -470,18 +729,8 @@ def main():
                    "stop": sorted(stops), "seed": args.seed,
                    "max_iters": p.max_iters},
         "effective_gbps_whole_step": round(iters * bytes_per_iter / dt / 1e9, 2),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": KERNEL[args.storage],
-            "achieved": round(achieved, 2) if achieved else None,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": traffic,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": round(avg_ms * 1e3, 3),
-            "launches": kt_n,
-        },
+        "roofline": hbm_roofline(KERNEL[args.storage], bytes_per_launch, avg_ms, kt_n,
+                                 traffic_from_counters(n, m, args.storage), ceiling),
     }
     if not args.no_omp and args.storage == "f32":
         log("[bench] OMP decode of the same signal")
@@ -497,12 +746,55 @@ def main():
                               "frac": round(o_ach / HBM_PEAK_GBS, 4) if o_ach else None,
                               "traffic": traffic_from_counters(p.n, p.m, "omp")}}
     dec.close()
+    del y, x, r
+    torch.cuda.empty_cache()
+
+    # decodes to check against the oracle at the end: (where in the line, problem, decode)
+    singles = [(("errors",), p, main_g, prec == "f64")]
+    default_main = args.workload == "c1b" and args.storage == "f32"
+    if default_main and not args.no_reduced:
+        line["reduced_precision"] = {}
+        base = None
+        for dist in ("normal", "loguniform"):
+            log(f"[bench] reduced-precision dictionaries, {dist} values")
+            q = mpgen.make_problem("c2", args.seed, dist=dist, psi=base)
+            base = q.psi
+            if args.max_iters is not None:
+                q.max_iters = min(q.max_iters, args.max_iters)
+            for storage in ("bf16", "fp8"):
+                leg, g = bench_single(q, storage, args.steps, args.warmup, args.profile_every,
+                                      ceiling, f"c2: {WORKLOADS['c2']}, {dist} values")
+                key = f"{storage}_{dist}"
+                line["reduced_precision"][key] = leg
+                singles.append((("reduced_precision", key, "errors"), q, g, False))
+        del base
+    if default_main and not args.no_small:
+        line["small"] = {}
+        for wl, steps in (("c0", 20), ("c1a", 5)):
+            log(f"[bench] small single-signal workload {wl}")
+            q = mpgen.make_problem(wl, args.seed)
+            if args.max_iters is not None:
+                q.max_iters = min(q.max_iters, args.max_iters)
+            leg, g = bench_single(q, "f32", steps, args.warmup, args.profile_every, ceiling,
+                                  f"{wl}: {WORKLOADS[wl]}")
+            leg["roofline"]["bound"] = "cache-resident"
+            leg["roofline"]["note"] = ("the dictionary (%.0f MiB) fits in the 256 MB MALL: "
+                                       "the bytes are algorithmic, not HBM traffic"
+                                       % (4.0 * q.n * q.m / 2 ** 20))
+            line["small"][wl] = leg
+            singles.append((("small", wl, "errors"), q, g, False))
+    many = []
     if not args.no_batched:
         log("[bench] batched form (256 signals, shared dictionary)")
-        line["batched"] = bench_batched(args.seed, sequential=not args.no_sequential)
+        line["batched"], chk = bench_batched(args.seed, sequential=not args.no_sequential)
+        many.append((("batched", "errors"), chk))
     if not args.no_ragged:
-        log("[bench] ragged instances (512 problems of uneven size)")
-        line["ragged"] = bench_ragged(args.seed)
+        log("[bench] ragged instances (512 problems of uneven size), FP32 and BF16")
+        recs, chks = bench_ragged(args.seed)
+        line["ragged"] = recs["f32"]
+        line["ragged_bf16"] = recs["bf16"]
+        many.append((("ragged", "errors"), chks["f32"]))
+        many.append((("ragged_bf16", "errors"), chks["bf16"]))
     if not args.no_f64 and args.storage != "f64":
         log("[bench] FP64 decode of the same workload")
         line["f64"] = bench_f64(args.seed)
@@ -513,9 +805,34 @@ def main():
         log("[bench] Fig. 1 experiment (batched decodes over the sigma-rho grid)")
         line["phase"] = bench_phase(args.seed)
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(p)
+        log("[bench] cpu baseline (oracle), then the oracle's checks of each decode")
+        import oracle
+        line["cpu_baseline"], free = cpu_baseline(p)
+        frees = {id(p): free}
+        corr = (None, None)  # (dictionary, its Correlator), reused by consecutive checks
+        for where, q, g, y64 in singles:
+            if id(q) not in frees:  # the oracle's own run: whole, or its first 200 steps at N=8192
+                cap = min(q.max_iters, 200) if q.n >= 8192 else q.max_iters
+                frees[id(q)] = oracle.solve(q.psi, q.y, q.eps, cap)
+            if corr[0] is not q.psi:
+                corr = (None, None)
+                corr = (q.psi, oracle.Correlator(q.psi))
+            err = _round_errors(oracle_errors(q.psi, q.y, g, free=frees[id(q)], y64=y64,
+                                              corr=corr[1]))
+            err["tol"] = "misses must be 0; x~, r within 1e-5 (FP32) of the FP64 replay"
+            _put(line, where, err)
+            log(f"[bench] checked {'/'.join(where)}")
+        corr = None
+        for where, chk in many:
+            _put(line, where, _round_errors(many_errors(chk)))
+            log(f"[bench] checked {'/'.join(where)}")
     print(json.dumps(line), flush=True)
+
+
+def _put(d, path, value):
+    for k in path[:-1]:
+        d = d.setdefault(k, {})
+    d[path[-1]] = value
 
 
 if __name__ == "__main__":

@@ -241,11 +241,16 @@ def encode(psi: np.ndarray, x: np.ndarray, support: Optional[np.ndarray] = None,
     return y.astype(dtype)
 
 
-def make_problem(name: str, seed: int, dist: str = "normal", precision: str = "f32") -> Problem:
+def make_problem(name: str, seed: int, dist: str = "normal", precision: str = "f32",
+                 psi: Optional[np.ndarray] = None) -> Problem:
     """A single-signal workload (``c0``, ``c1a``, ``c1b`` or ``c2``).
 
     ``precision='f64'`` draws the same problem for the FP64 decoder: the
-    dictionary, x and y stay FP64 (no rounding to FP32 anywhere)."""
+    dictionary, x and y stay FP64 (no rounding to FP32 anywhere).
+    ``psi``: the dictionary this workload and seed draw, already drawn (by an
+    earlier call with another ``dist``); it is used as given, which saves
+    drawing it again (the dictionary has a stream of its own, so nothing
+    else changes)."""
     if precision not in ("f32", "f64"):
         raise ValueError(precision)
     dt = np.float64 if precision == "f64" else np.float32
@@ -253,7 +258,10 @@ def make_problem(name: str, seed: int, dist: str = "normal", precision: str = "f
     r_psi, r_sup, r_val = rng_streams(w["wid"], seed, 3)
     if dist == "loguniform":  # a separate value stream for the second distribution
         r_val = rng_streams(w["wid"] + 100, seed, 1)[0]
-    psi = gaussian_unit_dictionary(r_psi, w["n"], w["m"], dtype=dt)
+    if psi is None:
+        psi = gaussian_unit_dictionary(r_psi, w["n"], w["m"], dtype=dt)
+    elif psi.shape != (w["n"], w["m"]) or psi.dtype != dt or not psi.flags.f_contiguous:
+        raise ValueError("psi must be this workload's (N, M) column-major dictionary")
     x, support = sparse_signal(r_sup, r_val, w["m"], w["k"], dist, dtype=dt)
     y = encode(psi, x, support, dtype=dt)
     return Problem(psi, x, y, support, w["eps"], w["max_iters"],

@@ -8,6 +8,8 @@
 // smallest index on ties, eq. 16).  A launch returns at once when the device
 // state says the run has stopped, so the host can enqueue launches ahead
 // without reading anything back.
+#include <algorithm>
+
 #include "k_common.h"
 #include "mp_internal.h"
 
@@ -117,7 +119,7 @@ constexpr int kCorrThreads = 1024;
 __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
     const float* __restrict__ psi, int64_t ld, int64_t n, int64_t m, float* __restrict__ rbuf,
     int cols_per_wg, uint64_t* __restrict__ keys, BalState* __restrict__ bal, long long k,
-    long long max_iters, double thr, float* __restrict__ x, DevState* __restrict__ st,
+    long long max_iters, float* __restrict__ x, DevState* __restrict__ st,
     mp_trace tr) {
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t kred[kCorrThreads / kWave];
@@ -137,6 +139,8 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   int done_v = 0;
   if (threadIdx.x == 0)
     done_v = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // eps^2 ||y||^2, set by the init kernel before the first launch
+  const double thr = st->thr;
   v4f rq[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -185,6 +189,24 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   record_pass_time(bal, par, t_begin);
 }
 
+// The first n floats of the residual half the state names (st->r_sel) into
+// r: the end of a carried decode, one launch instead of a host round trip.
+__global__ __launch_bounds__(256) void k_copy_selected(const float* __restrict__ rbuf, int64_t ld,
+                                                       int64_t n, const DevState* __restrict__ st,
+                                                       float* __restrict__ r) {
+  const float* src = rbuf + (st->r_sel ? ld : 0);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride)
+    r[i] = src[i];
+}
+
+hipError_t launch_copy_selected(const float* rbuf, int64_t ld, int64_t n, const DevState* st,
+                                float* r, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 64);
+  k_copy_selected<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(rbuf, ld, n, st, r);
+  return hipGetLastError();
+}
+
 CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
   // One 16-wave workgroup per CU (one LDS copy of r per CU, few keys);
   // a workgroup takes at least one column per wave.
@@ -201,7 +223,7 @@ CorrGeom corr_f32_geometry(int64_t m, int num_cus) {
 
 hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
                               const CorrGeom& g, uint64_t* keys, BalState* bal, long long k,
-                              long long max_iters, double thr, float* x, DevState* st, mp_trace tr,
+                              long long max_iters, float* x, DevState* st, mp_trace tr,
                               hipStream_t s) {
   const size_t lds = static_cast<size_t>(ld) * sizeof(float);
   static bool big_lds = false;  // residuals above 60 KB need the opt-in limit
@@ -212,7 +234,7 @@ hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m
     big_lds = true;
   }
   k_mp_step_f32<<<dim3(g.grid), dim3(kCorrThreads), lds, s>>>(
-      psi, ld, n, m, rbuf, g.cols_per_wg, keys, bal, k, max_iters, thr, x, st, tr);
+      psi, ld, n, m, rbuf, g.cols_per_wg, keys, bal, k, max_iters, x, st, tr);
   return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
     const v4u* __restrict__ psiq, const float* __restrict__ scales,
     const float* __restrict__ psi32, int64_t ld, int64_t n, int64_t m, float* __restrict__ rbuf,
     int cols_per_wg, int rescore_k, uint64_t* __restrict__ keys, long long k,
-    long long max_iters, double thr, float* __restrict__ x, DevState* __restrict__ st,
+    long long max_iters, float* __restrict__ x, DevState* __restrict__ st,
     mp_trace tr) {
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t lists[kLpWaves * kTopK];
@@ -160,6 +160,8 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
   int done_v = 0;
   if (threadIdx.x == 0)
     done_v = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // eps^2 ||y||^2, set by the init kernel before the first launch
+  const double thr = st->thr;
   v4f rq[RPT];
 #pragma unroll
   for (int u = 0; u < RPT; ++u) {
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(kLpThreads) void k_mp_step_lp(
 hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
                              const float* psi32, int64_t ld, int64_t n, int64_t m, float* rbuf,
                              const CorrGeom& g, int rescore_k, uint64_t* keys, long long k,
-                             long long max_iters, double thr, float* x, DevState* st,
+                             long long max_iters, float* x, DevState* st,
                              mp_trace tr, hipStream_t s) {
   const size_t lds = static_cast<size_t>(ld) * sizeof(float);
   const v4u* q = static_cast<const v4u*>(psiq);
@@ -282,11 +284,11 @@ hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* sc
   }
   if (storage == MP_BF16)
     k_mp_step_lp<2><<<dim3(g.grid), dim3(kLpThreads), lds, s>>>(
-        q, nullptr, psi32, ld, n, m, rbuf, g.cols_per_wg, rescore_k, keys, k, max_iters, thr, x,
+        q, nullptr, psi32, ld, n, m, rbuf, g.cols_per_wg, rescore_k, keys, k, max_iters, x,
         st, tr);
   else
     k_mp_step_lp<1><<<dim3(g.grid), dim3(kLpThreads), lds, s>>>(
-        q, scales, psi32, ld, n, m, rbuf, g.cols_per_wg, rescore_k, keys, k, max_iters, thr, x,
+        q, scales, psi32, ld, n, m, rbuf, g.cols_per_wg, rescore_k, keys, k, max_iters, x,
         st, tr);
   return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 // Host side of libmp.so: argument checking, context ownership, the iteration
 // driver, and the C ABI declared in include/mp.h.
 #include <math.h>
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -111,6 +112,8 @@ void free_ctx(mp_ctx* c) {
   (void)hipFree(c->partials);
   (void)hipFree(c->bal);
   if (c->h_st) (void)hipHostFree(c->h_st);
+  for (hipEvent_t e : c->done_ev)
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
@@ -170,6 +173,44 @@ mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
   return MP_OK;
 }
 
+// The pinned host mirror of the device state (entry 0) and the two slots
+// run_iterations copies each chunk's state into (entries 1, 2), with the
+// events that mark those copies: made once per context, so that a decode
+// allocates nothing.
+bool make_host_state(mp_ctx* c) {
+  if (hipHostMalloc(&c->h_st, 3 * sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess) {
+    c->h_st = nullptr;
+    return false;
+  }
+  for (hipEvent_t& e : c->done_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      return false;
+    }
+  return true;
+}
+
+// Length of the next chunk of launches.  Doubling from 4 up to kMaxChunk
+// while the run is young; once two chunk-end states are known, the
+// remaining steps are estimated from the decay of ||r||^2 between them
+// (ln rr falls about linearly once MP settles) and the chunk is cut to what
+// that estimate still needs beyond the launches already in flight, plus a
+// margin: launches issued past the stop return at once but still cost a
+// dispatch each, which dominates short decodes.  Returns 0 when the
+// launches in flight should cover the estimate (the caller then waits).
+int next_chunk(int doubling, long long issued, const mp::DevState* a, const mp::DevState* b) {
+  const double thr = b ? b->thr : 0.0;
+  if (!a || !b || b->done || b->t <= a->t || !(b->rr > thr) || !(a->rr > b->rr) ||
+      !(thr > 0.0))
+    return doubling;
+  const double rate = (std::log(a->rr) - std::log(b->rr)) / static_cast<double>(b->t - a->t);
+  const double rem = std::log(b->rr / thr) / rate;  // steps still needed after b
+  const long long ahead = issued - (b->t + 1);         // launches in flight past b
+  const double want = std::ceil(rem * 1.25) + 2.0 - static_cast<double>(ahead);
+  if (want <= 0.0) return 0;
+  return static_cast<int>(std::min<double>(want, doubling));
+}
+
 // The single-signal iteration driver: after init (state already copied to
 // c->h_st), enqueue chunks of iterations with `enqueue(e0, e1)` (record e0,
 // when not null, before the iteration's launch and e1 after it); the kernels
@@ -186,20 +227,18 @@ mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
 // launch) every prof_every-th iteration is timed on its own.  Only launches
 // that performed an iteration are counted: a window, all its launches.
 template <typename Enqueue>
-mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, Enqueue enqueue) {
+mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, Enqueue enqueue,
+                         bool known_running = false, const mp::DevState* dst = nullptr) {
+  if (!dst) dst = c->st;
   c->prof_ms = 0.0;
   c->prof_launches = 0;
   long long issued = 0;
   int chunk = 4;
-  hipEvent_t done_ev[2] = {nullptr, nullptr};
-  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[0], hipEventDisableTiming));
-  HIP_TRY(c, hipEventCreateWithFlags(&done_ev[1], hipEventDisableTiming));
-  mp::DevState* h_slot = nullptr;
-  if (hipHostMalloc(&h_slot, 2 * sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess) {
-    (void)hipEventDestroy(done_ev[0]);
-    (void)hipEventDestroy(done_ev[1]);
-    return fail(c, MP_ENOMEM, "pinned state slots");
-  }
+  hipEvent_t* done_ev = c->done_ev;
+  mp::DevState* h_slot = c->h_st + 1;
+  // the last two chunk-end states read back (for the chunk-length estimate)
+  mp::DevState hist[2];
+  int nhist = 0;
   long long slot_base[2] = {0, 0};
   int slot_len[2] = {0, 0};
   mp_status status = MP_OK;
@@ -226,13 +265,19 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, E
       }
     }
   };
-  bool finished = c->h_st->done != 0;
+  bool finished = !known_running && c->h_st->done != 0;
   int next = 0;      // slot the next chunk goes to
   int inflight = 0;  // chunks enqueued but not yet waited for
   while (!finished && status == MP_OK) {
     while (inflight < 2 && issued < T && status == MP_OK) {
       const int k = next;
-      const int len = static_cast<int>(std::min<long long>(chunk, T - issued));
+      int want = next_chunk(chunk, issued, nhist == 2 ? &hist[0] : nullptr,
+                            nhist >= 1 ? &hist[nhist - 1] : nullptr);
+      if (want == 0) {
+        if (inflight > 0) break;  // wait for what is in flight
+        want = 2;
+      }
+      const int len = static_cast<int>(std::min<long long>(want, T - issued));
       const int w = windowed ? std::min(c->prof_every, kMaxChunk) : 1;
       for (int j = 0; j < len; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -252,7 +297,7 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, E
       slot_base[k] = issued;
       slot_len[k] = len;
       issued += len;
-      hipError_t e = hipMemcpyAsync(&h_slot[k], c->st, sizeof(mp::DevState),
+      hipError_t e = hipMemcpyAsync(&h_slot[k], dst, sizeof(mp::DevState),
                                     hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipEventRecord(done_ev[k], s);
       if (e != hipSuccess) {
@@ -273,14 +318,62 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, E
     --inflight;
     account(old);
     if (h_slot[old].done) finished = true;
+    if (nhist == 2) hist[0] = hist[1];
+    hist[nhist == 2 ? 1 : nhist] = h_slot[old];
+    if (nhist < 2) ++nhist;
   }
   // drain the chunk still in flight (its launches return at once)
   if (hipStreamSynchronize(s) != hipSuccess && status == MP_OK)
     status = fail(c, MP_EDEVICE, "stream synchronize failed");
-  (void)hipHostFree(h_slot);
-  (void)hipEventDestroy(done_ev[0]);
-  (void)hipEventDestroy(done_ev[1]);
   return status;
+}
+
+// Device buffers of one carried single-signal decode (FP32, BF16, FP8), the
+// context's own for mp_solve.
+struct CarriedBufs {
+  mp::DevState* st;  // the decode's state
+  float* r_work;     // 2 x ld floats: r_k in half k mod 2 (padding rows written 0)
+  uint64_t* keys;    // 2 x grid x kLpTopK key slots
+  mp::BalState* bal; // column shares and pass timings (any contents: a balance hint only)
+};
+
+mp_status finish_result(mp_ctx* c, mp_result* res);
+
+// The carried decode: launch k takes step k (k >= 1) and runs pass k+1, so T
+// steps take T+1 launches; r ends in the half the state names.  The kernels
+// read the stop threshold from the device state, so the host starts
+// launching without waiting for the init kernel (launches after a stop, zero
+// input included, return at once).  At the end one small kernel copies r out
+// of the half the state names, and the state comes back with one wait.
+// Allocates nothing: every buffer is in `b`, the context (pinned state slots
+// and events made at its creation) or the caller's arguments.
+mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_opts* opts,
+                        mp_result* res, const mp_trace& tr, hipStream_t s, const CarriedBufs& b) {
+  HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, b.r_work, b.st, opts->eps,
+                             static_cast<long long>(opts->max_iters), s));
+  long long k = 0;
+  const long long T = opts->max_iters;
+  const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
+    hipError_t e;
+    if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
+    if (c->storage == MP_F32)
+      e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, b.r_work, c->geom, b.keys, b.bal,
+                                 k, T, x, b.st, tr, s);
+    else
+      e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
+                                b.r_work, c->geom, c->rescore_k, b.keys, k, T, x, b.st, tr, s);
+    ++k;
+    if (e != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
+    return hipSuccess;
+  }, /*known_running=*/true, b.st);
+  if (st != MP_OK) return st;
+  if (r) HIP_TRY(c, mp::launch_copy_selected(b.r_work, c->ld, c->n, b.st, r, s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, b.st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  const mp_status fs = finish_result(c, res);
+  if (fs == MP_OK && res) res->persistent = 0;
+  return fs;
 }
 
 // Final state of a single-signal decode into `res`, with the internal stop
@@ -372,8 +465,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
   if (hipMalloc(&c->bal, sizeof(mp::BalState)) != hipSuccess) return bail(MP_ENOMEM, "shares");
-  if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
-    return bail(MP_ENOMEM, "pinned state");
+  if (!make_host_state(c)) return bail(MP_ENOMEM, "pinned state");
 
   hipError_t e = hipMemsetAsync(c->psi32, 0, psi_bytes, s);
   if (e == hipSuccess)
@@ -486,11 +578,17 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   c->prof_launches = 0;
   bool persistent = false;  // the one-bit decode ran as one persistent launch
 
+  if (c->storage != MP_SIGN1)
+    return solve_carried(c, y, x, r, opts, res, tr, s,
+                         CarriedBufs{c->st, c->r_work, c->partials, c->bal});
+
   HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, c->r_work, c->st, opts->eps,
                              static_cast<long long>(opts->max_iters), s));
-  HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  if (c->storage == MP_SIGN1) {
+  {
+    // the host needs the threshold and whether the run is over before it
+    // chooses between the persistent and the stepping decode
+    HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
     // c(0) = Psi^T y and r = y in FP64; launch k runs the stop test for the
     // k-1 steps taken and takes step k, so T steps take T+2 launches
     if (!c->h_st->done)
@@ -536,28 +634,6 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
       return hipSuccess;
     });
     if (st != MP_OK) return st;
-  } else {
-    // FP32, BF16, FP8: launch k takes step k (k >= 1) and runs pass k+1, so
-    // T steps take T+1 launches; r ends in the half the state names
-    long long k = 0;
-    const long long T = opts->max_iters;
-    const double thr = c->h_st->thr;
-    const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
-      hipError_t e;
-      if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
-      if (c->storage == MP_F32)
-        e = mp::launch_mp_step_f32(c->psi32, c->ld, c->n, c->m, c->r_work, c->geom, c->partials,
-                                   c->bal, k, T, thr, x, c->st, tr, s);
-      else
-        e = mp::launch_mp_step_lp(c->storage, c->psiq, c->scales, c->psi32, c->ld, c->n, c->m,
-                                  c->r_work, c->geom, c->rescore_k, c->partials, k, T, thr, x,
-                                  c->st, tr, s);
-      ++k;
-      if (e != hipSuccess) return e;
-      if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
-      return hipSuccess;
-    });
-    if (st != MP_OK) return st;
   }
 
   HIP_TRY(c, hipMemcpyAsync(c->h_st, c->st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
@@ -572,10 +648,8 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
     }
   }
   if (r) {
-    // the one-bit form keeps its FP32 r in the first half; the others in the
-    // half the state names
-    const float* rs = c->r_work + (c->storage != MP_SIGN1 && c->h_st->r_sel ? c->ld : 0);
-    HIP_TRY(c, hipMemcpyAsync(r, rs, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // the one-bit form keeps its FP32 r in the first n floats of r_work
+    HIP_TRY(c, hipMemcpyAsync(r, c->r_work, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
   HIP_TRY(c, hipStreamSynchronize(s));
   const mp_status fs = finish_result(c, res);
@@ -687,8 +761,7 @@ mp_status mp_create_f64(mp_ctx** out, const double* psi, int64_t n, int64_t m, i
   if (hipMalloc(&c->partials, sizeof(uint64_t) * nkeys) != hipSuccess)
     return bail(MP_ENOMEM, "partials");
   if (hipMalloc(&c->bal, sizeof(mp::BalState)) != hipSuccess) return bail(MP_ENOMEM, "shares");
-  if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
-    return bail(MP_ENOMEM, "pinned state");
+  if (!make_host_state(c)) return bail(MP_ENOMEM, "pinned state");
 
   hipError_t e = hipMemsetAsync(c->psi64, 0, psi_bytes, s);
   if (e == hipSuccess)
@@ -770,8 +843,7 @@ mp_status mp_create_signs(mp_ctx** out, const uint32_t* signs, int64_t n, int64_
       sizeof(unsigned long long) * mp::kSignSlotWords * 2 * static_cast<size_t>(c->geom.grid);
   if (hipMalloc(&c->sign_slots, slot_bytes) != hipSuccess)
     return bail(MP_ENOMEM, "step records");
-  if (hipHostMalloc(&c->h_st, sizeof(mp::DevState), hipHostMallocDefault) != hipSuccess)
-    return bail(MP_ENOMEM, "pinned state");
+  if (!make_host_state(c)) return bail(MP_ENOMEM, "pinned state");
   hipError_t e = mp::launch_copy_signs(signs, ldw, n, m, c->sign_ws, c->psis, s);
   if (e == hipSuccess) e = hipMemsetAsync(c->r_work, 0, c->ld * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(c->partials, 0, sizeof(uint64_t) * nkeys, s);

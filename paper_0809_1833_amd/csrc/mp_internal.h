@@ -83,11 +83,15 @@ hipError_t launch_norms(const float* psi, int64_t ld, int64_t n, int64_t m, doub
                         int* nonfinite, hipStream_t s);
 hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t m, float* r,
                        DevState* st, double eps, long long max_iters, hipStream_t s);
+// n floats of the residual half st->r_sel names (rbuf: 2 x ld) into r.
+hipError_t launch_copy_selected(const float* rbuf, int64_t ld, int64_t n, const DevState* st,
+                                float* r, hipStream_t s);
 // Launch k of an FP32 decode: step k (k >= 1) and pass k+1.  rbuf: 2 x ld
-// floats (r in half k mod 2); keys: 2 halves x one per workgroup.
+// floats (r in half k mod 2); keys: 2 halves x one per workgroup.  The stop
+// threshold is read from st (set by the init kernel).
 hipError_t launch_mp_step_f32(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
                               const CorrGeom& g, uint64_t* keys, BalState* bal, long long k,
-                              long long max_iters, double thr, float* x, DevState* st, mp_trace tr,
+                              long long max_iters, float* x, DevState* st, mp_trace tr,
                               hipStream_t s);
 
 // ---- kernels of the FP64 single-signal path (k_f64.hip) ---------------------
@@ -242,7 +246,7 @@ hipError_t launch_quant_fp8(const float* psi, int64_t ld, int64_t m, uint8_t* ou
 hipError_t launch_mp_step_lp(mp_dtype storage, const void* psiq, const float* scales,
                              const float* psi32, int64_t ld, int64_t n, int64_t m, float* rbuf,
                              const CorrGeom& g, int rescore_k, uint64_t* keys, long long k,
-                             long long max_iters, double thr, float* x, DevState* st,
+                             long long max_iters, float* x, DevState* st,
                              mp_trace tr, hipStream_t s);
 
 }  // namespace mp
@@ -269,7 +273,8 @@ struct mp_ctx {
   // per-decode work buffers
   float* r_work = nullptr;       // ld floats, rows n..ld-1 stay zero
   mp::DevState* st = nullptr;    // device state
-  mp::DevState* h_st = nullptr;  // pinned host mirror
+  mp::DevState* h_st = nullptr;  // pinned: host mirror, then two chunk-state slots
+  hipEvent_t done_ev[2] = {nullptr, nullptr};  // the chunk-state copies done
   uint64_t* partials = nullptr;  // key slots: kLpTopK per correlation workgroup
   mp::BalState* bal = nullptr;   // column shares and pass timings (FP32, FP64 passes)
   mp::CorrGeom geom{};

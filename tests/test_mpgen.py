@@ -36,6 +36,19 @@ def test_loguniform_values():
     assert np.all((v >= 1e-3 * (1 - 1e-6)) & (v <= 1.0))
 
 
+def test_given_dictionary_gives_the_same_problem():
+    """A dictionary drawn by an earlier call, passed back in, yields exactly
+    the problem a fresh draw gives (for the other value law too)."""
+    a = mpgen.make_problem("c0", 2)
+    for dist in ("normal", "loguniform"):
+        fresh = mpgen.make_problem("c0", 2, dist=dist)
+        reuse = mpgen.make_problem("c0", 2, dist=dist, psi=a.psi)
+        assert np.array_equal(fresh.psi, reuse.psi) and np.array_equal(fresh.y, reuse.y)
+        assert np.array_equal(fresh.x, reuse.x) and np.array_equal(fresh.support, reuse.support)
+    with pytest.raises(ValueError):
+        mpgen.make_problem("c0", 2, psi=np.ascontiguousarray(a.psi))
+
+
 def test_batch_recipe():
     bt = mpgen.make_batch(0, b=8, n=64, m=256, kmin=2, kmax=6)
     assert bt.x.shape == (256, 8) and bt.y.shape == (64, 8)
