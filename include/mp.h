@@ -185,6 +185,32 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
                    mp_result* res, const mp_trace* trace, void* stream);
 
 /*
+ * mp_solve_noalloc -- mp_solve for callers that cannot allocate memory while
+ * they decode: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as mp_solve for
+ * an MP_F32, MP_BF16 or MP_FP8_E4M3 context from mp_create (the same kernels,
+ * bit-identical results), but the decode's device work buffers (state,
+ * residual double buffer, per-workgroup keys, column-share state) live in
+ * a static array of 256 KiB that the library holds on each GPU it runs on
+ * until the process ends, and the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library call; the pinned state slots and events it
+ * uses were made by mp_create).
+ *
+ * Limits: N <= 16384 (the residual double buffer), at most 256 correlation
+ * workgroups (MP_EINVAL otherwise; mp_create's own limits already imply
+ * both on an MI355X).  Every call on one GPU shares that GPU's array and
+ * leaves its contents behind: calls that overlap on one GPU (other streams,
+ * other threads, other contexts) race and must not be issued.  Nothing in
+ * the array needs to start at zero: each decode writes its state and
+ * buffers before reading them, and the column shares left by an earlier
+ * call only guide the work split, never the results.
+ * Errors: as mp_solve, plus MP_EINVAL for a ragged, MP_F64 or MP_SIGN1
+ * context.
+ */
+mp_status mp_solve_noalloc(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
+                           mp_result* res, const mp_trace* trace, void* stream);
+
+/*
  * mp_solve_batched -- decode B signals that share the context's dictionary
  * (the paper encodes and decodes every signal with one dictionary,
  * Section 4).  Each signal runs its own Section 3 loop; the correlations of

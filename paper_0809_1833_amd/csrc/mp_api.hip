@@ -328,8 +328,9 @@ mp_status run_iterations(mp_ctx* c, long long T, hipStream_t s, bool windowed, E
   return status;
 }
 
-// Device buffers of one carried single-signal decode (FP32, BF16, FP8), the
-// context's own for mp_solve.
+// Device buffers of one carried single-signal decode (FP32, BF16, FP8): the
+// context's own (mp_solve) or carved from the library's static scratch
+// (mp_solve_noalloc).
 struct CarriedBufs {
   mp::DevState* st;  // the decode's state
   float* r_work;     // 2 x ld floats: r_k in half k mod 2 (padding rows written 0)
@@ -466,6 +467,12 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
     return bail(MP_ENOMEM, "partials");
   if (hipMalloc(&c->bal, sizeof(mp::BalState)) != hipSuccess) return bail(MP_ENOMEM, "shares");
   if (!make_host_state(c)) return bail(MP_ENOMEM, "pinned state");
+  // set-up of mp_solve_noalloc's scratch on this device (the entry point
+  // looks it up itself if this fails)
+  {
+    void* scratch_ptr = nullptr;
+    (void)mp::noalloc_scratch(dev, &scratch_ptr);
+  }
 
   hipError_t e = hipMemsetAsync(c->psi32, 0, psi_bytes, s);
   if (e == hipSuccess)
@@ -655,6 +662,38 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   const mp_status fs = finish_result(c, res);
   if (fs == MP_OK && res) res->persistent = persistent ? 1 : 0;
   return fs;
+}
+
+mp_status mp_solve_noalloc(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
+                           mp_result* res, const mp_trace* trace, void* stream) {
+  if (!ctx) return MP_EINVAL;
+  ctx->err.clear();
+  mp_ctx* c = ctx;
+  if (c->ragged || !(c->storage == MP_F32 || c->storage == MP_BF16 ||
+                     c->storage == MP_FP8_E4M3))
+    return fail(c, MP_EINVAL,
+                "mp_solve_noalloc decodes MP_F32, MP_BF16 and MP_FP8_E4M3 contexts of mp_create");
+  if (!y || !x || !opts) return fail(c, MP_EINVAL, "y, x and opts must not be NULL");
+  if (mp_status os = check_opts(c, opts); os != MP_OK) return os;
+  if (mp_status ts = check_trace(c, trace, c->n); ts != MP_OK) return ts;
+  if (c->ld > mp::kNoAllocMaxLd)
+    return fail(c, MP_EINVAL, "N exceeds the static scratch (at most 16384 rows)");
+  if (2 * static_cast<int64_t>(c->geom.grid) * mp::kLpTopK > mp::kNoAllocMaxKeys)
+    return fail(c, MP_EINVAL, "more correlation workgroups than the static scratch holds");
+  mp_trace tr{};
+  if (trace) tr = *trace;
+  HIP_TRY(c, hipSetDevice(c->device));
+  void* base = nullptr;
+  HIP_TRY(c, mp::noalloc_scratch(c->device, &base));
+  unsigned char* b = static_cast<unsigned char*>(base);
+  c->rescore_k = opts->rescore_k == 0 ? mp::kLpTopK : opts->rescore_k;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  return solve_carried(c, y, x, r, opts, res, tr, static_cast<hipStream_t>(stream),
+                       CarriedBufs{reinterpret_cast<mp::DevState*>(b),
+                                   reinterpret_cast<float*>(b + mp::kNoAllocR),
+                                   reinterpret_cast<uint64_t*>(b + mp::kNoAllocKeys),
+                                   reinterpret_cast<mp::BalState*>(b + mp::kNoAllocBal)});
 }
 
 static mp_status ensure_omp(mp_ctx* c, int64_t tq) {

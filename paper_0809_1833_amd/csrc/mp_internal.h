@@ -83,6 +83,21 @@ hipError_t launch_norms(const float* psi, int64_t ld, int64_t n, int64_t m, doub
                         int* nonfinite, hipStream_t s);
 hipError_t launch_init(const float* y, int64_t n, int64_t ld, float* x, int64_t m, float* r,
                        DevState* st, double eps, long long max_iters, hipStream_t s);
+// ---- the static scratch of mp_solve_noalloc (mp_noalloc.hip) ---------------
+// Layout: the decode state at 0, the residual double buffer (2 x ld floats,
+// ld <= kNoAllocMaxLd) at kNoAllocR, the key slots (2 x grid x kLpTopK) at
+// kNoAllocKeys, the column-share state at kNoAllocBal.
+constexpr size_t kNoAllocScratchBytes = 256 * 1024;
+constexpr int kNoAllocMaxDevices = 64;
+constexpr int64_t kNoAllocMaxLd = 16384;
+constexpr int64_t kNoAllocMaxKeys = 2 * 256 * 8;
+constexpr size_t kNoAllocR = 256;
+constexpr size_t kNoAllocKeys = kNoAllocR + 2 * kNoAllocMaxLd * sizeof(float);
+constexpr size_t kNoAllocBal = kNoAllocKeys + kNoAllocMaxKeys * sizeof(uint64_t);
+// The scratch's device address on `device` (which must be current), looked
+// up once per device and kept.
+hipError_t noalloc_scratch(int device, void** out);
+
 // n floats of the residual half st->r_sel names (rbuf: 2 x ld) into r.
 hipError_t launch_copy_selected(const float* rbuf, int64_t ld, int64_t n, const DevState* st,
                                 float* r, hipStream_t s);

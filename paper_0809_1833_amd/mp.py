@@ -83,6 +83,9 @@ def _load():
     lib.mp_solve.restype = ctypes.c_int
     lib.mp_solve.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
                              ctypes.POINTER(Trace), p]
+    lib.mp_solve_noalloc.restype = ctypes.c_int
+    lib.mp_solve_noalloc.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
+                                     ctypes.POINTER(Trace), p]
     lib.mp_destroy.restype = None
     lib.mp_destroy.argtypes = [p]
     lib.mp_status_str.restype = ctypes.c_char_p
@@ -172,6 +175,16 @@ def mp_solve(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
     st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
                           ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve", ctx)
+    return res
+
+
+def mp_solve_noalloc(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
+                     trace: Optional[Trace] = None, stream: Optional[int] = None) -> Result:
+    res = Result()
+    st = _load().mp_solve_noalloc(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts),
+                                  ctypes.byref(res),
+                                  ctypes.byref(trace) if trace is not None else None, stream)
+    _check(st, "mp_solve_noalloc", ctx)
     return res
 
 
@@ -359,13 +372,15 @@ class Decoder:
     def solve(self, y: torch.Tensor, eps: float, max_iters: int, x: Optional[torch.Tensor] = None,
               r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
               stream=None, omp: bool = False, step_launches: bool = False,
-              trace_r: bool = False):
+              trace_r: bool = False, noalloc: bool = False):
         """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, persistent,
         trace...).  ``omp=True`` decodes with Orthogonal Matching Pursuit
         (mp_solve_omp; MP_F32 storage).  ``step_launches=True``: the one-bit
         form steps with one launch per iteration (MP_SOLVE_STEP_LAUNCHES).
         ``trace_r=True`` (with ``trace_cap``): also the residual after every
-        traced step, ``r_trace`` of shape (steps, N)."""
+        traced step, ``r_trace`` of shape (steps, N).  ``noalloc=True``:
+        mp_solve_noalloc (the library's static scratch; MP_F32, MP_BF16 or
+        MP_FP8_E4M3 storage)."""
         dt = self.dtype
         if not y.is_cuda or y.dtype != dt or y.numel() != self.n:
             raise ValueError(f"y must be a {dt} CUDA tensor of N elements")
@@ -389,7 +404,10 @@ class Decoder:
                     MP_SOLVE_STEP_LAUNCHES if step_launches else 0)
         if omp and self.storage != "f32":
             raise ValueError("OMP decodes need f32 storage")
-        solve = mp_solve_f64 if self.storage == "f64" else (mp_solve_omp if omp else mp_solve)
+        if noalloc and (omp or self.storage in ("f64", "sign")):
+            raise ValueError("noalloc decodes need f32, bf16 or fp8 storage and plain MP")
+        solve = mp_solve_f64 if self.storage == "f64" else (
+            mp_solve_omp if omp else (mp_solve_noalloc if noalloc else mp_solve))
         res = solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
                     _stream_ptr(stream))
         out = dict(x=x, r=r, iters=res.iters, yy=res.yy, rr=res.rr,
