@@ -345,10 +345,12 @@ def traced_decode(dec, y, p, **kw):
     return g
 
 
-def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, rescore_k=0):
+def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, rescore_k=0,
+                 check=True):
     """Time `steps` decodes of problem p with the given dictionary storage,
-    then decode it once more with the whole per-step record.  Returns (the
-    leg's record, the decode to check against the oracle)."""
+    then (``check``) decode it once more with the whole per-step record.
+    Returns (the leg's record, the decode to check against the oracle or
+    None)."""
     import torch
 
     from paper_0809_1833_amd.mp import Decoder
@@ -362,7 +364,7 @@ def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, re
         r = torch.empty(n, dtype=torch.float32, device="cuda")
         iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
                                                       x, r, rescore_k=rescore_k)
-        g = traced_decode(dec, y, p, rescore_k=rescore_k)
+        g = traced_decode(dec, y, p, rescore_k=rescore_k) if check else None
     leg = {"workload": workload, "storage": storage,
            "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
            "us_per_iter": round(dt / max(iters, 1) * 1e6, 3),
@@ -468,7 +470,8 @@ def _round_errors(d):
     return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = True):
+def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = True,
+                  check: bool = True):
     """Batched workload: 256 signals, K_b ~ U{16..256}, sharing one N=2048,
     M=8192 dictionary.  signals/s of mp_solve_batched (BF16 matrix-core
     correlations, FP32 re-scoring) and, for comparison, of FP32 mp_solve run
@@ -511,11 +514,13 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
                        "frac": round(flops / gemm_s / 1e12 / 2500.0, 4),
                        "rounds": cnt, "gemm_ms_per_batch": round(ms * cnt, 3)}
         # one more decode with every signal's atoms recorded, for the checks
-        tr = dec.solve_batched(Y, bt.eps, caps, trace_cap=max(max(caps), 1))
-        torch.cuda.synchronize()
-        g = {"iters": tr["iters"], "stop": tr["stop"], "rr": tr["rr"], "yy": tr["yy"],
-             "idx": tr["idx"].cpu().numpy(), "x": tr["x"].cpu().numpy(),
-             "r": tr["r"].cpu().numpy()}
+        g = None
+        if check:
+            tr = dec.solve_batched(Y, bt.eps, caps, trace_cap=max(max(caps), 1))
+            torch.cuda.synchronize()
+            g = {"iters": tr["iters"], "stop": tr["stop"], "rr": tr["rr"], "yy": tr["yy"],
+                 "idx": tr["idx"].cpu().numpy(), "x": tr["x"].cpu().numpy(),
+                 "r": tr["r"].cpu().numpy()}
     if sequential:
         with Decoder(psi, storage="f32") as dec:
             x = torch.empty(m, dtype=torch.float32, device="cuda")
@@ -534,7 +539,8 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
                  "dict_of": [0] * nb, "g": g}
 
 
-def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: int = 1):
+def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: int = 1,
+                 check: bool = True):
     """Ragged workload: 512 independent problems, N_i ~ U{128,256,512,1024},
     M_i = 4 N_i, K_i = N_i / 16, eps = 1e-5, T_i = 20 K_i, each with its own
     dictionary, decoded in one persistent graph-replayed launch whose shape
@@ -570,14 +576,16 @@ def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: 
             dec.solve(yp, 1e-5, caps, want_r=False, x_out=x)
             kms, _ = dec.kernel_time()
             dec.set_profiling(0)
-            tr = dec.solve(yp, 1e-5, caps, trace_cap=max(caps))
-            torch.cuda.synchronize()
-            xo, yo = dec.x_off, dec.y_off
-            xs, rs = tr["x"].cpu().numpy(), tr["r"].cpu().numpy()
-            ti = tr["idx"].cpu().numpy()
-            g = {"iters": tr["iters"], "stop": tr["stop"], "rr": tr["rr"], "yy": tr["yy"],
-                 "idx": ti, "x": [xs[xo[i]:xo[i + 1]] for i in range(len(probs))],
-                 "r": [rs[yo[i]:yo[i + 1]] for i in range(len(probs))]}
+            g = None
+            if check:
+                tr = dec.solve(yp, 1e-5, caps, trace_cap=max(caps))
+                torch.cuda.synchronize()
+                xo, yo = dec.x_off, dec.y_off
+                xs, rs = tr["x"].cpu().numpy(), tr["r"].cpu().numpy()
+                ti = tr["idx"].cpu().numpy()
+                g = {"iters": tr["iters"], "stop": tr["stop"], "rr": tr["rr"], "yy": tr["yy"],
+                     "idx": ti, "x": [xs[xo[i]:xo[i + 1]] for i in range(len(probs))],
+                     "r": [rs[yo[i]:yo[i + 1]] for i in range(len(probs))]}
         nbytes = sum(it * esize * p.n * p.m for it, p in zip(res["iters"], probs))
         achieved = nbytes / (kms * 1e-3) / 1e9
         out.update(problems_per_s=round(len(probs) / dt, 2), solve_ms=round(dt * 1e3, 3),
@@ -646,6 +654,8 @@ def main():
                     help="dictionary copy the correlation pass streams (f64: the FP64 "
                          "decode, FP64 inputs)")
     ap.add_argument("--dist", default="normal", choices=["normal", "loguniform"])
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the streaming probe run that gives the measured read ceiling")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle: no CPU baseline and no error checks")
     ap.add_argument("--no-reduced", action="store_true",
@@ -684,7 +694,7 @@ def main():
     from paper_0809_1833_amd.mp import Decoder
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    ceiling = stream_ceiling()
+    ceiling = None if args.no_ceiling else stream_ceiling()
     log(f"[bench] streaming ceiling {ceiling} GB/s; generating {args.workload} seed {args.seed}")
     prec = "f64" if args.storage == "f64" else "f32"
     p = mpgen.make_problem(args.workload, args.seed, dist=args.dist, precision=prec)
@@ -703,8 +713,10 @@ def main():
     iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, args.steps, args.warmup,
                                                   args.profile_every, x, r, stream)
     log(f"[bench] {iters} iterations in {dt:.3f} s")
-    # the same decode once more, untimed, with its whole per-step record
-    main_g = traced_decode(dec, y, p)
+    # the same decode once more, untimed, with its whole per-step record (for
+    # the oracle's checks at the end)
+    check = not args.no_cpu_baseline
+    main_g = traced_decode(dec, y, p) if check else None
 
     bytes_per_launch = step_bytes(n, m, args.storage)
     rsize = 8.0 if prec == "f64" else 4.0
@@ -763,7 +775,8 @@ def main():
                 q.max_iters = min(q.max_iters, args.max_iters)
             for storage in ("bf16", "fp8"):
                 leg, g = bench_single(q, storage, args.steps, args.warmup, args.profile_every,
-                                      ceiling, f"c2: {WORKLOADS['c2']}, {dist} values")
+                                      ceiling, f"c2: {WORKLOADS['c2']}, {dist} values",
+                                      check=check)
                 key = f"{storage}_{dist}"
                 line["reduced_precision"][key] = leg
                 singles.append((("reduced_precision", key, "errors"), q, g, False))
@@ -776,7 +789,7 @@ def main():
             if args.max_iters is not None:
                 q.max_iters = min(q.max_iters, args.max_iters)
             leg, g = bench_single(q, "f32", steps, args.warmup, args.profile_every, ceiling,
-                                  f"{wl}: {WORKLOADS[wl]}")
+                                  f"{wl}: {WORKLOADS[wl]}", check=check)
             leg["roofline"]["bound"] = "cache-resident"
             leg["roofline"]["note"] = ("the dictionary (%.0f MiB) fits in the 256 MB MALL: "
                                        "the bytes are algorithmic, not HBM traffic"
@@ -786,11 +799,12 @@ def main():
     many = []
     if not args.no_batched:
         log("[bench] batched form (256 signals, shared dictionary)")
-        line["batched"], chk = bench_batched(args.seed, sequential=not args.no_sequential)
+        line["batched"], chk = bench_batched(args.seed, sequential=not args.no_sequential,
+                                             check=check)
         many.append((("batched", "errors"), chk))
     if not args.no_ragged:
         log("[bench] ragged instances (512 problems of uneven size), FP32 and BF16")
-        recs, chks = bench_ragged(args.seed)
+        recs, chks = bench_ragged(args.seed, check=check)
         line["ragged"] = recs["f32"]
         line["ragged_bf16"] = recs["bf16"]
         many.append((("ragged", "errors"), chks["f32"]))
