@@ -66,6 +66,13 @@ TRAFFIC = {
                                                "mp_internal.h")]),
     "omp": (os.path.join(ROOT, "profiles", "omp_select_traffic.json"),
             [os.path.join(_CSRC, f) for f in ("k_omp.hip", "k_common.h", "mp_internal.h")]),
+    # ragged solves: bytes per solve of the 512-instance workload (n = m = 0)
+    "ragged_f32": (os.path.join(ROOT, "profiles", "ragged_f32_traffic.json"),
+                   [os.path.join(_CSRC, f) for f in ("k_ragged.hip", "k_common.h", "k_lowp.h",
+                                                     "mp_internal.h")]),
+    "ragged_bf16": (os.path.join(ROOT, "profiles", "ragged_bf16_traffic.json"),
+                    [os.path.join(_CSRC, f) for f in ("k_ragged.hip", "k_common.h", "k_lowp.h",
+                                                      "mp_internal.h")]),
 }
 ESIZE = {"f64": 8.0, "f32": 4.0, "bf16": 2.0, "fp8": 1.0}
 KERNEL = {"f64": "k_mp_step_f64", "f32": "k_mp_step_f32", "bf16": "k_mp_step_lp",
@@ -365,12 +372,33 @@ def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, re
         iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
                                                       x, r, rescore_k=rescore_k)
         g = traced_decode(dec, y, p, rescore_k=rescore_k) if check else None
+        one_launch = "persistent" in stops
+        stops.discard("persistent")
+        if one_launch:
+            # the same decode with one launch per step, for comparison
+            s_it, s_dt, s_ms, s_n, _ = time_decodes(dec, y, p, steps, warmup, profile_every,
+                                                    x, r, rescore_k=rescore_k,
+                                                    step_launches=True)
     leg = {"workload": workload, "storage": storage,
            "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
            "us_per_iter": round(dt / max(iters, 1) * 1e6, 3),
            "iters_per_decode": iters // max(steps, 1), "stop": sorted(stops),
-           "roofline": hbm_roofline(KERNEL[storage], step_bytes(n, m, storage), avg_ms, kt_n,
-                                    traffic_from_counters(n, m, storage), ceiling)}
+           "one_launch": one_launch}
+    b = step_bytes(n, m, storage)
+    if one_launch:
+        # the whole decode in one launch with the dictionary's shares in LDS:
+        # the time per step, the dictionary bytes per step read from LDS
+        leg["roofline"] = {"bound": "exchange", "kernel": "k_f32_small",
+                           "avg_step_us": round(avg_ms * 1e3, 3), "steps": kt_n,
+                           "lds_bytes_per_step": 4.0 * n * m}
+        leg["step_launches"] = {
+            "iters_per_s": round(s_it / s_dt, 3), "us_per_iter": round(s_dt / max(s_it, 1) * 1e6, 3),
+            "roofline": hbm_roofline(KERNEL[storage], b, s_ms, s_n,
+                                     traffic_from_counters(n, m, storage), ceiling)}
+        leg["one_launch_over_step_launches"] = round((iters / dt) / (s_it / s_dt), 3)
+    else:
+        leg["roofline"] = hbm_roofline(KERNEL[storage], b, avg_ms, kt_n,
+                                       traffic_from_counters(n, m, storage), ceiling)
     return leg, g
 
 
@@ -594,10 +622,13 @@ def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: 
                    roofline={"bound": "hbm", "kernel": "k_ragged", "achieved": round(achieved, 2),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "traffic": traffic_from_counters(0, 0, "ragged_" + storage),
+                             "bytes_per_solve": nbytes,
                              "launch_ms": round(kms, 3),
                              "note": "algorithmic bytes count every instance's dictionary "
-                                     "once per iteration; small dictionaries (0.25-16 MiB) "
-                                     "may be re-read from L2/MALL"})
+                                     "once per iteration; the counters (traffic, bytes per "
+                                     "solve) show the dictionaries read from memory each "
+                                     "time, none re-read from L2"})
         recs[storage] = out
         checks[storage] = {"psis": [p.psi for p in probs], "ys": [p.y for p in probs],
                            "eps": 1e-5, "dict_of": list(range(len(probs))), "g": g}
@@ -790,10 +821,10 @@ def main():
                 q.max_iters = min(q.max_iters, args.max_iters)
             leg, g = bench_single(q, "f32", steps, args.warmup, args.profile_every, ceiling,
                                   f"{wl}: {WORKLOADS[wl]}", check=check)
-            leg["roofline"]["bound"] = "cache-resident"
-            leg["roofline"]["note"] = ("the dictionary (%.0f MiB) fits in the 256 MB MALL: "
-                                       "the bytes are algorithmic, not HBM traffic"
-                                       % (4.0 * q.n * q.m / 2 ** 20))
+            roof = leg["step_launches"]["roofline"] if leg["one_launch"] else leg["roofline"]
+            roof["bound"] = "cache-resident"
+            roof["note"] = ("the dictionary (%.0f MiB) fits in the 256 MB MALL: the bytes are "
+                            "algorithmic, not HBM traffic" % (4.0 * q.n * q.m / 2 ** 20))
             line["small"][wl] = leg
             singles.append((("small", wl, "errors"), q, g, False))
     many = []

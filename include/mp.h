@@ -91,9 +91,10 @@ typedef struct mp_opts {
                              mp_solve_omp; 0 for the others) */
 } mp_opts;
 
-/* mp_opts.flags: decode the one-bit form (MP_SIGN1) with one kernel launch
-   per step even where the whole decode fits one persistent launch (the same
-   results bit for bit; no effect on the other forms). */
+/* mp_opts.flags: decode with one kernel launch per step even where the whole
+   decode fits one persistent launch (the one-bit form MP_SIGN1, and MP_F32
+   contexts whose dictionary fits the LDS of at most 32 workgroups); the same
+   results bit for bit; no effect on the other forms. */
 #define MP_SOLVE_STEP_LAUNCHES 0x1u
 
 typedef struct mp_result {
@@ -173,9 +174,21 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
  *   opts     host: tolerance, cap, re-score count, flags (0 or
  *            MP_SOLVE_STEP_LAUNCHES)
  *   res      host or NULL: iteration count, norms, stop reason, and whether
- *            the decode ran as one persistent launch (one-bit form)
+ *            the decode ran as one persistent launch
  *   trace    host struct of device arrays, or NULL (see mp_trace)
  *   stream   hipStream_t as void*
+ *
+ * An MP_F32 context whose dictionary, split into shares of whole columns,
+ * fits the LDS of at most 32 workgroups beside r (at most 150 KB each, e.g.
+ * N = 256 with M up to 4608) decodes in one persistent launch, each
+ * workgroup keeping its share in LDS and exchanging its best key with the
+ * others through device memory each step (bit-identical to one launch per
+ * step, which MP_SOLVE_STEP_LAUNCHES selects).  That launch needs every
+ * workgroup resident at once: run it on a device no other kernel holds; a
+ * wait between its workgroups that exceeds the poll limit (2^22, or the
+ * non-negative integer in the environment variable MP_SMALL_SPIN_LIMIT, read
+ * at each decode; 0 gives up at the first wait) ends the decode with
+ * MP_EDEVICE.
  *
  * y, x and r must not overlap.  Errors: MP_EINVAL (NULL ctx/y/x/opts, eps < 0
  * or not finite, max_iters < 0, unknown flags, rescore_k outside 0..8),
@@ -192,7 +205,8 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
  * bit-identical results), but the decode's device work buffers (state,
  * residual double buffer, per-workgroup keys, column-share state) live in
  * a static array of 256 KiB that the library holds on each GPU it runs on
- * until the process ends, and the call allocates nothing (no hipMalloc,
+ * until the process ends (the decode always takes one launch per step), and
+ * the call allocates nothing (no hipMalloc,
  * hipFree or allocating library call; the pinned state slots and events it
  * uses were made by mp_create).
  *
@@ -369,7 +383,11 @@ typedef struct mp_ragged_config {
     int32_t threads;        /* workgroup size: 256, 512 or 1024 */
     int32_t cols_per_wave;  /* columns one wave streams at once: 1, 2 or 4 (MP_BF16: 1) */
     int32_t wgs_per_cu;     /* persistent workgroups per compute unit: 1..8 */
-    int32_t reserved;
+    int32_t split;          /* most parts one instance is cut into, 1..8 (0: the default,
+                               2).  An instance whose estimated work (n^2 m) exceeds the
+                               average per workgroup of the launch is decoded by up to
+                               `split` workgroups at once, each streaming a share of its
+                               columns; the parts exchange their candidates every step. */
 } mp_ragged_config;
 
 /*
@@ -395,7 +413,13 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
  * mp_solve_ragged -- decode every instance of a ragged context (the
  * Section 3 loop per instance) in one persistent launch, replayed from a
  * captured HIP graph while the arguments stay the same.  Workgroups take
- * instances largest first; each runs one instance's whole loop.
+ * instances largest first; each runs one instance's whole loop, or one part
+ * of it for an instance cut into parts (mp_ragged_config.split).  The parts
+ * of an instance wait for each other every step: the launch needs at least
+ * `split` of its workgroups resident at once (always so on an MI355X), and
+ * a wait that exceeds the poll limit (2^22, or the non-negative integer in
+ * the environment variable MP_RAGGED_SPIN_LIMIT, read at each call; 0 gives
+ * up at the first wait) ends the call with MP_EDEVICE.
  *
  *   Y        device: the y of all instances packed in instance order
  *            (instance i starts at n_0 + ... + n_{i-1})

@@ -570,7 +570,7 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
     if (k != 0) {
       const int idx = key_index(k);
       if (idx >= 0 && idx < m) {
-        const float c32 = dot_column_f32(
+        const float c32 = dot_column_f32<false>(
             reinterpret_cast<const v4f*>(psi32 + static_cast<int64_t>(idx) * ld), r_lds, ld4,
             lane);
         rk = make_key(c32, idx);

@@ -8,6 +8,8 @@
 // smallest index on ties, eq. 16).  A launch returns at once when the device
 // state says the run has stopped, so the host can enqueue launches ahead
 // without reading anything back.
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "k_common.h"
@@ -188,6 +190,191 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
   if (threadIdx.x == 0) k_out[blockIdx.x] = best;
   record_pass_time(bal, par, t_begin);
 }
+
+// ---------------------------------------------------------------------------
+// Small dictionaries: the whole decode in one launch of G <= kSmallMaxWgs
+// workgroups (one per CU), each holding its share of the columns in LDS for
+// the whole decode, so a step reads no dictionary bytes from memory.
+//
+// Step k does what launch k of k_mp_step_f32 does, with the same code for
+// the selection (the largest key of all workgroups, eq. 16), the update
+// (carried_update: every workgroup applies step k to its own LDS copy of r
+// and sums ||r_k||^2 in FP64 in the same order; workgroup 0 also keeps r,
+// x~, the trace and the state) and the correlations (dot_column_f32 over
+// the column's LDS copy, the same FMAs in the same order as over its copy in
+// memory), so results are bit-identical to the stepping form; which
+// workgroup scores a column does not change its correlation.  In place of
+// the kernel boundary, each workgroup publishes its best key of pass k as
+// two 64-bit words, each a 32-bit tag (decode epoch, step) over 32 bits of
+// the key, with relaxed device-scope atomics, and reads every workgroup's
+// words of the pass before it goes on; steps alternate between two halves
+// of the slots (a workgroup overwrites its words of pass k only after
+// reading every record of pass k+1, each of which its owner published
+// after reading every record of pass k).  The epoch, new for every decode,
+// keeps words of an earlier decode from matching.
+//
+// Every wait ends: the host launches this form only where the occupancy
+// query shows every workgroup resident at once (one per CU, G <= CUs), all
+// workgroups take the same decisions from the same gathered keys, and a
+// wait that has polled `spin_limit` times in vain sets the sticky
+// DevState::fail word and leaves, after which every other workgroup's wait
+// gives up too.
+constexpr int kSmallLds = 150 * 1024;  // dynamic LDS for r and a share, at most
+constexpr int kSmallMaxWgs = 32;
+constexpr unsigned kSmallEpochMod = 4096;
+
+__global__ __launch_bounds__(kCorrThreads) void k_f32_small(
+    const float* __restrict__ psi, int64_t ld, int64_t n, int64_t m, float* __restrict__ rbuf,
+    int cols_per_wg, unsigned long long* __restrict__ slots, unsigned epoch,
+    long long spin_limit, long long max_iters, float* __restrict__ x,
+    DevState* __restrict__ st, mp_trace tr) {
+  extern __shared__ v4f smem[];  // r (ld4 float4s), then the share's columns
+  __shared__ uint64_t kred[kCorrThreads / kWave];
+  __shared__ double dred[kCorrThreads / kWave];
+  __shared__ int s_flag;
+  const int ld4 = static_cast<int>(ld / 4);
+  const int G = static_cast<int>(gridDim.x);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  v4f* r_lds = smem;
+  v4f* cols = smem + ld4;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * cols_per_wg;
+  int64_t col1 = col0 + cols_per_wg;
+  if (col1 > m) col1 = m;
+  const unsigned ep = (epoch % kSmallEpochMod) << 20;
+
+  if (threadIdx.x == 0)
+    s_flag = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double thr = st->thr;
+  // r = y (half 0, written by the init kernel) and the share's columns into LDS
+  const v4f* r_in = reinterpret_cast<const v4f*>(rbuf);
+  for (int i = threadIdx.x; i < ld4; i += kCorrThreads) r_lds[i] = r_in[i];
+  {
+    const v4f* src = reinterpret_cast<const v4f*>(psi + col0 * ld);
+    const int total = static_cast<int>(col1 - col0) * ld4;
+    for (int i = threadIdx.x; i < total; i += kCorrThreads) cols[i] = src[i];
+  }
+  __syncthreads();
+  if (s_flag) return;  // the init kernel stopped the run (zero or non-finite y, T = 0, ...)
+  __syncthreads();     // s_flag is reused below
+  if (threadIdx.x == 0) s_flag = 0;
+  v4f* r_out = reinterpret_cast<v4f*>(rbuf + ld);  // workgroup 0 keeps r_k here (half 1)
+
+  for (long long k = 0;; ++k) {
+    if (k > 0) {
+      // every workgroup's key of pass k (published with step field k)
+      uint64_t kp = 0;
+      if (static_cast<int>(threadIdx.x) < G) {
+        const unsigned want = ep | (static_cast<unsigned>(k) & 0xFFFFFu);
+        unsigned long long* w0 = slots + ((k & 1) * kSmallMaxWgs + threadIdx.x) * 2;
+        long long spins = 0;
+        unsigned long long hi = 0, lo = 0;
+        for (;;) {
+          if (spins >= spin_limit) {  // spin_limit polls have failed (0: none is made)
+            s_flag = 1;
+            break;
+          }
+          lo = __hip_atomic_load(w0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (static_cast<unsigned>(lo >> 32) == want) {
+            hi = __hip_atomic_load(w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (static_cast<unsigned>(hi >> 32) == want) break;
+          }
+          ++spins;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        kp = ((hi & 0xFFFFFFFFull) << 32) | (lo & 0xFFFFFFFFull);
+      }
+      __syncthreads();
+      if (s_flag) {
+        if (threadIdx.x == 0) {
+          (void)__hip_atomic_fetch_or(&st->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+      }
+      const uint64_t win = block_max<kCorrThreads>(kp, kred);
+      const int idx = key_index(win);
+      const float c = key_value(win);
+      if (carried_winner_stops(idx, c, m, st)) return;
+      if (carried_update<kCorrThreads>(idx, c, psi, ld, n, r_lds, r_out, x, st, tr, k, max_iters,
+                                       thr, 1, dred))
+        return;
+    }
+    // pass k+1 over the share, from LDS
+    uint64_t best = 0;
+    for (int64_t col = col0 + wave; col < col1; col += kCorrThreads / kWave) {
+      const float cv = dot_column_f32<false>(cols + (col - col0) * ld4, r_lds, ld4, lane);
+      const uint64_t key = make_key(cv, static_cast<int>(col));
+      best = key > best ? key : best;
+    }
+    best = block_max<kCorrThreads>(best, kred);
+    if (threadIdx.x == 0) {
+      const unsigned long long tag =
+          static_cast<unsigned long long>(ep | (static_cast<unsigned>(k + 1) & 0xFFFFFu)) << 32;
+      unsigned long long* w0 = slots + (((k + 1) & 1) * kSmallMaxWgs + blockIdx.x) * 2;
+      __hip_atomic_store(w0, tag | (best >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(w0 + 1, tag | (best & 0xFFFFFFFFull), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Launch shape of the small-dictionary decode for an FP32 context, or
+// grid 0 where it does not apply (the share and r must fit the LDS limit,
+// at most kSmallMaxWgs workgroups, all resident at once).
+CorrGeom small_geometry(int64_t ld, int64_t m, int num_cus) {
+  CorrGeom g{0, 0};
+  constexpr int64_t kWaves = kCorrThreads / kWave;
+  const int64_t room = (kSmallLds - 4 * ld) / (4 * ld);  // columns that fit beside r
+  if (room < kWaves || ld > 16384) return g;
+  const int64_t cap = room / kWaves * kWaves;
+  int64_t grid = (m + cap - 1) / cap;
+  if (grid > kSmallMaxWgs || grid > num_cus) return g;
+  int64_t cpw = (m + grid - 1) / grid;
+  cpw = (cpw + kWaves - 1) / kWaves * kWaves;  // a whole number of columns per wave
+  grid = (m + cpw - 1) / cpw;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_f32_small),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLds) != hipSuccess)
+      return g;
+    attr_set = true;
+  }
+  int per_cu = 0;
+  const size_t lds = static_cast<size_t>(4 * ld * (cpw + 1));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(
+                                                       k_f32_small),
+                                                   kCorrThreads, lds) != hipSuccess ||
+      per_cu < 1)
+    return g;
+  g.cols_per_wg = static_cast<int>(cpw);
+  g.grid = static_cast<int>(grid);
+  return g;
+}
+
+hipError_t launch_f32_small(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
+                            const CorrGeom& g, unsigned long long* slots, unsigned epoch,
+                            long long max_iters, float* x, DevState* st, mp_trace tr,
+                            hipStream_t s) {
+  if (g.grid < 1 || g.grid > kSmallMaxWgs) return hipErrorInvalidValue;
+  // polls per wait before the run is marked failed; MP_SMALL_SPIN_LIMIT (a
+  // non-negative integer; 0 gives up at the first wait) overrides it, so
+  // that tests can drive the failure path
+  long long spin_limit = 1ll << 22;
+  if (const char* env = getenv("MP_SMALL_SPIN_LIMIT")) {
+    char* end = nullptr;
+    const long long v = strtoll(env, &end, 10);
+    if (end != env && v >= 0) spin_limit = v;
+  }
+  const size_t lds = static_cast<size_t>(4 * ld * (g.cols_per_wg + 1));
+  if (lds > static_cast<size_t>(kSmallLds)) return hipErrorInvalidValue;
+  k_f32_small<<<dim3(g.grid), dim3(kCorrThreads), lds, s>>>(psi, ld, n, m, rbuf, g.cols_per_wg,
+                                                            slots, epoch, spin_limit, max_iters,
+                                                            x, st, tr);
+  return hipGetLastError();
+}
+
+unsigned small_epoch_mod() { return kSmallEpochMod; }
+int small_max_wgs() { return kSmallMaxWgs; }
 
 // The first n floats of the residual half the state names (st->r_sel) into
 // r: the end of a carried decode, one launch instead of a host round trip.

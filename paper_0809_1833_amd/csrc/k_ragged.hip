@@ -1,13 +1,29 @@
 // Many independent Matching Pursuit problems of uneven size in one launch.
 //
 // Every instance has its own dictionary and signal.  A persistent grid of
-// workgroups takes instances from an on-device queue (largest first, as the
-// host ordered them) and each workgroup runs one instance's whole Section 3
-// loop (eqs. 8-12) by itself: the residual stays in LDS, the correlation
-// pass streams the instance's dictionary with every wave taking CC columns at
-// a time, and the argmax (smallest index on ties, eq. 16), the x~ and r
-// updates and the FP64 stopping test use only workgroup barriers.  No
-// workgroup ever waits for another one; each exits when the queue is empty.
+// workgroups takes items from an on-device work list (largest first, as the
+// host ordered them) and runs one instance's whole Section 3 loop (eqs. 8-12)
+// for each: the residual stays in LDS, the correlation pass streams the
+// instance's dictionary with every wave taking CC columns at a time, and the
+// argmax (smallest index on ties, eq. 16), the x~ and r updates and the FP64
+// stopping test use only workgroup barriers.  An instance whose work would
+// hold one workgroup far longer than the average item is cut by the host
+// into `parts` consecutive items, one per column share: every part keeps the
+// whole residual, streams its own columns and, each step, publishes its best
+// candidates (FP32: one key; BF16: its 8 best) as self-tagged 64-bit words
+// (32-bit tag = step + 1 over 32 bits of a key, relaxed device-scope
+// atomics) and reads its siblings' words of the same step, so that every
+// part takes the same winner and applies the same update with the same
+// arithmetic (part 0 alone writes x~, the trace, r and the result).  Steps
+// alternate between two halves of the instance's record slot: a part
+// overwrites its words of step t only after reading every record of step
+// t + 1, each published after its owner read every record of step t.  The
+// slots are cleared before every decode.  Results do not depend on the
+// split.  Every wait ends: the parts of an instance are consecutive in the
+// list, so whenever the workgroups resident at once outnumber the parts of
+// one instance, some complete group of parts is running; and a wait that
+// polls `spin_limit` times in vain sets the queue's fail word and leaves the
+// instance, after which its siblings' waits give up too.
 //
 // With BF16 storage each wave keeps the 8 best reduced-precision candidates
 // of its columns; the workgroup merges them, re-scores up to 8 against the
@@ -59,19 +75,80 @@ __device__ inline void dot_cols_f32(const v4f* const (&p)[CC], const v4f* __rest
   for (int c = 0; c < CC; ++c) acc[c] = wave_sum(acc[c]);
 }
 
-__global__ void k_ragged_reset(RQueue* q) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) q->next = 0u;
+// Before a decode: the work list from its start, no failure, record slots
+// zero (a plain fill, so that the decode can be captured in a graph).
+__global__ __launch_bounds__(256) void k_ragged_reset(RQueue* q, unsigned long long* slots,
+                                                      int64_t nwords) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    q->next = 0u;
+    q->fail = 0;
+  }
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < nwords; i += stride)
+    slots[i] = 0ull;
+}
+
+// Publish this part's record of step t (kTopK keys in lanes 0..kTopK-1 of
+// wave 0, or one key in lane 0) and gather the parts' records into lanes
+// (part * kTopK + j) of wave 0; keys past a part's count are 0.  Called by
+// wave 0 only.  Returns false when a wait gave up (the queue's fail word is
+// then set).
+template <int K>
+__device__ inline bool ragged_exchange(uint64_t mine, int lane, int part, int parts,
+                                       unsigned long long* __restrict__ rec, long long t,
+                                       long long spin_limit, RQueue* __restrict__ q,
+                                       uint64_t& got) {
+  const unsigned long long tag = static_cast<unsigned long long>(static_cast<unsigned>(t + 1))
+                                 << 32;
+  unsigned long long* half = rec + (t & 1) * kRaggedMaxParts * kRaggedRecWords;
+  if (lane < K) {
+    unsigned long long* w = half + part * kRaggedRecWords + 2 * lane;
+    __hip_atomic_store(w, tag | (mine >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, tag | (mine & 0xFFFFFFFFull), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  got = 0;
+  bool ok = true;
+  const int pq = lane / K, j = lane % K;
+  if (pq < parts && (K > 1 || lane < parts)) {
+    unsigned long long* w = half + pq * kRaggedRecWords + 2 * j;
+    long long spins = 0;
+    for (;;) {
+      if (spins >= spin_limit) {
+        ok = false;
+        break;
+      }
+      const unsigned long long lo = __hip_atomic_load(w + 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+      if ((lo >> 32) == (tag >> 32)) {
+        const unsigned long long hi = __hip_atomic_load(w, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        if ((hi >> 32) == (tag >> 32)) {
+          got = ((hi & 0xFFFFFFFFull) << 32) | (lo & 0xFFFFFFFFull);
+          break;
+        }
+      }
+      ++spins;
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  ok = __all(ok);
+  if (!ok && lane == 0)
+    (void)__hip_atomic_fetch_or(&q->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return ok;
 }
 
 template <int NT, int CC, bool LP>
 __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
-                                               const int* __restrict__ order, int count,
+                                               const RItem* __restrict__ items, int nitems,
                                                const float* __restrict__ Y,
                                                float* __restrict__ X, float* __restrict__ R,
                                                const long long* __restrict__ caps,
                                                long long cap_all, double eps, int rescore_k,
                                                RResult* __restrict__ res,
-                                               RQueue* __restrict__ q, mp_trace tr) {
+                                               RQueue* __restrict__ q,
+                                               unsigned long long* __restrict__ slots,
+                                               long long spin_limit, mp_trace tr) {
   constexpr int W = NT / kWave;
   extern __shared__ v4f r_lds[];
   float* rf = reinterpret_cast<float*>(r_lds);
@@ -80,7 +157,8 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
   __shared__ uint64_t lists[16 * kTopK];  // LP: per-wave top-8 lists (zero padded)
   __shared__ uint64_t cand[kTopK];
   __shared__ uint64_t resc[kTopK];
-  __shared__ int s_item;
+  __shared__ uint64_t s_best;
+  __shared__ int s_item, s_ok;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
 
   for (;;) {
@@ -90,16 +168,24 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
     __syncthreads();
     const int item = s_item;
     __syncthreads();  // s_item is rewritten next time round
-    if (item >= count) break;
-    const int id = order[item];
+    if (item >= nitems) break;
+    const RItem it = items[item];
+    const int id = it.id, part = it.part, parts = it.parts;
     const RInst d = inst[id];
     const int64_t n = d.n, m = d.m, ld = d.ld;
     const int ld4 = static_cast<int>(ld / 4);
     const float* y = Y + d.y_off;
     float* x = X + d.x_off;
+    // this part's columns
+    const int64_t cb = m * part / parts, ce = m * (part + 1) / parts;
+    unsigned long long* rec =
+        parts > 1 ? slots + static_cast<int64_t>(it.slot) * 2 * kRaggedMaxParts * kRaggedRecWords
+                  : nullptr;
+    const bool lead = part == 0;  // writes x~, the trace, r and the result
 
     // ---- init (eq. 8) ----
-    for (int64_t j = threadIdx.x; j < m; j += NT) x[j] = 0.0f;
+    if (lead)
+      for (int64_t j = threadIdx.x; j < m; j += NT) x[j] = 0.0f;
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < ld; i += NT) {
       const float v = i < n ? y[i] : 0.0f;
@@ -126,32 +212,51 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
           reason = MP_STOP_MAX_ITERS;
           break;
         }
-        // ---- correlation pass (eq. 9) and argmax ----
+        // ---- correlation pass (eq. 9) over this part's columns and argmax ----
         uint64_t best = 0;
         if constexpr (!LP) {
-          for (int64_t c0 = static_cast<int64_t>(wave) * CC; c0 < m; c0 += W * CC) {
+          for (int64_t c0 = cb + static_cast<int64_t>(wave) * CC; c0 < ce; c0 += W * CC) {
             const v4f* p[CC];
 #pragma unroll
             for (int c = 0; c < CC; ++c)
-              p[c] = reinterpret_cast<const v4f*>(d.psi32 + (c0 + c < m ? c0 + c : c0) * ld);
+              p[c] = reinterpret_cast<const v4f*>(d.psi32 + (c0 + c < ce ? c0 + c : c0) * ld);
             float acc[CC];
             dot_cols_f32<CC>(p, r_lds, ld4, lane, acc);
 #pragma unroll
             for (int c = 0; c < CC; ++c) {
-              if (c0 + c < m) {
+              if (c0 + c < ce) {
                 const uint64_t k = make_key(acc[c], static_cast<int>(c0 + c));
                 best = k > best ? k : best;
               }
             }
           }
           best = block_max<NT>(best, kred);
+          if (parts > 1) {
+            // the siblings' best keys of this step; the largest is the winner
+            if (wave == 0) {
+              uint64_t got = 0;
+              const bool ok = ragged_exchange<1>(best, lane, part, parts, rec, t, spin_limit, q,
+                                                 got);
+              const uint64_t win = wave_max(got);
+              if (lane == 0) {
+                s_best = win;
+                s_ok = ok ? 1 : 0;
+              }
+            }
+            __syncthreads();
+            best = s_best;
+            if (!s_ok) {
+              reason = kStopInternal;
+              break;
+            }
+          }
         } else {
           const int nq = static_cast<int>(ld * 2 / 16);
           const v4u* pq = reinterpret_cast<const v4u*>(d.psib);
           uint64_t L[kTopK];
 #pragma unroll
           for (int j = 0; j < kTopK; ++j) L[j] = 0;
-          for (int64_t col = wave; col < m; col += W)
+          for (int64_t col = cb + wave; col < ce; col += W)
             top8_insert(L, make_key(dot_column_lp<2>(pq + col * nq, r_lds, nq, lane),
                                     static_cast<int>(col)));
           uint64_t v = 0;
@@ -163,17 +268,31 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
             for (int k = W * kTopK + lane; k < 16 * kTopK; k += kWave) lists[k] = 0;
           __syncthreads();
           if (wave == 0) {
-            const uint64_t c8 = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
+            uint64_t c8 = top8_of_lists16(lists[lane], lists[lane + kWave], lane);
+            int ok = 1;
+            if (parts > 1) {
+              // the siblings' 8 best of this step, lanes 8 p + j, merged into
+              // the instance's 8 best
+              uint64_t got = 0;
+              ok = ragged_exchange<kTopK>(c8, lane, part, parts, rec, t, spin_limit, q, got)
+                       ? 1 : 0;
+              c8 = top8_of_lists16(got, 0ull, lane);
+            }
             if (lane < kTopK) cand[lane] = c8;
+            if (lane == 0) s_ok = ok;
           }
           __syncthreads();
+          if (parts > 1 && !s_ok) {
+            reason = kStopInternal;
+            break;
+          }
           for (int qd = wave; qd < rescore_k; qd += W) {
             const uint64_t k = cand[qd];
             uint64_t rk = 0;
             if (k != 0) {
               const int idx = key_index(k);
               if (idx >= 0 && idx < m) {
-                const float c32 = dot_column_f32(
+                const float c32 = dot_column_f32<false>(
                     reinterpret_cast<const v4f*>(d.psi32 + static_cast<int64_t>(idx) * ld),
                     r_lds, ld4, lane);
                 rk = make_key(c32, idx);
@@ -196,7 +315,7 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
         }
         // ---- update (eqs. 10-12); every wave is past the pass (barrier above) ----
         const float* colp = d.psi32 + static_cast<int64_t>(idx) * ld;
-        float* rt = tr.r && t < tr.cap
+        float* rt = lead && tr.r && t < tr.cap
                         ? tr.r + (static_cast<int64_t>(id) * tr.cap + t) * tr.ldr : nullptr;
         s = 0.0;
         for (int64_t i = threadIdx.x; i < n; i += NT) {
@@ -206,7 +325,7 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
           s += static_cast<double>(vv) * vv;
         }
         rr = block_sum<NT>(s, dred);  // its barriers publish the new r to all waves
-        if (threadIdx.x == 0) {
+        if (lead && threadIdx.x == 0) {
           x[idx] += c;
           if (t < tr.cap) {
             const int64_t o = static_cast<int64_t>(id) * tr.cap + t;
@@ -218,9 +337,9 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
         ++t;
       }
     }
-    if (R)
+    if (R && lead)
       for (int64_t i = threadIdx.x; i < n; i += NT) R[d.y_off + i] = rf[i];
-    if (threadIdx.x == 0) {
+    if (lead && threadIdx.x == 0) {
       RResult o;
       o.t = t;
       o.yy = yy;
@@ -236,14 +355,16 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
 // ---------------------------------------------------------------------------
 
 template <int NT, int CC, bool LP>
-static hipError_t launch_ragged_t(int grid, size_t lds, const RInst* inst, const int* order,
-                                  int count, const float* Y, float* X, float* R,
+static hipError_t launch_ragged_t(int grid, size_t lds, const RInst* inst, const RItem* items,
+                                  int nitems, const float* Y, float* X, float* R,
                                   const long long* caps, long long cap_all, double eps,
-                                  int rescore_k, RResult* res, RQueue* q, mp_trace tr,
+                                  int rescore_k, RResult* res, RQueue* q,
+                                  unsigned long long* slots, long long spin_limit, mp_trace tr,
                                   hipStream_t s) {
   // instances have n <= 8192, so the residual needs at most 32 KB of LDS
-  k_ragged<NT, CC, LP><<<dim3(grid), dim3(NT), lds, s>>>(inst, order, count, Y, X, R, caps,
-                                                         cap_all, eps, rescore_k, res, q, tr);
+  k_ragged<NT, CC, LP><<<dim3(grid), dim3(NT), lds, s>>>(inst, items, nitems, Y, X, R, caps,
+                                                         cap_all, eps, rescore_k, res, q, slots,
+                                                         spin_limit, tr);
   return hipGetLastError();
 }
 
@@ -252,20 +373,26 @@ bool ragged_config_valid(const RConfig& cf, bool lp) {
   const bool cc_ok = lp ? cf.cols_per_wave == 1
                         : (cf.cols_per_wave == 1 || cf.cols_per_wave == 2 ||
                            cf.cols_per_wave == 4);
-  return nt_ok && cc_ok && cf.wgs_per_cu >= 1 && cf.wgs_per_cu <= 8;
+  return nt_ok && cc_ok && cf.wgs_per_cu >= 1 && cf.wgs_per_cu <= 8 && cf.split >= 1 &&
+         cf.split <= kRaggedMaxParts;
 }
 
 hipError_t launch_ragged(const RConfig& cf, bool lp, int grid, size_t lds, const RInst* inst,
-                         const int* order, int count, const float* Y, float* X, float* R,
+                         const RItem* items, int nitems, const float* Y, float* X, float* R,
                          const long long* caps, long long cap_all, double eps, int rescore_k,
-                         RResult* res, RQueue* q, mp_trace tr, hipStream_t s) {
-  k_ragged_reset<<<dim3(1), dim3(64), 0, s>>>(q);
+                         RResult* res, RQueue* q, unsigned long long* slots, int nslots,
+                         long long spin_limit, mp_trace tr, hipStream_t s) {
+  const int64_t nwords = static_cast<int64_t>(nslots) * 2 * kRaggedMaxParts * kRaggedRecWords;
+  int64_t rb = (nwords + 255) / 256;
+  rb = rb < 1 ? 1 : (rb > 256 ? 256 : rb);
+  k_ragged_reset<<<dim3(static_cast<unsigned>(rb)), dim3(256), 0, s>>>(q, slots, nwords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 #define MP_RAGGED_CASE(NT, CC, LP)                                                          \
   if (cf.threads == NT && cf.cols_per_wave == CC && lp == LP)                               \
-    return launch_ragged_t<NT, CC, LP>(grid, lds, inst, order, count, Y, X, R, caps,         \
-                                       cap_all, eps, rescore_k, res, q, tr, s);
+    return launch_ragged_t<NT, CC, LP>(grid, lds, inst, items, nitems, Y, X, R, caps,        \
+                                       cap_all, eps, rescore_k, res, q, slots, spin_limit, tr, \
+                                       s);
   MP_RAGGED_CASE(256, 1, false)
   MP_RAGGED_CASE(256, 2, false)
   MP_RAGGED_CASE(256, 4, false)

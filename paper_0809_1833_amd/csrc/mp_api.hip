@@ -19,6 +19,8 @@ thread_local std::string g_create_error;
 constexpr int64_t kMaxN = 16384;          // the residual is staged whole in LDS
 constexpr int64_t kMaxSignN = 16384;      // two 16-byte chunks of a column per lane
 constexpr int64_t kMaxRaggedN = 8192;     // per-instance residual in LDS, 32 KB
+constexpr int kMaxRaggedSplit = 4096;     // instances cut into parts, at most
+constexpr int kRaggedDefaultSplit = 2;    // parts of an instance, at most, unless configured
 constexpr int64_t kLdAlign = 64;          // padded column length (floats): 256 B aligned
 constexpr int kMaxChunk = 64;             // iterations enqueued per host check
 constexpr double kNormTol = 1e-4;
@@ -66,7 +68,9 @@ void free_ragged(mp_ctx* c) {
   (void)hipFree(c->r_psi32);
   (void)hipFree(c->r_psib);
   (void)hipFree(c->r_inst);
-  (void)hipFree(c->r_order);
+  (void)hipFree(c->r_items);
+  (void)hipFree(c->r_slots);
+  if (c->h_rq) (void)hipHostFree(c->h_rq);
   (void)hipFree(c->r_caps);
   (void)hipFree(c->r_res);
   (void)hipFree(c->r_queue);
@@ -106,6 +110,7 @@ void free_ctx(mp_ctx* c) {
   (void)hipFree(c->sign_r64);
   (void)hipFree(c->sign_rrp);
   (void)hipFree(c->sign_slots);
+  (void)hipFree(c->small_slots);
   (void)hipFree(c->scales);
   (void)hipFree(c->r_work);
   (void)hipFree(c->st);
@@ -349,9 +354,40 @@ mp_status finish_result(mp_ctx* c, mp_result* res);
 // Allocates nothing: every buffer is in `b`, the context (pinned state slots
 // and events made at its creation) or the caller's arguments.
 mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_opts* opts,
-                        mp_result* res, const mp_trace& tr, hipStream_t s, const CarriedBufs& b) {
+                        mp_result* res, const mp_trace& tr, hipStream_t s, const CarriedBufs& b,
+                        bool allow_one_launch) {
   HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, b.r_work, b.st, opts->eps,
                              static_cast<long long>(opts->max_iters), s));
+  if (allow_one_launch && c->storage == MP_F32 && c->small.grid > 0 &&
+      !(opts->flags & MP_SOLVE_STEP_LAUNCHES)) {
+    // the whole decode in one launch, every share of the dictionary in LDS:
+    // a new tag epoch for every decode (never 0 mod the epoch range: the
+    // zeroed words match no step); when it wraps, clear the words so that
+    // none left from a decode that many decodes ago can match
+    c->small_epoch = c->small_epoch % (mp::small_epoch_mod() - 1) + 1;
+    if (c->small_epoch == 1)
+      HIP_TRY(c, hipMemsetAsync(c->small_slots, 0,
+                                sizeof(unsigned long long) * 2 * 2 * mp::small_max_wgs(), s));
+    if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    HIP_TRY(c, mp::launch_f32_small(c->psi32, c->ld, c->n, c->m, b.r_work, c->small,
+                                    c->small_slots, c->small_epoch, opts->max_iters, x, b.st, tr,
+                                    s));
+    if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    if (r) HIP_TRY(c, mp::launch_copy_selected(b.r_work, c->ld, c->n, b.st, r, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_st, b.st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->profiling) {
+      // the launch time per step taken (t steps, t passes)
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) {
+        c->prof_ms = ms;
+        c->prof_launches = c->h_st->t > 0 ? c->h_st->t : 1;
+      }
+    }
+    const mp_status fs = finish_result(c, res);
+    if (fs == MP_OK && res) res->persistent = 1;
+    return fs;
+  }
   long long k = 0;
   const long long T = opts->max_iters;
   const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
@@ -467,6 +503,16 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
     return bail(MP_ENOMEM, "partials");
   if (hipMalloc(&c->bal, sizeof(mp::BalState)) != hipSuccess) return bail(MP_ENOMEM, "shares");
   if (!make_host_state(c)) return bail(MP_ENOMEM, "pinned state");
+  // the one-launch decode of small FP32 dictionaries (every share in LDS)
+  if (storage == MP_F32) {
+    c->small = mp::small_geometry(c->ld, m, c->num_cus);
+    if (c->small.grid > 0) {
+      const size_t bytes = sizeof(unsigned long long) * 2 * 2 * mp::small_max_wgs();
+      if (hipMalloc(&c->small_slots, bytes) != hipSuccess) return bail(MP_ENOMEM, "step records");
+      if (hipMemsetAsync(c->small_slots, 0, bytes, s) != hipSuccess)
+        return bail(MP_EDEVICE, "step records");
+    }
+  }
   // set-up of mp_solve_noalloc's scratch on this device (the entry point
   // looks it up itself if this fails)
   {
@@ -587,7 +633,7 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
 
   if (c->storage != MP_SIGN1)
     return solve_carried(c, y, x, r, opts, res, tr, s,
-                         CarriedBufs{c->st, c->r_work, c->partials, c->bal});
+                         CarriedBufs{c->st, c->r_work, c->partials, c->bal}, true);
 
   HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, c->r_work, c->st, opts->eps,
                              static_cast<long long>(opts->max_iters), s));
@@ -693,7 +739,8 @@ mp_status mp_solve_noalloc(mp_ctx* ctx, const float* y, float* x, float* r, cons
                        CarriedBufs{reinterpret_cast<mp::DevState*>(b),
                                    reinterpret_cast<float*>(b + mp::kNoAllocR),
                                    reinterpret_cast<uint64_t*>(b + mp::kNoAllocKeys),
-                                   reinterpret_cast<mp::BalState*>(b + mp::kNoAllocBal)});
+                                   reinterpret_cast<mp::BalState*>(b + mp::kNoAllocBal)},
+                       false);
 }
 
 static mp_status ensure_omp(mp_ctx* c, int64_t tq) {
@@ -1214,8 +1261,12 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
     return bail(MP_ENOMEM, "dictionary copies");
   if (storage == MP_BF16 && hipMalloc(&c->r_psib, sizeof(uint16_t) * elems) != hipSuccess)
     return bail(MP_ENOMEM, "BF16 copies");
+  const int64_t max_split = std::min<int64_t>(count, kMaxRaggedSplit);
   if (hipMalloc(&c->r_inst, sizeof(mp::RInst) * count) != hipSuccess ||
-      hipMalloc(&c->r_order, sizeof(int) * count) != hipSuccess ||
+      hipMalloc(&c->r_items, sizeof(mp::RItem) * count * mp::kRaggedMaxParts) != hipSuccess ||
+      hipMalloc(&c->r_slots, sizeof(unsigned long long) * max_split * 2 * mp::kRaggedMaxParts *
+                                 mp::kRaggedRecWords) != hipSuccess ||
+      hipHostMalloc(&c->h_rq, sizeof(mp::RQueue), hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&c->r_caps, sizeof(long long) * count) != hipSuccess ||
       hipMalloc(&c->r_res, sizeof(mp::RResult) * count) != hipSuccess ||
       hipMalloc(&c->r_queue, sizeof(mp::RQueue)) != hipSuccess ||
@@ -1271,17 +1322,16 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
     desc[i].psi32 = c->r_psi32 + psi_off[i];
     desc[i].psib = storage == MP_BF16 ? c->r_psib + psi_off[i] : nullptr;
   }
-  // most work first (iterations grow with n, a pass costs n * m)
-  std::vector<int> order(static_cast<size_t>(count));
-  for (int64_t i = 0; i < count; ++i) order[i] = static_cast<int>(i);
-  std::stable_sort(order.begin(), order.end(), [&](int a1, int b1) {
-    const double wa = static_cast<double>(desc[a1].n) * desc[a1].n * desc[a1].m;
-    const double wb = static_cast<double>(desc[b1].n) * desc[b1].n * desc[b1].m;
-    return wa > wb;
-  });
+  // most work first (iterations grow with n, a pass costs n * m); the work
+  // list itself is built per launch shape (ragged_items)
+  c->r_est.resize(count);
+  for (int64_t i = 0; i < count; ++i)
+    c->r_est[i] = static_cast<double>(desc[i].n) * desc[i].n * desc[i].m;
+  c->r_order.resize(count);
+  for (int64_t i = 0; i < count; ++i) c->r_order[i] = static_cast<int>(i);
+  std::stable_sort(c->r_order.begin(), c->r_order.end(),
+                   [&](int a1, int b1) { return c->r_est[a1] > c->r_est[b1]; });
   e = hipMemcpyAsync(c->r_inst, desc.data(), sizeof(mp::RInst) * count, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(c->r_order, order.data(), sizeof(int) * count, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
   *out = c;
@@ -1291,10 +1341,11 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
 mp_status mp_ragged_set_config(mp_ctx* ctx, const mp_ragged_config* cfg) {
   if (!ctx || !cfg) return MP_EINVAL;
   if (!ctx->ragged) return fail(ctx, MP_EINVAL, "not a ragged context");
-  mp::RConfig cf{cfg->threads, cfg->cols_per_wave, cfg->wgs_per_cu};
+  mp::RConfig cf{cfg->threads, cfg->cols_per_wave, cfg->wgs_per_cu,
+                 cfg->split == 0 ? kRaggedDefaultSplit : cfg->split};
   if (!mp::ragged_config_valid(cf, ctx->storage == MP_BF16))
     return fail(ctx, MP_EINVAL, "threads must be 256/512/1024, cols_per_wave 1/2/4 (BF16: 1), "
-                                "wgs_per_cu 1..8");
+                                "wgs_per_cu 1..8, split 0..8");
   ctx->r_cfg = cf;
   return MP_OK;
 }
@@ -1304,7 +1355,39 @@ mp_status mp_ragged_get_config(const mp_ctx* ctx, mp_ragged_config* cfg) {
   cfg->threads = ctx->r_cfg.threads;
   cfg->cols_per_wave = ctx->r_cfg.cols_per_wave;
   cfg->wgs_per_cu = ctx->r_cfg.wgs_per_cu;
-  cfg->reserved = 0;
+  cfg->split = ctx->r_cfg.split;
+  return MP_OK;
+}
+
+// The work list for the current launch shape: instances most work first; an
+// instance whose work exceeds the average per workgroup of the grid is cut
+// into parts (at most cfg.split, each a share of its columns; at most
+// kMaxRaggedSplit instances are cut), consecutive in the list.
+static mp_status ragged_items(mp_ctx* c, int grid, hipStream_t s) {
+  if (c->r_nitems > 0 && memcmp(&c->r_items_cfg, &c->r_cfg, sizeof(mp::RConfig)) == 0)
+    return MP_OK;
+  double total = 0.0;
+  for (double w : c->r_est) total += w;
+  const double target = total / std::max(grid, 1);
+  std::vector<mp::RItem> items;
+  items.reserve(c->r_count * 2);
+  int nslots = 0;
+  for (int id : c->r_order) {
+    int parts = 1;
+    if (c->r_cfg.split > 1 && nslots < kMaxRaggedSplit && target > 0.0) {
+      const double want = std::ceil(c->r_est[id] / target);
+      parts = static_cast<int>(std::min<double>(want, c->r_cfg.split));
+      parts = std::max(1, std::min<int>(parts, static_cast<int>(c->r_m[id])));
+    }
+    const int slot = parts > 1 ? nslots++ : -1;
+    for (int p = 0; p < parts; ++p) items.push_back(mp::RItem{id, p, parts, slot});
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->r_items, items.data(), sizeof(mp::RItem) * items.size(),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->r_nitems = static_cast<int>(items.size());
+  c->r_nslots = nslots;
+  c->r_items_cfg = c->r_cfg;
   return MP_OK;
 }
 
@@ -1338,17 +1421,28 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
     HIP_TRY(c, hipMemcpyAsync(c->r_caps, max_iters, sizeof(long long) * c->r_count,
                               hipMemcpyHostToDevice, s));
   int grid = c->num_cus * c->r_cfg.wgs_per_cu;
-  if (grid > c->r_count) grid = static_cast<int>(c->r_count);
+  if (mp_status is = ragged_items(c, grid, s); is != MP_OK) return is;
+  if (grid > c->r_nitems) grid = c->r_nitems;
   const size_t lds = static_cast<size_t>(c->r_max_ld) * sizeof(float);
+  // polls per wait between the parts of an instance before the solve fails;
+  // MP_RAGGED_SPIN_LIMIT (a non-negative integer; 0 gives up at the first
+  // wait) overrides it, so that tests can drive the failure path
+  long long spin_limit = 1ll << 22;
+  if (const char* env = getenv("MP_RAGGED_SPIN_LIMIT")) {
+    char* end = nullptr;
+    const long long v = strtoll(env, &end, 10);
+    if (end != env && v >= 0) spin_limit = v;
+  }
 
   // (re)capture the solve as a graph when its arguments change
   struct Key {
     const void *y, *x, *r, *caps, *ti, *tc, *trr, *tres;
     double eps;
-    long long cap_all, tcap, tldr;
-    int rk, threads, cc, grid;
+    long long cap_all, tcap, tldr, spin;
+    int rk, threads, cc, grid, split, nitems, nslots, pad;
   } key{Y, X, R, caps, tr.idx, tr.coef, tr.rr, tr.r, opts->eps, opts->max_iters, tr.cap, tr.ldr,
-        rk, c->r_cfg.threads, c->r_cfg.cols_per_wave, grid};
+        spin_limit, rk, c->r_cfg.threads, c->r_cfg.cols_per_wave, grid, c->r_cfg.split,
+        c->r_nitems, c->r_nslots, 0};
   const unsigned char* kb = reinterpret_cast<const unsigned char*>(&key);
   std::vector<unsigned char> kv(kb, kb + sizeof key);
   if (!c->r_graph || kv != c->r_graph_key) {
@@ -1357,10 +1451,10 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
       c->r_graph = nullptr;
     }
     HIP_TRY(c, hipStreamBeginCapture(c->r_cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = mp::launch_ragged(c->r_cfg, lp, grid, lds, c->r_inst, c->r_order,
-                                      static_cast<int>(c->r_count), Y, X, R, caps,
-                                      opts->max_iters, opts->eps, rk, c->r_res, c->r_queue, tr,
-                                      c->r_cap_stream);
+    hipError_t le = mp::launch_ragged(c->r_cfg, lp, grid, lds, c->r_inst, c->r_items,
+                                      c->r_nitems, Y, X, R, caps, opts->max_iters, opts->eps,
+                                      rk, c->r_res, c->r_queue, c->r_slots, c->r_nslots,
+                                      spin_limit, tr, c->r_cap_stream);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(c->r_cap_stream, &g);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -1388,6 +1482,7 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
   if (e1) HIP_TRY(c, hipEventRecord(e1, s));
   HIP_TRY(c, hipMemcpyAsync(c->h_rres, c->r_res, sizeof(mp::RResult) * c->r_count,
                             hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(c->h_rq, c->r_queue, sizeof(mp::RQueue), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if (e1) {
     float ms = 0.f;
@@ -1409,6 +1504,8 @@ mp_status mp_solve_ragged(mp_ctx* ctx, const float* Y, float* X, float* R, const
       res[i].persistent = 0;
     }
   }
+  if (c->h_rq->fail)
+    return fail(c, MP_EDEVICE, "a wait between the parts of an instance gave up");
   if (internal)
     return fail(c, MP_EDEVICE, "internal error: a selected index fell outside the dictionary");
   if (nonfinite) return fail(c, MP_ENONFINITE, "an instance's y holds NaN or Inf");

@@ -98,6 +98,19 @@ constexpr size_t kNoAllocBal = kNoAllocKeys + kNoAllocMaxKeys * sizeof(uint64_t)
 // up once per device and kept.
 hipError_t noalloc_scratch(int device, void** out);
 
+// Small dictionaries (every workgroup's share of the columns in LDS): the
+// whole FP32 decode in one launch.  small_geometry gives grid 0 where it
+// does not apply.  rbuf: 2 x ld floats (r = y in half 0 from the init
+// kernel; r after the last step in half 1).  slots: 2 x small_max_wgs() x 2
+// words, zeroed at creation and whenever the epoch wraps.
+CorrGeom small_geometry(int64_t ld, int64_t m, int num_cus);
+hipError_t launch_f32_small(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
+                            const CorrGeom& g, unsigned long long* slots, unsigned epoch,
+                            long long max_iters, float* x, DevState* st, mp_trace tr,
+                            hipStream_t s);
+unsigned small_epoch_mod();
+int small_max_wgs();
+
 // n floats of the residual half st->r_sel names (rbuf: 2 x ld) into r.
 hipError_t launch_copy_selected(const float* rbuf, int64_t ld, int64_t n, const DevState* st,
                                 float* r, hipStream_t s);
@@ -237,18 +250,32 @@ struct RResult {
   int reason, pad;
 };
 struct RQueue {
-  unsigned next;           // next position of the instance order to take
+  unsigned next;           // next position of the work list to take
+  int fail;                // set (atomic OR) when a wait between the parts of an instance gave up
 };
+// One entry of the ragged work list: part `part` of `parts` of instance `id`
+// (columns [part m / parts, (part + 1) m / parts)); the parts of one instance
+// are consecutive in the list and exchange their candidates through record
+// slot `slot` every step (slot < 0 when parts == 1).
+struct RItem {
+  int id, part, parts, slot;
+};
+constexpr int kRaggedMaxParts = 8;
+constexpr int kRaggedRecWords = 16;  // words of one part's record: 8 keys, 2 words each
 struct RConfig {           // launch shape, chosen by the autotuner
   int threads;             // workgroup size: 256, 512 or 1024
   int cols_per_wave;       // columns a wave streams at once: 1, 2 or 4 (BF16: 1)
   int wgs_per_cu;          // persistent workgroups per CU
+  int split;               // most parts an instance is cut into: 1 .. kRaggedMaxParts
 };
 bool ragged_config_valid(const RConfig& cf, bool lp);
+// slots: nslots x 2 x kRaggedMaxParts x kRaggedRecWords words (cleared by the
+// launch before the decode)
 hipError_t launch_ragged(const RConfig& cf, bool lp, int grid, size_t lds, const RInst* inst,
-                         const int* order, int count, const float* Y, float* X, float* R,
+                         const RItem* items, int nitems, const float* Y, float* X, float* R,
                          const long long* caps, long long cap_all, double eps, int rescore_k,
-                         RResult* res, RQueue* q, mp_trace tr, hipStream_t s);
+                         RResult* res, RQueue* q, unsigned long long* slots, int nslots,
+                         long long spin_limit, mp_trace tr, hipStream_t s);
 
 // ---- reduced-precision storage (k_lowp.hip) ---------------------------------
 constexpr int kLpTopK = 8;  // candidates kept per pass and re-scored in FP32
@@ -293,6 +320,9 @@ struct mp_ctx {
   uint64_t* partials = nullptr;  // key slots: kLpTopK per correlation workgroup
   mp::BalState* bal = nullptr;   // column shares and pass timings (FP32, FP64 passes)
   mp::CorrGeom geom{};
+  mp::CorrGeom small{};          // MP_F32: the one-launch decode's shape (grid 0: not used)
+  unsigned long long* small_slots = nullptr;  // its step records
+  unsigned small_epoch = 0;      // tag epoch of its last decode
   // profiling of the correlation kernel
   bool profiling = false;
   int prof_every = 1;            // time every prof_every-th launch
@@ -322,12 +352,18 @@ struct mp_ctx {
   float* r_psi32 = nullptr;        // all instances' FP32 copies, packed
   uint16_t* r_psib = nullptr;      // all BF16 copies, packed (MP_BF16 storage)
   mp::RInst* r_inst = nullptr;     // device descriptors
-  int* r_order = nullptr;          // device: instance ids, most work first
+  mp::RItem* r_items = nullptr;    // device: the work list (room for count x kRaggedMaxParts)
+  unsigned long long* r_slots = nullptr;  // device: the split instances' step records
+  int r_nitems = 0, r_nslots = 0;  // the work list uploaded for r_items_cfg
+  mp::RConfig r_items_cfg{0, 0, 0, 0};
+  std::vector<int> r_order;        // host: instance ids, most work first
+  std::vector<double> r_est;       // host: work estimate of each instance
   long long* r_caps = nullptr;     // device: per-instance caps
   mp::RResult* r_res = nullptr;    // device results
   mp::RResult* h_rres = nullptr;   // pinned host copy
+  mp::RQueue* h_rq = nullptr;      // pinned host copy of the queue (its fail word)
   mp::RQueue* r_queue = nullptr;
-  mp::RConfig r_cfg{1024, 2, 1};
+  mp::RConfig r_cfg{1024, 2, 1, 2};
   std::vector<int64_t> r_n, r_m;   // host copies of the sizes
   // the solve captured as a graph (replayed while its arguments are unchanged)
   hipStream_t r_cap_stream = nullptr;

@@ -57,7 +57,7 @@ class Instance(ctypes.Structure):
 
 class RaggedConfig(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("cols_per_wave", ctypes.c_int32),
-                ("wgs_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wgs_per_cu", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class MPError(RuntimeError):
@@ -260,15 +260,17 @@ def mp_solve_ragged(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opt
     return res
 
 
-def mp_ragged_set_config(ctx, threads: int, cols_per_wave: int, wgs_per_cu: int) -> None:
-    cfg = RaggedConfig(threads, cols_per_wave, wgs_per_cu, 0)
+def mp_ragged_set_config(ctx, threads: int, cols_per_wave: int, wgs_per_cu: int,
+                         split: int = 0) -> None:
+    cfg = RaggedConfig(threads, cols_per_wave, wgs_per_cu, split)
     _check(_load().mp_ragged_set_config(ctx, ctypes.byref(cfg)), "mp_ragged_set_config", ctx)
 
 
 def mp_ragged_get_config(ctx):
     cfg = RaggedConfig()
     _check(_load().mp_ragged_get_config(ctx, ctypes.byref(cfg)), "mp_ragged_get_config", ctx)
-    return dict(threads=cfg.threads, cols_per_wave=cfg.cols_per_wave, wgs_per_cu=cfg.wgs_per_cu)
+    return dict(threads=cfg.threads, cols_per_wave=cfg.cols_per_wave, wgs_per_cu=cfg.wgs_per_cu,
+                split=cfg.split)
 
 
 def mp_destroy(ctx) -> None:
@@ -543,8 +545,10 @@ class RaggedDecoder:
     def handle(self):
         return self._ctx
 
-    def set_config(self, threads: int, cols_per_wave: int, wgs_per_cu: int):
-        mp_ragged_set_config(self._ctx, threads, cols_per_wave, wgs_per_cu)
+    def set_config(self, threads: int, cols_per_wave: int, wgs_per_cu: int, split: int = 0):
+        """Launch shape; ``split``: most parts one instance is cut into (0:
+        the library's default)."""
+        mp_ragged_set_config(self._ctx, threads, cols_per_wave, wgs_per_cu, split)
 
     def get_config(self):
         return mp_ragged_get_config(self._ctx)

@@ -1,11 +1,13 @@
 """Autotuner for the ragged decode's launch shape.
 
 The ragged decode (``mp_solve_ragged``) runs one persistent launch whose
-shape -- workgroup size, columns streamed per wave, workgroups per CU --
-changes speed but never results.  ``tune_ragged`` times every valid shape on
-the actual instances and keeps the fastest; the choice is cached in a JSON
-file keyed by the GPU architecture, the storage type and the multiset of
-instance sizes, so later runs with the same shape of work reuse it.
+shape -- workgroup size, columns streamed per wave, workgroups per CU, and
+the most parts one large instance is cut into -- changes speed but never
+results.  ``tune_ragged`` times every valid shape on the actual instances
+(with the default split), then the split choices on the fastest shape, and
+keeps the fastest; the choice is cached in a JSON file keyed by the GPU
+architecture, the storage type and the multiset of instance sizes, so later
+runs with the same shape of work reuse it.
 
 Cache file: ``$MP_TUNE_CACHE`` if set, else ``~/.cache/mp_mi355x_tune.json``.
 """
@@ -22,6 +24,8 @@ import torch
 
 FP32_SHAPES = [(t, c, w) for t in (256, 512, 1024) for c in (1, 2, 4) for w in (1, 2)]
 BF16_SHAPES = [(t, 1, w) for t in (256, 512, 1024) for w in (1, 2)]
+SPLITS = (1, 2, 4)
+DEFAULT_SPLIT = 2
 
 
 def cache_path() -> str:
@@ -64,16 +68,17 @@ def tune_ragged(dec, y_packed: torch.Tensor, eps: float, max_iters, reps: int = 
     Returns dict(config=..., ms=..., timings=[...], cached=bool)."""
     key = workload_key(dec)
     cache = _load_cache() if use_cache else {}
-    if use_cache and key in cache:
+    if use_cache and key in cache and "split" in cache[key]["config"]:
         cfg = cache[key]["config"]
-        dec.set_config(cfg["threads"], cfg["cols_per_wave"], cfg["wgs_per_cu"])
+        dec.set_config(cfg["threads"], cfg["cols_per_wave"], cfg["wgs_per_cu"], cfg["split"])
         return dict(cache[key], cached=True)
     if shapes is None:
         shapes = BF16_SHAPES if dec.storage == "bf16" else FP32_SHAPES
     timings = []
     x = torch.empty(dec.x_off[-1], dtype=torch.float32, device=y_packed.device)
-    for (t, c, w) in shapes:
-        dec.set_config(t, c, w)
+
+    def time_shape(t, c, w, sp):
+        dec.set_config(t, c, w, sp)
         dec.solve(y_packed, eps, max_iters, want_r=False, x_out=x)  # capture + warm-up
         torch.cuda.synchronize()
         best = float("inf")
@@ -82,12 +87,20 @@ def tune_ragged(dec, y_packed: torch.Tensor, eps: float, max_iters, reps: int = 
             dec.solve(y_packed, eps, max_iters, want_r=False, x_out=x)
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
-        timings.append(dict(threads=t, cols_per_wave=c, wgs_per_cu=w, ms=round(best * 1e3, 3)))
+        timings.append(dict(threads=t, cols_per_wave=c, wgs_per_cu=w, split=sp,
+                            ms=round(best * 1e3, 3)))
         if log:
-            log(f"[tune] threads={t} cols/wave={c} wgs/cu={w}: {best * 1e3:.2f} ms")
+            log(f"[tune] threads={t} cols/wave={c} wgs/cu={w} split={sp}: {best * 1e3:.2f} ms")
+
+    for (t, c, w) in shapes:
+        time_shape(t, c, w, DEFAULT_SPLIT)
+    win = min(timings, key=lambda d: d["ms"])
+    for sp in SPLITS:
+        if sp != DEFAULT_SPLIT:
+            time_shape(win["threads"], win["cols_per_wave"], win["wgs_per_cu"], sp)
     win = min(timings, key=lambda d: d["ms"])
     cfg = dict(threads=win["threads"], cols_per_wave=win["cols_per_wave"],
-               wgs_per_cu=win["wgs_per_cu"])
+               wgs_per_cu=win["wgs_per_cu"], split=win["split"])
     dec.set_config(**cfg)
     entry = dict(config=cfg, ms=win["ms"], timings=timings)
     if use_cache:

@@ -136,19 +136,53 @@ def test_ragged_workload_whole_run(storage):
             assert rep.prefix >= min(rep.iters_ora, 50), (i, rep)
 
 
-def test_launch_shape_does_not_change_selections():
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_launch_shape_does_not_change_selections(storage):
+    """Every launch shape, and every split of the instances into parts (40
+    instances on a grid of 256 or more workgroups: each exceeds the average
+    work per workgroup, so each is cut into `split` parts that exchange
+    their candidates every step), gives the same atoms, x~ and r bit for
+    bit."""
     probs = mpgen.make_ragged(1, count=40, n_choices=(64, 128, 256, 512))
     caps = [p.max_iters for p in probs]
-    with _ragged(probs) as dec:
+    with _ragged(probs, storage) as dec:
         yp = _ypacked(probs)
+        dec.set_config(1024, 1, 1, 1)
         ref = _solve(dec, yp, 1e-5, caps, 64)
-        for shape in [(256, 1, 1), (512, 2, 2), (1024, 4, 1), (256, 4, 2), (1024, 1, 2)]:
+        shapes = [(256, 1, 1, 1), (512, 2, 2, 2), (1024, 4, 1, 4), (256, 4, 2, 8),
+                  (1024, 1, 2, 3), (1024, 2, 1, 2), (512, 1, 1, 8)]
+        if storage == "bf16":
+            shapes = [(t, 1, w, sp) for (t, c, w, sp) in shapes]
+        for shape in shapes:
+            print(f"[ragged {storage} shape {shape}]", flush=True)
             dec.set_config(*shape)
             assert dec.get_config() == dict(threads=shape[0], cols_per_wave=shape[1],
-                                            wgs_per_cu=shape[2])
+                                            wgs_per_cu=shape[2], split=shape[3])
             g = _solve(dec, yp, 1e-5, caps, 64)
             assert np.array_equal(g["idx"], ref["idx"]), shape
             assert np.array_equal(g["x"], ref["x"]), shape
+            assert np.array_equal(g["r"], ref["r"]), shape
+            assert g["iters"] == ref["iters"] and g["stop"] == ref["stop"], shape
+
+
+def test_split_wait_limit_fails_cleanly(monkeypatch):
+    """The waits between the parts of an instance allowed no poll
+    (MP_RAGGED_SPIN_LIMIT=0, read at each call): the solve returns
+    MP_EDEVICE, and the context then solves as before."""
+    from paper_0809_1833_amd import mp
+    probs = mpgen.make_ragged(5, count=16, n_choices=(128, 256))
+    caps = [p.max_iters for p in probs]
+    with _ragged(probs) as dec:
+        yp = _ypacked(probs)
+        dec.set_config(1024, 1, 1, 4)
+        a = _solve(dec, yp, 1e-5, caps, 8)
+        monkeypatch.setenv("MP_RAGGED_SPIN_LIMIT", "0")
+        with pytest.raises(mp.MPError) as e:
+            _solve(dec, yp, 1e-5, caps, 8)
+        assert e.value.status == mp.MP_EDEVICE
+        monkeypatch.delenv("MP_RAGGED_SPIN_LIMIT")
+        b = _solve(dec, yp, 1e-5, caps, 8)
+    assert np.array_equal(a["x"], b["x"]) and a["iters"] == b["iters"]
 
 
 def test_graph_replay_and_recapture():
@@ -216,7 +250,8 @@ def test_autotuner_picks_a_valid_shape(tmp_path, monkeypatch):
         yp = _ypacked(probs)
         res = tune.tune_ragged(dec, yp, 1e-5, caps, reps=1,
                                shapes=[(256, 1, 1), (1024, 2, 1), (512, 4, 2)])
-        assert not res["cached"] and len(res["timings"]) == 3
+        # three shapes at the default split, then the other splits on the best
+        assert not res["cached"] and len(res["timings"]) == 3 + len(tune.SPLITS) - 1
         assert dec.get_config() == res["config"]
         again = tune.tune_ragged(dec, yp, 1e-5, caps)
         assert again["cached"] and again["config"] == res["config"]
