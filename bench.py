@@ -744,6 +744,8 @@ def main():
     iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, args.steps, args.warmup,
                                                   args.profile_every, x, r, stream)
     log(f"[bench] {iters} iterations in {dt:.3f} s")
+    one_launch = "persistent" in stops
+    stops.discard("persistent")
     # the same decode once more, untimed, with its whole per-step record (for
     # the oracle's checks at the end)
     check = not args.no_cpu_baseline
@@ -775,6 +777,13 @@ def main():
         "roofline": hbm_roofline(KERNEL[args.storage], bytes_per_launch, avg_ms, kt_n,
                                  traffic_from_counters(n, m, args.storage), ceiling),
     }
+    if one_launch:
+        # a small dictionary decoded in one launch from its shares in LDS: the
+        # time per step, bound by the exchange of the workgroups' best keys
+        line["config"]["one_launch"] = True
+        line["roofline"] = {"bound": "exchange", "kernel": "k_f32_small",
+                            "avg_step_us": round(avg_ms * 1e3, 3), "steps": kt_n,
+                            "lds_bytes_per_step": 4.0 * n * m}
     if not args.no_omp and args.storage == "f32":
         log("[bench] OMP decode of the same signal")
         o_it, o_dt, o_ms, o_n, o_stops = time_decodes(dec, y, p, args.steps, args.warmup,
