@@ -509,6 +509,7 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
     import torch
 
     import mpgen
+    from paper_0809_1833_amd import tune
     from paper_0809_1833_amd.mp import Decoder
 
     bt = mpgen.make_batch(seed)
@@ -519,6 +520,13 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
     out = {"workload": f"N={n}, M={m}, B={nb} signals, K_b ~ U{{16..256}}, eps={bt.eps}, "
                        "T_b=20 K_b, shared dictionary"}
     with Decoder(psi, storage="bf16") as dec:
+        # the product's tile rule, from the tuner's cache or timed here
+        tn = tune.tune_batched(dec, Y, bt.eps, caps, reps=2, log=log)
+        out["config"] = tn["config"]
+        out["tuned_from_cache"] = tn["cached"]
+        if not tn["cached"]:
+            out["tile_rule_ms"] = {f"{d['atoms128_above']}/{d['atoms64_above']}": d["ms"]
+                                   for d in tn["timings"]}
         for _ in range(warmup):
             dec.solve_batched(Y, bt.eps, caps, want_r=False)
         torch.cuda.synchronize()
@@ -567,7 +575,7 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
                  "dict_of": [0] * nb, "g": g}
 
 
-def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: int = 1,
+def bench_ragged(seed: int, storages=("f32", "bf16"), reps: int = 3, tune_reps: int = 2,
                  check: bool = True):
     """Ragged workload: 512 independent problems, N_i ~ U{128,256,512,1024},
     M_i = 4 N_i, K_i = N_i / 16, eps = 1e-5, T_i = 20 K_i, each with its own

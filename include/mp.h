@@ -255,6 +255,27 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
                            const int64_t* max_iters_b, mp_result* res, const mp_trace* trace,
                            void* stream);
 
+/* Tile of the batched product by the number of signals still active (chosen
+   by the autotuner; results do not depend on it beyond which 8 candidates of
+   each signal reach the FP32 re-score, and the selection is the re-scored
+   one): 128 atoms x 64 signals per workgroup while more than atoms128_above
+   signals are active, 64 atoms while more than atoms64_above, else 32 (more
+   workgroups for a small product).  The 128- and 64-atom forms that stage the
+   residuals in LDS need the padded column length to be a multiple of 256
+   (otherwise 64 atoms without staging).  Default {2^31 - 1, 96}: no 128-atom
+   tile. */
+typedef struct mp_batched_config {
+    int32_t atoms128_above;
+    int32_t atoms64_above;
+} mp_batched_config;
+
+/* mp_batched_set_config / mp_batched_get_config -- the product tile rule of
+   mp_solve_batched on this context (the Section 4 setting of one dictionary
+   for every signal).  Errors: MP_EINVAL (NULL, a ragged, MP_F64 or MP_SIGN1
+   context, a negative count). */
+mp_status mp_batched_set_config(mp_ctx* ctx, const mp_batched_config* cfg);
+mp_status mp_batched_get_config(const mp_ctx* ctx, mp_batched_config* cfg);
+
 /*
  * mp_create_f64 -- mp_create for an FP64 dictionary: the double-precision
  * configuration of the decoder (the paper times single- and double-precision

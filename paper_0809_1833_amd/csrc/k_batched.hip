@@ -180,40 +180,43 @@ constexpr int kBCorrWaves = kBCorrThreads / kWave;   // K split
 constexpr int kBCorrTileB = 64;                      // signals per workgroup
 constexpr int kBPre = 4;                             // K-steps in flight per wave
 
-// Each signal's 8 best atoms of a product tile (the epilogue of both product
+// Each signal's 8 best atoms of a product tile (the epilogue of the product
 // kernels): `ct` holds the tile's TM x 64 correlations; thread (wave, lane)
-// sorts the keys of rows [wave * TM/4, (wave + 1) * TM/4) of signal column
-// `lane` with sorting networks, and the four sorted lists are merged pairwise
-// into the signal's 8 best atoms (descending), written to `partials`.
+// of waves 0-3 sorts the keys of rows [wave * TM/4, (wave + 1) * TM/4) of
+// signal column `lane` with sorting networks, and the four sorted lists are
+// merged pairwise into the signal's 8 best atoms (descending), written to
+// `partials`.  Every thread of the workgroup calls it (barriers).
 template <int TM>
 __device__ void tile_top8(const float (*ct)[kBCorrTileB + 1],
                           uint64_t (&lists)[2][kBTopK][kBCorrTileB], int64_t m0, int64_t m,
                           int nact, int j0, int lane, int wave, uint64_t* __restrict__ partials,
                           int mtiles) {
-  constexpr int RP = TM / 4;  // rows per thread: 16 or 8
-  static_assert(RP == 16 || RP == 8, "tile height");
+  constexpr int RP = TM / 4;  // rows per thread of waves 0-3: 32, 16 or 8
+  static_assert(RP == 32 || RP == 16 || RP == 8, "tile height");
   uint64_t L[kBTopK];
-  {
-    uint64_t v[RP];
+  if (wave < 4) {
+    // groups of 8 rows, each sorted, merged into the running top 8
 #pragma unroll
-    for (int i = 0; i < RP; ++i) {
-      const int rr = wave * RP + i;
-      const int64_t atom = m0 + rr;
-      v[i] = atom < m ? make_key(ct[rr][lane], static_cast<int>(atom)) : 0ull;
-    }
-#pragma unroll
-    for (int q = 0; q < kBTopK; ++q) L[q] = v[q];
-    sort8_keys(L);
-    if constexpr (RP == 16) {
+    for (int g = 0; g < RP / kBTopK; ++g) {
       uint64_t h[kBTopK];
 #pragma unroll
-      for (int q = 0; q < kBTopK; ++q) h[q] = v[kBTopK + q];
+      for (int q = 0; q < kBTopK; ++q) {
+        const int rr = wave * RP + g * kBTopK + q;
+        const int64_t atom = m0 + rr;
+        h[q] = atom < m ? make_key(ct[rr][lane], static_cast<int>(atom)) : 0ull;
+      }
       sort8_keys(h);
-      merge8_keys(L, h);
+      if (g == 0) {
+#pragma unroll
+        for (int q = 0; q < kBTopK; ++q) L[q] = h[q];
+      } else {
+        merge8_keys(L, h);
+      }
     }
   }
-  // waves 2, 3 hand their lists to waves 0, 1; then wave 1 to wave 0
-  if (wave >= 2)
+  // waves 2, 3 hand their lists to waves 0, 1; then wave 1 to wave 0 (waves
+  // past 3, if any, only take part in the barriers)
+  if (wave >= 2 && wave < 4)
 #pragma unroll
     for (int q = 0; q < kBTopK; ++q) lists[wave - 2][q][lane] = L[q];
   __syncthreads();
@@ -362,28 +365,33 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // ---------------------------------------------------------------------------
-// Product tile of 64 atoms x 64 signals with the residual operand staged in
-// LDS (the form used while many signals are active).  Wave w owns atom rows
-// 16w .. 16w + 15 over all of K (4 MFMA 16x16 blocks per K-step, no
+// Product tile of 16 NW atoms x 64 signals with the residual operand staged
+// in LDS (the form used while many signals are active): NW = 4 waves (64
+// atoms, two workgroups per CU) or 8 waves (128 atoms, one workgroup per CU,
+// a quarter less L2 -> L1 traffic per atom-signal product).  Wave w owns atom
+// rows 16w .. 16w + 15 over all of K (4 MFMA 16x16 blocks per K-step, no
 // reduction across waves); its dictionary operand comes straight from the
 // tiled BF16 copy (1 KB per K-step, two register sets of one chunk each).
 // The workgroup stages the 64 signals' residual rows chunk by chunk (kSChunk
 // K elements, full 128-byte lines: 16 threads per row) into one of two LDS
 // buffers while the MFMAs read the other; one barrier per chunk.  Used when
-// ld is a multiple of 2 kSChunk.  Rows are
-// padded by 16 bytes so that the 16 signal rows one operand read touches
-// fall on distinct banks.  The epilogue is k_bcorr's.
+// ld is a multiple of 2 kSChunk.  Rows are padded by 16 bytes so that the
+// 16 signal rows one operand read touches fall on distinct banks.  The
+// residual buffers and the correlation tile share the LDS (the tile is
+// written after the last chunk).  The epilogue is k_bcorr's.
 constexpr int kSChunk = 128;                  // K elements per staged chunk (4 K-steps)
 constexpr int kSRow = kSChunk + 8;            // LDS row stride in BF16 elements
-constexpr int kSLoads = kBCorrTileB * kSChunk / 8 / kBCorrThreads;  // 16-byte loads per thread
-
-__global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr_s(
+template <int NW>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_bcorr_s(
     const uint16_t* __restrict__ psit, int64_t ld, int64_t m, const uint16_t* Rq, int64_t ldq,
     const int* __restrict__ acts, int64_t cap, const BState* __restrict__ bs,
     uint64_t* __restrict__ partials, int mtiles, int par) {
   // Rq without __restrict__: its loads then stay where the memory clobber
   // below puts them (restrict-qualified loads count as invariant and move)
-  constexpr int TM = 64;
+  static_assert(NW == 4 || NW == 8, "waves per workgroup");
+  constexpr int NT = NW * kWave;
+  constexpr int TM = 16 * NW;
+  constexpr int SL = kBCorrTileB * kSChunk / 8 / NT;  // 16-byte staging loads per thread
   const int nact = bs->n_active[par];
   const int* act = acts + par * cap;
   const int j0 = blockIdx.y * kBCorrTileB;
@@ -394,9 +402,14 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
   const int64_t m0 = static_cast<int64_t>(blockIdx.x) * TM;
   const int koff = 8 * (lane / 16);
 
-  __shared__ uint16_t bst[2][kBCorrTileB * kSRow];
-  __shared__ float ctile[TM][kBCorrTileB + 1];
+  constexpr int kBufElems = kBCorrTileB * kSRow;
+  constexpr int kBufBytes = 2 * kBufElems * 2;
+  constexpr int kTileBytes = TM * (kBCorrTileB + 1) * 4;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBufBytes > kTileBytes ? kBufBytes
+                                                                                   : kTileBytes];
   __shared__ uint64_t lists[2][kBTopK][kBCorrTileB];
+  uint16_t(*bst)[kBufElems] = reinterpret_cast<uint16_t(*)[kBufElems]>(smem);
+  float(*ctile)[kBCorrTileB + 1] = reinterpret_cast<float(*)[kBCorrTileB + 1]>(smem);
 
   // this wave's dictionary rows (rows past the last atom read the last one;
   // the epilogue skips them)
@@ -404,11 +417,11 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
   if (row > m - 1) row = m - 1;
   const uint16_t* arow = psit + (row / 16) * 16 * ld + (row % 16) * 32 + koff;
   // this thread's share of the staging: row sig[q], 16 bytes at K offset soff
-  const uint16_t* srow[kSLoads];
-  int sdst[kSLoads];
+  const uint16_t* srow[SL];
+  int sdst[SL];
 #pragma unroll
-  for (int q = 0; q < kSLoads; ++q) {
-    const int f = t + q * kBCorrThreads;
+  for (int q = 0; q < SL; ++q) {
+    const int f = t + q * NT;
     const int sg = f / (kSChunk / 8);
     const int part = f % (kSChunk / 8);
     int j = j0 + sg;
@@ -431,15 +444,15 @@ __global__ __launch_bounds__(kBCorrThreads) __attribute__((amdgpu_waves_per_eu(2
       ra[set][kk] = *reinterpret_cast<const v8bf*>(
           arow + static_cast<int64_t>(chunk * KS + kk) * 32 * 16);
   };
-  v4u sreg[kSLoads];
+  v4u sreg[SL];
   auto load_b = [&](int chunk) {
     const int64_t k0 = static_cast<int64_t>(chunk) * kSChunk;
 #pragma unroll
-    for (int q = 0; q < kSLoads; ++q) sreg[q] = *reinterpret_cast<const v4u*>(srow[q] + k0);
+    for (int q = 0; q < SL; ++q) sreg[q] = *reinterpret_cast<const v4u*>(srow[q] + k0);
   };
   auto store_b = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < kSLoads; ++q) *reinterpret_cast<v4u*>(&bst[buf][sdst[q]]) = sreg[q];
+    for (int q = 0; q < SL; ++q) *reinterpret_cast<v4u*>(&bst[buf][sdst[q]]) = sreg[q];
   };
   // Chunk c (buffer and register set b = c mod 2): first request chunk c+1
   // (residual rows, then the dictionary operand into the other set), then
@@ -673,25 +686,34 @@ hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, floa
 }
 
 // Atoms per product tile for a round expected to have `nact_hint` active
-// signals: 64 when many are active, 32 (twice the workgroups) when few are.
-int bcorr_tile_m(int nact_hint) { return nact_hint > 96 ? 64 : 32; }
+// signals: the more signals, the larger the tile (fewer dictionary re-reads
+// per signal); the fewer, the smaller (more workgroups for the same work).
+int bcorr_tile_m(int nact_hint, const BConfig& cf, int64_t ld) {
+  const bool staged = ld % (2 * kSChunk) == 0;
+  if (nact_hint > cf.atoms128_above && staged) return 128;
+  if (nact_hint > cf.atoms64_above || nact_hint > cf.atoms128_above) return 64;
+  return 32;
+}
 int bcorr_mtiles(int64_t m, int tile_m) { return static_cast<int>((m + tile_m - 1) / tile_m); }
 
 hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, int64_t n,
                          int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
                          BSlot* slots, int* act, int* keep, int64_t cap, BState* bs,
-                         uint64_t* partials, long long round, int nact_hint, int rescore_k,
-                         mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const int tile_m = bcorr_tile_m(nact_hint);
+                         uint64_t* partials, long long round, int nact_hint, const BConfig& cf,
+                         int rescore_k, mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const int tile_m = bcorr_tile_m(nact_hint, cf, ld);
   const int mtiles = bcorr_mtiles(m, tile_m);
   const int btiles = (nact_hint + kBCorrTileB - 1) / kBCorrTileB;  // >= the round's tiles
   const int par = static_cast<int>(round & 1);
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
   const dim3 grid(mtiles, btiles > 0 ? btiles : 1);
-  if (tile_m == 64 && ld % (2 * kSChunk) == 0)
-    k_bcorr_s<<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
-                                                    mtiles, par);
+  if (tile_m == 128)
+    k_bcorr_s<8><<<grid, dim3(8 * kWave), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
+                                                   mtiles, par);
+  else if (tile_m == 64 && ld % (2 * kSChunk) == 0)
+    k_bcorr_s<4><<<grid, dim3(4 * kWave), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
+                                                   mtiles, par);
   else if (tile_m == 64)
     k_bcorr<4><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
                                                      mtiles, par);

@@ -999,7 +999,7 @@ static mp_status ensure_batched(mp_ctx* c, int64_t B, hipStream_t s) {
   if (B <= c->bcap) return MP_OK;
   free_batched(c);
   const int64_t cap = B;
-  const int mtiles = mp::bcorr_mtiles(c->m, 32);  // the larger of the two tilings
+  const int mtiles = mp::bcorr_mtiles(c->m, mp::kBTileMinAtoms);  // the most lists of a tiling
   const size_t ldb = static_cast<size_t>(c->ld);
   c->ldq = c->ld + 32;
   bool ok = hipMalloc(&c->b_r32, sizeof(float) * ldb * cap) == hipSuccess &&
@@ -1113,7 +1113,7 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
         hipError_t e = mp::launch_bround(c->psibt, c->psi32, c->ld, c->n, c->m, c->b_r32,
                                          c->b_rq, c->ldq, X, ldx, c->b_slots, c->b_act,
                                          c->b_keep, c->bcap, c->b_state, c->b_partials,
-                                         issued + j, nact_hint, rk, tr, s, e0, e1);
+                                         issued + j, nact_hint, c->b_cfg, rk, tr, s, e0, e1);
         if (e != hipSuccess) {
           status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
           break;
@@ -1335,6 +1335,23 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bail(MP_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
   *out = c;
+  return MP_OK;
+}
+
+mp_status mp_batched_set_config(mp_ctx* ctx, const mp_batched_config* cfg) {
+  if (!ctx || !cfg) return MP_EINVAL;
+  if (ctx->ragged || ctx->storage == MP_F64 || ctx->storage == MP_SIGN1)
+    return fail(ctx, MP_EINVAL, "batched decoding needs an FP32, BF16 or FP8 context");
+  if (cfg->atoms128_above < 0 || cfg->atoms64_above < 0)
+    return fail(ctx, MP_EINVAL, "the active counts must be >= 0");
+  ctx->b_cfg = mp::BConfig{cfg->atoms128_above, cfg->atoms64_above};
+  return MP_OK;
+}
+
+mp_status mp_batched_get_config(const mp_ctx* ctx, mp_batched_config* cfg) {
+  if (!ctx || !cfg || ctx->ragged) return MP_EINVAL;
+  cfg->atoms128_above = ctx->b_cfg.atoms128_above;
+  cfg->atoms64_above = ctx->b_cfg.atoms64_above;
   return MP_OK;
 }
 

@@ -224,7 +224,19 @@ hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, floa
                         int64_t ldx, int64_t m, float* R32, uint16_t* Rq, int64_t ldq, BSlot* slots,
                         const long long* tcap, long long tcap_all, double eps, int nslots,
                         int* act, int* keep, int64_t cap, BState* bs, hipStream_t s);
-int bcorr_tile_m(int nact_hint);
+// Product tile by the number of active signals: 128 atoms (eight waves)
+// while more than atoms128_above are active, 64 atoms while more than
+// atoms64_above, else 32 atoms; the two staged forms need ld % 256 == 0
+// (otherwise 64 atoms without staging).  Chosen by the autotuner.
+struct BConfig {
+  int atoms128_above;
+  int atoms64_above;
+};
+// By default no 128-atom tile: on N=2048, M=8192, B=256 it made the decode
+// slower at every switch point tried (46.4 against 44.4 ms).
+constexpr BConfig kBConfigDefault{0x7fffffff, 96};
+constexpr int kBTileMinAtoms = 32;  // the smallest tile, which has the most partial lists
+int bcorr_tile_m(int nact_hint, const BConfig& cf, int64_t ld);
 int bcorr_mtiles(int64_t m, int tile_m);
 // Round `round` (0, 1, ...).  nact_hint >= the number of active signals (the
 // host's last reading; the count only decreases): it sizes the grids and
@@ -234,8 +246,8 @@ int bcorr_mtiles(int64_t m, int tile_m);
 hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, int64_t n,
                          int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
                          BSlot* slots, int* act, int* keep, int64_t cap, BState* bs,
-                         uint64_t* partials, long long round, int nact_hint, int rescore_k,
-                         mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                         uint64_t* partials, long long round, int nact_hint, const BConfig& cf,
+                         int rescore_k, mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // ---- many independent instances (k_ragged.hip) -------------------------------
 struct RInst {             // one instance, device-resident descriptor
@@ -345,6 +357,7 @@ struct mp_ctx {
   uint64_t* b_partials = nullptr;  // bcap x mtiles x 8
   int* b_keep = nullptr;           // 4 x bcap: round flags (2 x), list source positions (2 x)
   long long* b_tcap = nullptr;     // bcap
+  mp::BConfig b_cfg = mp::kBConfigDefault;  // product tile by active count
   // ragged contexts (mp_create_ragged): many instances, each its own dictionary
   bool ragged = false;
   int64_t r_count = 0;

@@ -60,6 +60,10 @@ class RaggedConfig(ctypes.Structure):
                 ("wgs_per_cu", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
+class BatchedConfig(ctypes.Structure):
+    _fields_ = [("atoms128_above", ctypes.c_int32), ("atoms64_above", ctypes.c_int32)]
+
+
 class MPError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
@@ -101,6 +105,10 @@ def _load():
     lib.mp_solve_ragged.restype = ctypes.c_int
     lib.mp_solve_ragged.argtypes = [p, p, p, p, ctypes.POINTER(Opts), p, p,
                                     ctypes.POINTER(Trace), p]
+    lib.mp_batched_set_config.restype = ctypes.c_int
+    lib.mp_batched_set_config.argtypes = [p, ctypes.POINTER(BatchedConfig)]
+    lib.mp_batched_get_config.restype = ctypes.c_int
+    lib.mp_batched_get_config.argtypes = [p, ctypes.POINTER(BatchedConfig)]
     lib.mp_ragged_set_config.restype = ctypes.c_int
     lib.mp_ragged_set_config.argtypes = [p, ctypes.POINTER(RaggedConfig)]
     lib.mp_ragged_get_config.restype = ctypes.c_int
@@ -258,6 +266,17 @@ def mp_solve_ragged(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opt
                                  ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve_ragged", ctx)
     return res
+
+
+def mp_batched_set_config(ctx, atoms128_above: int, atoms64_above: int) -> None:
+    cfg = BatchedConfig(atoms128_above, atoms64_above)
+    _check(_load().mp_batched_set_config(ctx, ctypes.byref(cfg)), "mp_batched_set_config", ctx)
+
+
+def mp_batched_get_config(ctx):
+    cfg = BatchedConfig()
+    _check(_load().mp_batched_get_config(ctx, ctypes.byref(cfg)), "mp_batched_get_config", ctx)
+    return dict(atoms128_above=cfg.atoms128_above, atoms64_above=cfg.atoms64_above)
 
 
 def mp_ragged_set_config(ctx, threads: int, cols_per_wave: int, wgs_per_cu: int,
@@ -421,6 +440,15 @@ class Decoder:
             if tres is not None:
                 out.update(r_trace=tres[:k])
         return out
+
+    def set_batched_config(self, atoms128_above: int, atoms64_above: int) -> None:
+        """Product tile rule of solve_batched: 128 atoms while more than
+        atoms128_above signals are active, 64 while more than atoms64_above,
+        else 32."""
+        mp_batched_set_config(self._ctx, atoms128_above, atoms64_above)
+
+    def get_batched_config(self):
+        return mp_batched_get_config(self._ctx)
 
     def solve_batched(self, y: torch.Tensor, eps: float, max_iters, trace_cap: int = 0,
                       rescore_k: int = 0, want_r: bool = True, stream=None,

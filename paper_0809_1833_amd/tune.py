@@ -1,4 +1,4 @@
-"""Autotuner for the ragged decode's launch shape.
+"""Autotuners for the ragged decode's launch shape and the batched product's tiles.
 
 The ragged decode (``mp_solve_ragged``) runs one persistent launch whose
 shape -- workgroup size, columns streamed per wave, workgroups per CU, and
@@ -8,6 +8,12 @@ results.  ``tune_ragged`` times every valid shape on the actual instances
 keeps the fastest; the choice is cached in a JSON file keyed by the GPU
 architecture, the storage type and the multiset of instance sizes, so later
 runs with the same shape of work reuse it.
+
+The batched decode (``mp_solve_batched``) picks the product's tile every
+round from the number of signals still active: 128, 64 or 32 atoms per
+workgroup.  ``tune_batched`` times whole batched decodes under each rule of
+a small grid of switch points and keeps the fastest, cached by architecture,
+dictionary shape, batch size and the multiset of per-signal caps.
 
 Cache file: ``$MP_TUNE_CACHE`` if set, else ``~/.cache/mp_mi355x_tune.json``.
 """
@@ -102,6 +108,60 @@ def tune_ragged(dec, y_packed: torch.Tensor, eps: float, max_iters, reps: int = 
     cfg = dict(threads=win["threads"], cols_per_wave=win["cols_per_wave"],
                wgs_per_cu=win["wgs_per_cu"], split=win["split"])
     dec.set_config(**cfg)
+    entry = dict(config=cfg, ms=win["ms"], timings=timings)
+    if use_cache:
+        cache[key] = entry
+        _store_cache(cache)
+    return dict(entry, cached=False)
+
+
+NEVER = 2**31 - 1  # a switch point no active count exceeds: the tile is not used
+ATOMS128_ABOVE = (64, 128, 192, NEVER)
+ATOMS64_ABOVE = (32, 64, 96, 160, NEVER)
+
+
+def batched_key(dec, n_signals: int, max_iters, arch: Optional[str] = None) -> str:
+    if arch is None:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    caps = [int(v) for v in max_iters] if hasattr(max_iters, "__len__") else [int(max_iters)]
+    digest = hashlib.sha256(json.dumps(sorted(Counter(caps).items())).encode()).hexdigest()[:16]
+    return f"batched|{arch}|{dec.n}|{dec.m}|{n_signals}|{digest}"
+
+
+def batched_rules():
+    """The switch-point pairs tried: a 64-atom switch at or below the
+    128-atom one (above it the 64-atom tile would never run), or none."""
+    return [(a128, a64) for a128 in ATOMS128_ABOVE for a64 in ATOMS64_ABOVE
+            if a64 <= a128 or a64 == NEVER]
+
+
+def tune_batched(dec, Y: torch.Tensor, eps: float, max_iters, reps: int = 2,
+                 rules: Optional[Iterable] = None, use_cache: bool = True, log=None) -> dict:
+    """Time whole batched decodes of Y under each tile rule, apply and return
+    the fastest: dict(config=..., ms=..., timings=[...], cached=bool)."""
+    key = batched_key(dec, Y.shape[1], max_iters)
+    cache = _load_cache() if use_cache else {}
+    if use_cache and key in cache:
+        cfg = cache[key]["config"]
+        dec.set_batched_config(cfg["atoms128_above"], cfg["atoms64_above"])
+        return dict(cache[key], cached=True)
+    timings = []
+    for (a128, a64) in (rules if rules is not None else batched_rules()):
+        dec.set_batched_config(a128, a64)
+        dec.solve_batched(Y, eps, max_iters, want_r=False)  # warm-up
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            dec.solve_batched(Y, eps, max_iters, want_r=False)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        timings.append(dict(atoms128_above=a128, atoms64_above=a64, ms=round(best * 1e3, 3)))
+        if log:
+            log(f"[tune] batched tiles: 128 above {a128}, 64 above {a64}: {best * 1e3:.2f} ms")
+    win = min(timings, key=lambda d: d["ms"])
+    cfg = dict(atoms128_above=win["atoms128_above"], atoms64_above=win["atoms64_above"])
+    dec.set_batched_config(**cfg)
     entry = dict(config=cfg, ms=win["ms"], timings=timings)
     if use_cache:
         cache[key] = entry

@@ -154,3 +154,17 @@ def test_binding_structs_match_the_header():
     assert [f[0] for f in mp.TraceF64._fields_] == _struct_fields(text, "mp_trace_f64")
     assert ctypes.sizeof(mp.Result) == 32 and ctypes.sizeof(mp.Opts) == 24
     assert ctypes.sizeof(mp.Trace) == 48 and ctypes.sizeof(mp.TraceF64) == 48
+    assert [f[0] for f in mp.BatchedConfig._fields_] == _struct_fields(text, "mp_batched_config")
+    assert [f[0] for f in mp.RaggedConfig._fields_] == _struct_fields(text, "mp_ragged_config")
+
+
+def test_batched_tile_rules_tried():
+    """The tuner's switch-point pairs: each runs every tile it names (a
+    64-atom switch at or below the 128-atom one, or none), and the library's
+    default rule is among them."""
+    from paper_0809_1833_amd import tune
+    rules = tune.batched_rules()
+    assert len(rules) == len(set(rules))
+    for a128, a64 in rules:
+        assert a64 <= a128 or a64 == tune.NEVER
+    assert (tune.NEVER, 96) in rules and (tune.NEVER, tune.NEVER) in rules

@@ -133,6 +133,69 @@ def test_batched_workload_whole_run():
             assert rep.prefix >= min(rep.iters_ora, 100)
 
 
+NEVER = 2**31 - 1
+
+
+@pytest.mark.parametrize("rule", [(0, 0), (0, NEVER), (NEVER, 0), (NEVER, NEVER), (100, 40)])
+def test_batched_tile_rules(rule):
+    """Every tile rule of the batched product -- 128 atoms on eight waves, 64
+    staged, 32, and a rule that switches tiles as signals stop -- decodes
+    160 signals with every step judged by the FP64 oracle (no selection off
+    the FP64 argmax where the gap exceeds 1e-5 ||r||, x~ and r within 1e-5 of
+    the oracle's replay).  M = 4000 leaves a ragged last tile for each tile
+    height; N = 512 lets the staged forms run."""
+    bt = mpgen.make_batch(5, b=160, n=512, m=4000, kmin=2, kmax=12)
+    eps = 1e-5
+    with _decoder(bt.psi) as dec:
+        dec.set_batched_config(*rule)
+        assert dec.get_batched_config() == dict(atoms128_above=rule[0], atoms64_above=rule[1])
+        cap = int(bt.max_iters.max())
+        out = dec.solve_batched(_dev(bt.y), eps, list(bt.max_iters), trace_cap=cap, trace_r=True)
+        torch.cuda.synchronize()
+    corr = oracle.Correlator(bt.psi)
+    misses = steps = 0
+    xe = re = 0.0
+    for b in range(bt.y.shape[1]):
+        k = out["iters"][b]
+        gb = dict(x=_np(out["x"][:, b]), r=_np(out["r"][:, b]), iters=k, stop=out["stop"][b],
+                  idx=_np(out["idx"][b, :k]), coef=_np(out["coef"][b, :k]),
+                  r_trace=_np(out["r_trace"][b, :k]))
+        w = whole_run(bt.psi, bt.y[:, b], eps, gb, oracle_ties=False, corr=corr)
+        misses += w.misses
+        steps += w.steps
+        xe, re = max(xe, w.x_err), max(re, w.r_err)
+    print(f"[tile rule {rule}] steps {steps} misses {misses} x {xe:.2e} r {re:.2e}", flush=True)
+    assert misses == 0 and steps == sum(out["iters"])
+    assert xe <= 1e-5 and re <= 1e-5
+
+
+def test_batched_tuner(tmp_path, monkeypatch):
+    """The tuner times the rules it is given, applies the fastest, caches it."""
+    from paper_0809_1833_amd import tune
+    monkeypatch.setenv("MP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    bt = mpgen.make_batch(2, b=40, n=256, m=1024, kmin=2, kmax=8)
+    caps = list(bt.max_iters)
+    with _decoder(bt.psi) as dec:
+        Y = _dev(bt.y)
+        res = tune.tune_batched(dec, Y, 1e-5, caps, reps=1,
+                                rules=[(NEVER, NEVER), (NEVER, 16), (16, 16)])
+        assert not res["cached"] and len(res["timings"]) == 3
+        assert dec.get_batched_config() == res["config"]
+        again = tune.tune_batched(dec, Y, 1e-5, caps)
+        assert again["cached"] and again["config"] == res["config"]
+
+
+def test_batched_config_errors():
+    from paper_0809_1833_amd import mp
+    bt = mpgen.make_batch(1, b=2, n=64, m=256, kmin=2, kmax=4)
+    with _decoder(bt.psi) as dec:
+        assert dec.get_batched_config() == dict(atoms128_above=NEVER, atoms64_above=96)
+        with pytest.raises(mp.MPError) as e:
+            dec.set_batched_config(-1, 5)
+        assert e.value.status == mp.MP_EINVAL
+        assert dec.get_batched_config() == dict(atoms128_above=NEVER, atoms64_above=96)
+
+
 def test_mixed_stops_and_caps():
     """Zero signals, zero caps, tiny caps and normal signals in one batch."""
     bt = mpgen.make_batch(3, b=9, n=250, m=1000, kmin=3, kmax=8)
