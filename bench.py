@@ -352,6 +352,42 @@ def traced_decode(dec, y, p, **kw):
     return g
 
 
+def concurrent_decodes(psi, y, p, storage, steps, nd=4):
+    """Stream-ordered decodes of the same signal on `nd` contexts, one stream
+    each: every round issues one decode per context, then collects them all.
+    Returns the aggregate iterations/s."""
+    import torch
+
+    from paper_0809_1833_amd.mp import Decoder
+
+    decs = [Decoder(psi, storage=storage) for _ in range(nd)]
+    streams = [torch.cuda.Stream() for _ in range(nd)]
+    xs = [torch.empty(p.m, dtype=torch.float32, device="cuda") for _ in range(nd)]
+    rs = [torch.empty(p.n, dtype=torch.float32, device="cuda") for _ in range(nd)]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+
+    def round_():
+        for d, s, x, r in zip(decs, streams, xs, rs):
+            d.solve(y, p.eps, p.max_iters, x=x, r=r, stream=s, asynchronous=True)
+        return sum(d.result()["iters"] for d in decs)
+
+    try:
+        round_()
+        torch.cuda.synchronize()
+        total = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            total += round_()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        for d in decs:
+            d.close()
+    return {"contexts": nd, "streams": nd, "decodes": nd * steps,
+            "iters_per_s": round(total / dt, 3)}
+
+
 def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, rescore_k=0,
                  check=True):
     """Time `steps` decodes of problem p with the given dictionary storage,
@@ -366,7 +402,6 @@ def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, re
     psi = torch.from_numpy(np.ascontiguousarray(p.psi.T)).cuda().t()
     y = torch.from_numpy(p.y).cuda()
     with Decoder(psi, storage=storage) as dec:
-        del psi
         x = torch.empty(m, dtype=torch.float32, device="cuda")
         r = torch.empty(n, dtype=torch.float32, device="cuda")
         iters, dt, avg_ms, kt_n, stops = time_decodes(dec, y, p, steps, warmup, profile_every,
@@ -374,11 +409,14 @@ def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, re
         g = traced_decode(dec, y, p, rescore_k=rescore_k) if check else None
         one_launch = "persistent" in stops
         stops.discard("persistent")
+        conc = None
         if one_launch:
             # the same decode with one launch per step, for comparison
             s_it, s_dt, s_ms, s_n, _ = time_decodes(dec, y, p, steps, warmup, profile_every,
                                                     x, r, rescore_k=rescore_k,
                                                     step_launches=True)
+            conc = concurrent_decodes(psi, y, p, storage, steps)
+        del psi
     leg = {"workload": workload, "storage": storage,
            "iters_per_s": round(iters / dt, 3), "ms_per_decode": round(dt / steps * 1e3, 3),
            "us_per_iter": round(dt / max(iters, 1) * 1e6, 3),
@@ -396,6 +434,8 @@ def bench_single(p, storage, steps, warmup, profile_every, ceiling, workload, re
             "roofline": hbm_roofline(KERNEL[storage], b, s_ms, s_n,
                                      traffic_from_counters(n, m, storage), ceiling)}
         leg["one_launch_over_step_launches"] = round((iters / dt) / (s_it / s_dt), 3)
+        conc["over_one_stream"] = round(conc["iters_per_s"] / (iters / dt), 3)
+        leg["concurrent"] = conc
     else:
         leg["roofline"] = hbm_roofline(KERNEL[storage], b, avg_ms, kt_n,
                                        traffic_from_counters(n, m, storage), ceiling)

@@ -22,9 +22,10 @@
  *    device; "host" pointers to ordinary host memory.  The library never
  *    frees caller memory and never keeps a caller pointer past the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
- *    is ordered on that stream; every mp_solve* call returns only after its
- *    decode has finished (the host needs the device's stop flag to know when
- *    to stop issuing iterations).
+ *    is ordered on that stream; an mp_solve* call returns only after its
+ *    decode has finished (the host reads the device's stop flag to know when
+ *    to stop issuing iterations), except a decode with MP_SOLVE_ASYNC, which
+ *    is only enqueued (its result comes from mp_solve_result).
  *  - Errors are reported by return code only; nothing aborts the process.
  *    mp_last_error(ctx) returns a human-readable detail for the last failed
  *    call on a context.
@@ -87,8 +88,9 @@ typedef struct mp_opts {
     int32_t rescore_k;    /* reduced-precision storage: how many best candidates of
                              each pass are re-scored against the FP32 columns (1..8;
                              0 means 8).  Ignored for MP_F32 storage. */
-    uint32_t flags;       /* 0 or MP_SOLVE_STEP_LAUNCHES (mp_solve, mp_solve_f64 and
-                             mp_solve_omp; 0 for the others) */
+    uint32_t flags;       /* 0, or MP_SOLVE_STEP_LAUNCHES (mp_solve, mp_solve_f64 and
+                             mp_solve_omp) and MP_SOLVE_ASYNC (mp_solve and
+                             mp_solve_noalloc); 0 for the others */
 } mp_opts;
 
 /* mp_opts.flags: decode with one kernel launch per step even where the whole
@@ -96,6 +98,21 @@ typedef struct mp_opts {
    contexts whose dictionary fits the LDS of at most 32 workgroups); the same
    results bit for bit; no effect on the other forms. */
 #define MP_SOLVE_STEP_LAUNCHES 0x1u
+
+/* mp_opts.flags: a stream-ordered decode (mp_solve and mp_solve_noalloc on
+   MP_F32, MP_BF16 and MP_FP8_E4M3 contexts).  The call enqueues the whole
+   decode on its stream and returns without waiting for the device: x~, r and
+   the trace are final once the stream reaches the point of the call, and the
+   result (iterations, norms, stop reason, and the errors only the device can
+   find: non-finite y, a wait that gave up) is collected with mp_solve_result.
+   res must be NULL.  Since the host cannot see when the decode stops, it
+   enqueues every launch the cap allows (max_iters + 1; the one launch of a
+   decode held in LDS); a launch past the stop returns at once, costing its
+   dispatch only (about 4 us at N=8192, M=32768), so a cap far above the steps
+   needed costs that per spare step.  Decodes on different contexts overlap
+   on different streams; a context holds one stream-ordered decode at a time
+   (every decode call on it returns MP_EINVAL until mp_solve_result). */
+#define MP_SOLVE_ASYNC 0x2u
 
 typedef struct mp_result {
     int64_t iters;        /* updates performed */
@@ -196,6 +213,17 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
  */
 mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opts* opts,
                    mp_result* res, const mp_trace* trace, void* stream);
+
+/*
+ * mp_solve_result -- wait for the stream-ordered decode (MP_SOLVE_ASYNC) last
+ * issued on ctx and return its result: the same result and errors mp_solve
+ * gives for that decode.  The context can then decode again.
+ *
+ *   res      host or NULL: as for mp_solve
+ * Errors: MP_EINVAL (NULL ctx, or no stream-ordered decode pending), and the
+ * decode's own: MP_ENONFINITE, MP_EDEVICE.
+ */
+mp_status mp_solve_result(mp_ctx* ctx, mp_result* res);
 
 /*
  * mp_solve_noalloc -- mp_solve for callers that cannot allocate memory while

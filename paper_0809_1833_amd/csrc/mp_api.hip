@@ -116,6 +116,8 @@ void free_ctx(mp_ctx* c) {
   (void)hipFree(c->st);
   (void)hipFree(c->partials);
   (void)hipFree(c->bal);
+  if (c->async_pending && c->async_ev) (void)hipEventSynchronize(c->async_ev);
+  if (c->async_ev) (void)hipEventDestroy(c->async_ev);
   if (c->h_st) (void)hipHostFree(c->h_st);
   for (hipEvent_t e : c->done_ev)
     if (e) (void)hipEventDestroy(e);
@@ -167,12 +169,21 @@ mp_status check_trace(mp_ctx* c, const T* trace, int64_t rows) {
   return MP_OK;
 }
 
-mp_status check_opts(mp_ctx* c, const mp_opts* opts) {
+// A context with a stream-ordered decode not yet collected takes no other
+// decode (its device state and the host mirror belong to that decode).
+mp_status check_not_pending(mp_ctx* c) {
+  if (c->async_pending)
+    return fail(c, MP_EINVAL, "a stream-ordered decode is pending: collect it with mp_solve_result");
+  return MP_OK;
+}
+
+mp_status check_opts(mp_ctx* c, const mp_opts* opts,
+                     uint32_t allowed = MP_SOLVE_STEP_LAUNCHES) {
+  if (mp_status ps = check_not_pending(c); ps != MP_OK) return ps;
   if (!(opts->eps >= 0.0) || !isfinite(opts->eps))
     return fail(c, MP_EINVAL, "eps must be finite and >= 0");
   if (opts->max_iters < 0) return fail(c, MP_EINVAL, "max_iters must be >= 0");
-  if (opts->flags & ~static_cast<uint32_t>(MP_SOLVE_STEP_LAUNCHES))
-    return fail(c, MP_EINVAL, "unknown opts.flags");
+  if (opts->flags & ~allowed) return fail(c, MP_EINVAL, "unknown opts.flags");
   if (opts->rescore_k < 0 || opts->rescore_k > 8)
     return fail(c, MP_EINVAL, "rescore_k must be in 0..8");
   return MP_OK;
@@ -192,6 +203,10 @@ bool make_host_state(mp_ctx* c) {
       e = nullptr;
       return false;
     }
+  if (hipEventCreateWithFlags(&c->async_ev, hipEventDisableTiming) != hipSuccess) {
+    c->async_ev = nullptr;
+    return false;
+  }
   return true;
 }
 
@@ -353,9 +368,22 @@ mp_status finish_result(mp_ctx* c, mp_result* res);
 // of the half the state names, and the state comes back with one wait.
 // Allocates nothing: every buffer is in `b`, the context (pinned state slots
 // and events made at its creation) or the caller's arguments.
+//
+// Stream-ordered (MP_SOLVE_ASYNC): the same launches, all T+1 of them
+// enqueued at once (the host does not read the state), then the state copy
+// into the host mirror and the context's event; mp_solve_result waits for it.
+mp_status enqueue_result(mp_ctx* c, const mp::DevState* st, hipStream_t s, int persistent) {
+  HIP_TRY(c, hipMemcpyAsync(c->h_st, st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipEventRecord(c->async_ev, s));
+  c->async_pending = true;
+  c->async_persistent = persistent;
+  return MP_OK;
+}
+
 mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_opts* opts,
                         mp_result* res, const mp_trace& tr, hipStream_t s, const CarriedBufs& b,
                         bool allow_one_launch) {
+  const bool async = (opts->flags & MP_SOLVE_ASYNC) != 0;
   HIP_TRY(c, mp::launch_init(y, c->n, c->ld, x, c->m, b.r_work, b.st, opts->eps,
                              static_cast<long long>(opts->max_iters), s));
   if (allow_one_launch && c->storage == MP_F32 && c->small.grid > 0 &&
@@ -368,12 +396,14 @@ mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_
     if (c->small_epoch == 1)
       HIP_TRY(c, hipMemsetAsync(c->small_slots, 0,
                                 sizeof(unsigned long long) * 2 * 2 * mp::small_max_wgs(), s));
-    if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+    const bool timed = c->profiling && !async;
+    if (timed) HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, mp::launch_f32_small(c->psi32, c->ld, c->n, c->m, b.r_work, c->small,
                                     c->small_slots, c->small_epoch, opts->max_iters, x, b.st, tr,
                                     s));
-    if (c->profiling) HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    if (timed) HIP_TRY(c, hipEventRecord(c->ev[1], s));
     if (r) HIP_TRY(c, mp::launch_copy_selected(b.r_work, c->ld, c->n, b.st, r, s));
+    if (async) return enqueue_result(c, b.st, s, 1);
     HIP_TRY(c, hipMemcpyAsync(c->h_st, b.st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     if (c->profiling) {
@@ -390,7 +420,7 @@ mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_
   }
   long long k = 0;
   const long long T = opts->max_iters;
-  const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, [&](hipEvent_t e0, hipEvent_t e1) {
+  auto step = [&](hipEvent_t e0, hipEvent_t e1) {
     hipError_t e;
     if (e0 && (e = hipEventRecord(e0, s)) != hipSuccess) return e;
     if (c->storage == MP_F32)
@@ -403,7 +433,18 @@ mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_
     if (e != hipSuccess) return e;
     if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;
     return hipSuccess;
-  }, /*known_running=*/true, b.st);
+  };
+  if (async) {
+    const long long launches = T > 0 ? T + 1 : 0;
+    for (long long j = 0; j < launches; ++j) {
+      const hipError_t e = step(nullptr, nullptr);
+      if (e != hipSuccess) return fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+    }
+    if (r) HIP_TRY(c, mp::launch_copy_selected(b.r_work, c->ld, c->n, b.st, r, s));
+    return enqueue_result(c, b.st, s, 0);
+  }
+  const mp_status st = run_iterations(c, T > 0 ? T + 1 : 0, s, true, step,
+                                      /*known_running=*/true, b.st);
   if (st != MP_OK) return st;
   if (r) HIP_TRY(c, mp::launch_copy_selected(b.r_work, c->ld, c->n, b.st, r, s));
   HIP_TRY(c, hipMemcpyAsync(c->h_st, b.st, sizeof(mp::DevState), hipMemcpyDeviceToHost, s));
@@ -619,7 +660,13 @@ mp_status mp_solve(mp_ctx* ctx, const float* y, float* x, float* r, const mp_opt
   if (ctx->storage == MP_F64)
     return fail(ctx, MP_EINVAL, "an MP_F64 context is decoded with mp_solve_f64");
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
-  if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
+  if (mp_status os = check_opts(ctx, opts, MP_SOLVE_STEP_LAUNCHES | MP_SOLVE_ASYNC); os != MP_OK)
+    return os;
+  if (opts->flags & MP_SOLVE_ASYNC) {
+    if (ctx->storage == MP_SIGN1)
+      return fail(ctx, MP_EINVAL, "stream-ordered decodes need MP_F32, MP_BF16 or MP_FP8_E4M3");
+    if (res) return fail(ctx, MP_EINVAL, "a stream-ordered decode takes res = NULL");
+  }
   mp_trace tr{};
   if (mp_status ts = check_trace(ctx, trace, ctx->n); ts != MP_OK) return ts;
   if (trace) tr = *trace;
@@ -720,7 +767,10 @@ mp_status mp_solve_noalloc(mp_ctx* ctx, const float* y, float* x, float* r, cons
     return fail(c, MP_EINVAL,
                 "mp_solve_noalloc decodes MP_F32, MP_BF16 and MP_FP8_E4M3 contexts of mp_create");
   if (!y || !x || !opts) return fail(c, MP_EINVAL, "y, x and opts must not be NULL");
-  if (mp_status os = check_opts(c, opts); os != MP_OK) return os;
+  if (mp_status os = check_opts(c, opts, MP_SOLVE_STEP_LAUNCHES | MP_SOLVE_ASYNC); os != MP_OK)
+    return os;
+  if ((opts->flags & MP_SOLVE_ASYNC) && res)
+    return fail(c, MP_EINVAL, "a stream-ordered decode takes res = NULL");
   if (mp_status ts = check_trace(c, trace, c->n); ts != MP_OK) return ts;
   if (c->ld > mp::kNoAllocMaxLd)
     return fail(c, MP_EINVAL, "N exceeds the static scratch (at most 16384 rows)");
@@ -741,6 +791,19 @@ mp_status mp_solve_noalloc(mp_ctx* ctx, const float* y, float* x, float* r, cons
                                    reinterpret_cast<uint64_t*>(b + mp::kNoAllocKeys),
                                    reinterpret_cast<mp::BalState*>(b + mp::kNoAllocBal)},
                        false);
+}
+
+mp_status mp_solve_result(mp_ctx* ctx, mp_result* res) {
+  if (!ctx) return MP_EINVAL;
+  mp_ctx* c = ctx;
+  if (!c->async_pending) return fail(c, MP_EINVAL, "no stream-ordered decode is pending");
+  c->err.clear();
+  HIP_TRY(c, hipSetDevice(c->device));
+  c->async_pending = false;
+  HIP_TRY(c, hipEventSynchronize(c->async_ev));
+  const mp_status fs = finish_result(c, res);
+  if (fs == MP_OK && res) res->persistent = c->async_persistent;
+  return fs;
 }
 
 static mp_status ensure_omp(mp_ctx* c, int64_t tq) {
@@ -774,7 +837,13 @@ mp_status mp_solve_omp(mp_ctx* ctx, const float* y, float* x, float* r, const mp
   if (ctx->ragged || ctx->storage != MP_F32)
     return fail(ctx, MP_EINVAL, "mp_solve_omp needs an MP_F32 context from mp_create");
   if (!y || !x || !opts) return fail(ctx, MP_EINVAL, "y, x and opts must not be NULL");
-  if (mp_status os = check_opts(ctx, opts); os != MP_OK) return os;
+  if (mp_status os = check_opts(ctx, opts, MP_SOLVE_STEP_LAUNCHES | MP_SOLVE_ASYNC); os != MP_OK)
+    return os;
+  if (opts->flags & MP_SOLVE_ASYNC) {
+    if (ctx->storage == MP_SIGN1)
+      return fail(ctx, MP_EINVAL, "stream-ordered decodes need MP_F32, MP_BF16 or MP_FP8_E4M3");
+    if (res) return fail(ctx, MP_EINVAL, "a stream-ordered decode takes res = NULL");
+  }
   mp_trace tr{};
   if (mp_status ts = check_trace(ctx, trace, ctx->n); ts != MP_OK) return ts;
   if (trace) tr = *trace;
@@ -1035,6 +1104,7 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
   if (c->ragged) return fail(c, MP_EINVAL, "a ragged context is decoded with mp_solve_ragged");
   if (c->storage == MP_F64 || c->storage == MP_SIGN1)
     return fail(c, MP_EINVAL, "batched decoding needs an FP32, BF16 or FP8 context");
+  if (mp_status ps = check_not_pending(c); ps != MP_OK) return ps;
   if (B < 0) return fail(c, MP_EINVAL, "B must be >= 0");
   if (B == 0) return MP_OK;
   if (B >= (int64_t{1} << 31) / 2) return fail(c, MP_EINVAL, "B too large");

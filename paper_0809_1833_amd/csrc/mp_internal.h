@@ -329,6 +329,11 @@ struct mp_ctx {
   mp::DevState* st = nullptr;    // device state
   mp::DevState* h_st = nullptr;  // pinned: host mirror, then two chunk-state slots
   hipEvent_t done_ev[2] = {nullptr, nullptr};  // the chunk-state copies done
+  // a stream-ordered decode (MP_SOLVE_ASYNC): its state is copied into
+  // h_st[0], then async_ev is recorded; collected by mp_solve_result
+  hipEvent_t async_ev = nullptr;
+  bool async_pending = false;
+  int async_persistent = 0;
   uint64_t* partials = nullptr;  // key slots: kLpTopK per correlation workgroup
   mp::BalState* bal = nullptr;   // column shares and pass timings (FP32, FP64 passes)
   mp::CorrGeom geom{};

@@ -27,6 +27,7 @@ STOP_CONVERGED, STOP_MAX_ITERS, STOP_STALLED, STOP_ZERO_INPUT = 0, 1, 2, 3
 STOP_NAMES = {0: "converged", 1: "max_iters", 2: "stalled", 3: "zero_input"}
 MP_SKIP_NORM_CHECK = 0x1
 MP_SOLVE_STEP_LAUNCHES = 0x1  # mp_opts.flags
+MP_SOLVE_ASYNC = 0x2  # mp_opts.flags
 DTYPES = {"f32": MP_F32, "bf16": MP_BF16, "fp8": MP_FP8_E4M3, "f64": MP_F64, "sign": MP_SIGN1}
 
 
@@ -87,6 +88,8 @@ def _load():
     lib.mp_solve.restype = ctypes.c_int
     lib.mp_solve.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
                              ctypes.POINTER(Trace), p]
+    lib.mp_solve_result.restype = ctypes.c_int
+    lib.mp_solve_result.argtypes = [p, ctypes.POINTER(Result)]
     lib.mp_solve_noalloc.restype = ctypes.c_int
     lib.mp_solve_noalloc.argtypes = [p, p, p, p, ctypes.POINTER(Opts), ctypes.POINTER(Result),
                                      ctypes.POINTER(Trace), p]
@@ -178,21 +181,31 @@ def mp_create(psi_ptr: int, n: int, m: int, ld: int, storage: int = MP_F32, flag
 
 
 def mp_solve(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
-             trace: Optional[Trace] = None, stream: Optional[int] = None) -> Result:
-    res = Result()
-    st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts), ctypes.byref(res),
+             trace: Optional[Trace] = None, stream: Optional[int] = None,
+             want_result: bool = True) -> Optional[Result]:
+    """``want_result=False`` passes res = NULL (required with MP_SOLVE_ASYNC)."""
+    res = Result() if want_result else None
+    st = _load().mp_solve(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts),
+                          ctypes.byref(res) if res is not None else None,
                           ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve", ctx)
     return res
 
 
 def mp_solve_noalloc(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opts,
-                     trace: Optional[Trace] = None, stream: Optional[int] = None) -> Result:
-    res = Result()
+                     trace: Optional[Trace] = None, stream: Optional[int] = None,
+                     want_result: bool = True) -> Optional[Result]:
+    res = Result() if want_result else None
     st = _load().mp_solve_noalloc(ctx, y_ptr, x_ptr, r_ptr, ctypes.byref(opts),
-                                  ctypes.byref(res),
+                                  ctypes.byref(res) if res is not None else None,
                                   ctypes.byref(trace) if trace is not None else None, stream)
     _check(st, "mp_solve_noalloc", ctx)
+    return res
+
+
+def mp_solve_result(ctx) -> Result:
+    res = Result()
+    _check(_load().mp_solve_result(ctx, ctypes.byref(res)), "mp_solve_result", ctx)
     return res
 
 
@@ -393,7 +406,7 @@ class Decoder:
     def solve(self, y: torch.Tensor, eps: float, max_iters: int, x: Optional[torch.Tensor] = None,
               r: Optional[torch.Tensor] = None, trace_cap: int = 0, rescore_k: int = 0,
               stream=None, omp: bool = False, step_launches: bool = False,
-              trace_r: bool = False, noalloc: bool = False):
+              trace_r: bool = False, noalloc: bool = False, asynchronous: bool = False):
         """Decode one signal.  Returns dict(x, r, iters, yy, rr, stop, persistent,
         trace...).  ``omp=True`` decodes with Orthogonal Matching Pursuit
         (mp_solve_omp; MP_F32 storage).  ``step_launches=True``: the one-bit
@@ -401,7 +414,10 @@ class Decoder:
         ``trace_r=True`` (with ``trace_cap``): also the residual after every
         traced step, ``r_trace`` of shape (steps, N).  ``noalloc=True``:
         mp_solve_noalloc (the library's static scratch; MP_F32, MP_BF16 or
-        MP_FP8_E4M3 storage)."""
+        MP_FP8_E4M3 storage).  ``asynchronous=True``: a stream-ordered decode
+        (MP_SOLVE_ASYNC): returns dict(x, r, and the whole trace arrays) at
+        once, final when ``stream`` gets there; ``result()`` then waits and
+        gives the rest."""
         dt = self.dtype
         if not y.is_cuda or y.dtype != dt or y.numel() != self.n:
             raise ValueError(f"y must be a {dt} CUDA tensor of N elements")
@@ -422,11 +438,25 @@ class Decoder:
             tr = (TraceF64 if self.storage == "f64" else Trace)(
                 tidx.data_ptr(), tcoef.data_ptr(), trr.data_ptr(), trace_cap, _ptr(tres), self.n)
         opts = Opts(float(eps), int(max_iters), int(rescore_k),
-                    MP_SOLVE_STEP_LAUNCHES if step_launches else 0)
+                    (MP_SOLVE_STEP_LAUNCHES if step_launches else 0) |
+                    (MP_SOLVE_ASYNC if asynchronous else 0))
         if omp and self.storage != "f32":
             raise ValueError("OMP decodes need f32 storage")
         if noalloc and (omp or self.storage in ("f64", "sign")):
             raise ValueError("noalloc decodes need f32, bf16 or fp8 storage and plain MP")
+        if asynchronous:
+            if omp or self.storage in ("f64", "sign"):
+                raise ValueError("stream-ordered decodes need f32, bf16 or fp8 storage and "
+                                 "plain MP")
+            solve = mp_solve_noalloc if noalloc else mp_solve
+            solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
+                  _stream_ptr(stream), want_result=False)
+            out = dict(x=x, r=r)
+            if tr is not None:
+                out.update(idx=tidx, coef=tcoef, rr_trace=trr)
+                if tres is not None:
+                    out.update(r_trace=tres)
+            return out
         solve = mp_solve_f64 if self.storage == "f64" else (
             mp_solve_omp if omp else (mp_solve_noalloc if noalloc else mp_solve))
         res = solve(self._ctx, y.data_ptr(), x.data_ptr(), r.data_ptr(), opts, tr,
@@ -440,6 +470,14 @@ class Decoder:
             if tres is not None:
                 out.update(r_trace=tres[:k])
         return out
+
+    def result(self):
+        """Wait for the stream-ordered decode last issued on this decoder and
+        return dict(iters, yy, rr, stop, persistent) (mp_solve_result)."""
+        res = mp_solve_result(self._ctx)
+        return dict(iters=res.iters, yy=res.yy, rr=res.rr,
+                    stop=STOP_NAMES.get(res.stop_reason, res.stop_reason),
+                    persistent=bool(res.persistent))
 
     def set_batched_config(self, atoms128_above: int, atoms64_above: int) -> None:
         """Product tile rule of solve_batched: 128 atoms while more than

@@ -57,6 +57,7 @@ def test_solve_and_destroy_accept_null_context():
     lib = mp.library()
     opts = mp.Opts(1e-5, 10, 0, 0)
     assert lib.mp_solve(None, 1, 1, None, ctypes.byref(opts), None, None, None) == mp.MP_EINVAL
+    assert lib.mp_solve_result(None, None) == mp.MP_EINVAL
     lib.mp_destroy(None)
 
 
@@ -141,7 +142,7 @@ def _struct_fields(text, name):
 def test_binding_flags_match_the_header():
     import re
     text = _header_text()
-    for name in ("MP_SKIP_NORM_CHECK", "MP_SOLVE_STEP_LAUNCHES"):
+    for name in ("MP_SKIP_NORM_CHECK", "MP_SOLVE_STEP_LAUNCHES", "MP_SOLVE_ASYNC"):
         value = re.search(r"#define %s (0x[0-9a-fA-F]+)u" % name, text).group(1)
         assert getattr(mp, name) == int(value, 16), name
 
