@@ -530,13 +530,20 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
   }
   const int j = blockIdx.x;
   if (j >= nact) return;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  // this position's partial lists (the product wrote one descending list of
+  // 8 keys per atom tile): the first group of this wave requested at once,
+  // since it depends on the position only
+  const uint64_t* pk = partials + static_cast<int64_t>(j) * mtiles * kBTopK;
+  const int nkeys = mtiles * kBTopK;
+  const int i0 = wave * 2 * kWave + lane;
+  uint64_t ka = i0 < nkeys ? pk[i0] : 0ull;
+  uint64_t kc = i0 + kWave < nkeys ? pk[i0 + kWave] : 0ull;
   const int b = acts[par * cap + j];
   BSlot* sl = slots + b;
-  if (sl->done) {  // stopped in the previous round; the same value in every thread
-    if (threadIdx.x == 0) flags_now[j] = 0;
-    return;
-  }
-  // the signal's state, requested now rather than after the update
+  // the signal's state and r requested together; a signal that stopped in
+  // the previous round (still on this list) is dropped after the merge
+  const int was_done = sl->done;
   long long t0 = 0, tmax = 0;
   double thr = 0.0;
   if (threadIdx.x == 0) {
@@ -546,39 +553,41 @@ __global__ __launch_bounds__(kBSelThreads) void k_bselect(
   }
   extern __shared__ v4f r_lds[];
   __shared__ uint64_t wl[kBSelWaves][kBTopK];
-  __shared__ uint64_t cand[kBTopK];
   __shared__ uint64_t resc[kBTopK];
   __shared__ double dred[kBSelWaves];
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   float* r = R32 + static_cast<int64_t>(b) * ld;
   const int ld4 = static_cast<int>(ld / 4);
   for (int i = threadIdx.x; i < ld4; i += kBSelThreads) r_lds[i] = reinterpret_cast<const v4f*>(r)[i];
 
-  // the signal's 8 best candidates: the product wrote one descending list of
-  // 8 keys per atom tile; each wave merges 16 lists at a time across its
-  // lanes and keeps a running top 8, then wave 0 merges the 8 waves' lists
+  // the signal's 8 best candidates: each wave merges 16 lists at a time
+  // across its lanes and keeps a running top 8; then every wave merges the 8
+  // waves' lists (the same result in each), so that wave q can take
+  // candidate q without another barrier
   {
-    const uint64_t* pk = partials + static_cast<int64_t>(j) * mtiles * kBTopK;
-    const int nkeys = mtiles * kBTopK;
     uint64_t top = 0;
     for (int g = wave; g * 2 * kWave < nkeys; g += kBSelWaves) {
-      const int i = g * 2 * kWave + lane;
-      const uint64_t a = i < nkeys ? pk[i] : 0ull;
-      const uint64_t c = i + kWave < nkeys ? pk[i + kWave] : 0ull;
-      top = merge_lane_lists8(top, top8_of_lists16(a, c, lane), lane);
+      if (g != wave) {
+        const int i = g * 2 * kWave + lane;
+        ka = i < nkeys ? pk[i] : 0ull;
+        kc = i + kWave < nkeys ? pk[i + kWave] : 0ull;
+      }
+      top = merge_lane_lists8(top, top8_of_lists16(ka, kc, lane), lane);
     }
     if (lane < kBTopK) wl[wave][lane] = top;
   }
-  __syncthreads();
-  if (wave == 0) {
-    static_assert(kBSelWaves * kBTopK == kWave, "one list per group of 8 lanes");
-    const uint64_t t8 = top8_of_lists16(wl[lane / kBTopK][lane % kBTopK], 0ull, lane);
-    if (lane < kBTopK) cand[lane] = t8;
+  if (was_done) {  // the same value in every thread
+    if (threadIdx.x == 0) flags_now[j] = 0;
+    return;
   }
   __syncthreads();
-  // re-score in FP32, one candidate per wave
+  static_assert(kBSelWaves * kBTopK == kWave, "one list per group of 8 lanes");
+  const uint64_t t8 = top8_of_lists16(wl[lane / kBTopK][lane % kBTopK], 0ull, lane);
+  // re-score in FP32, one candidate per wave (candidate q is lane q's key)
   for (int q = wave; q < rescore_k; q += kBSelWaves) {
-    const uint64_t k = cand[q];
+    const uint64_t k =
+        (static_cast<uint64_t>(static_cast<uint32_t>(__shfl(static_cast<int>(t8 >> 32), q)))
+         << 32) |
+        static_cast<uint32_t>(__shfl(static_cast<int>(t8 & 0xffffffffu), q));
     uint64_t rk = 0;
     if (k != 0) {
       const int idx = key_index(k);
