@@ -251,7 +251,9 @@ def test_autotuner_picks_a_valid_shape(tmp_path, monkeypatch):
         res = tune.tune_ragged(dec, yp, 1e-5, caps, reps=1,
                                shapes=[(256, 1, 1), (1024, 2, 1), (512, 4, 2)])
         # three shapes at the default split, then the other splits on the best
-        assert not res["cached"] and len(res["timings"]) == 3 + len(tune.SPLITS) - 1
+        # (here all three)
+        assert not res["cached"]
+        assert len(res["timings"]) == 3 + min(3, tune.SPLIT_SHAPES) * (len(tune.SPLITS) - 1)
         assert dec.get_config() == res["config"]
         again = tune.tune_ragged(dec, yp, 1e-5, caps)
         assert again["cached"] and again["config"] == res["config"]
