@@ -111,7 +111,10 @@ typedef struct mp_opts {
    dispatch only (about 4 us at N=8192, M=32768), so a cap far above the steps
    needed costs that per spare step.  Decodes on different contexts overlap
    on different streams; a context holds one stream-ordered decode at a time
-   (every decode call on it returns MP_EINVAL until mp_solve_result). */
+   (every decode call on it returns MP_EINVAL until mp_solve_result).
+   mp_solve_noalloc decodes all use the library's one static scratch per
+   GPU, so stream-ordered ones must not overlap either: issue them on one
+   stream. */
 #define MP_SOLVE_ASYNC 0x2u
 
 typedef struct mp_result {
