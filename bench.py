@@ -589,6 +589,15 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
                        "peak": 2500.0, "unit": "TFLOP/s",
                        "frac": round(flops / gemm_s / 1e12 / 2500.0, 4),
                        "rounds": cnt, "gemm_ms_per_batch": round(ms * cnt, 3)}
+        # the same products against memory: every round reads the BF16
+        # dictionary once and each active signal's BF16 residual once (below
+        # the BF16 ridge of about 312 flop/B even at 256 signals)
+        opnd = cnt * 2.0 * n * m + 2.0 * n * total_iters
+        out["operand_bytes"] = {"bound": "hbm", "kernel": "k_bcorr",
+                                "achieved": round(opnd / gemm_s / 1e9, 2), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(opnd / gemm_s / 1e9 / HBM_PEAK_GBS, 4),
+                                "bytes_per_batch": opnd,
+                                "flop_per_byte": round(flops / opnd, 1)}
         # one more decode with every signal's atoms recorded, for the checks
         g = None
         if check:
