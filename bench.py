@@ -565,8 +565,9 @@ def bench_batched(seed: int, reps: int = 3, warmup: int = 1, sequential: bool = 
         out["config"] = tn["config"]
         out["tuned_from_cache"] = tn["cached"]
         if not tn["cached"]:
-            out["tile_rule_ms"] = {f"{d['atoms128_above']}/{d['atoms64_above']}": d["ms"]
-                                   for d in tn["timings"]}
+            out["tile_rule_ms"] = {
+                f"{d['atoms128_above']}/{d['atoms64_above']}/{d['atoms32_above']}": d["ms"]
+                for d in tn["timings"]}
         for _ in range(warmup):
             dec.solve_batched(Y, bt.eps, caps, want_r=False)
         torch.cuda.synchronize()

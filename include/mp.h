@@ -290,14 +290,18 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
    by the autotuner; results do not depend on it beyond which 8 candidates of
    each signal reach the FP32 re-score, and the selection is the re-scored
    one): 128 atoms x 64 signals per workgroup while more than atoms128_above
-   signals are active, 64 atoms while more than atoms64_above, else 32 (more
-   workgroups for a small product).  The 128- and 64-atom forms that stage the
-   residuals in LDS need the padded column length to be a multiple of 256
-   (otherwise 64 atoms without staging).  Default {2^31 - 1, 96}: no 128-atom
-   tile. */
+   signals are active, 64 atoms while more than atoms64_above, 32 while more
+   than atoms32_above, else 16 (more workgroups for a small product; the 32-
+   and 16-atom tiles give the same products).  The 128- and 64-atom forms that
+   stage the residuals in LDS need the padded column length to be a multiple
+   of 256 (otherwise 64 atoms without staging), and a 128- or 64-atom tile
+   gives way to the next smaller one where its grid, ceil(M / atoms) x
+   ceil(active / 64) workgroups, would not cover every compute unit.
+   Default {2^31 - 1, 96, 0}: no 128-atom and no 16-atom tile. */
 typedef struct mp_batched_config {
     int32_t atoms128_above;
     int32_t atoms64_above;
+    int32_t atoms32_above;
 } mp_batched_config;
 
 /* mp_batched_set_config / mp_batched_get_config -- the product tile rule of

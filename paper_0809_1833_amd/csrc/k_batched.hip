@@ -191,19 +191,21 @@ __device__ void tile_top8(const float (*ct)[kBCorrTileB + 1],
                           uint64_t (&lists)[2][kBTopK][kBCorrTileB], int64_t m0, int64_t m,
                           int nact, int j0, int lane, int wave, uint64_t* __restrict__ partials,
                           int mtiles) {
-  constexpr int RP = TM / 4;  // rows per thread of waves 0-3: 32, 16 or 8
-  static_assert(RP == 32 || RP == 16 || RP == 8, "tile height");
+  constexpr int RP = TM / 4;  // rows per thread of waves 0-3: 32, 16, 8 or 4
+  static_assert(RP == 32 || RP == 16 || RP == 8 || RP == 4, "tile height");
   uint64_t L[kBTopK];
   if (wave < 4) {
-    // groups of 8 rows, each sorted, merged into the running top 8
+    // groups of 8 rows (4 rows and 4 empty keys in a 16-atom tile), each
+    // sorted, merged into the running top 8
 #pragma unroll
-    for (int g = 0; g < RP / kBTopK; ++g) {
+    for (int g = 0; g < (RP + kBTopK - 1) / kBTopK; ++g) {
       uint64_t h[kBTopK];
 #pragma unroll
       for (int q = 0; q < kBTopK; ++q) {
-        const int rr = wave * RP + g * kBTopK + q;
+        const int rl = g * kBTopK + q;  // row of this thread's share
+        const int rr = wave * RP + (rl < RP ? rl : 0);
         const int64_t atom = m0 + rr;
-        h[q] = atom < m ? make_key(ct[rr][lane], static_cast<int>(atom)) : 0ull;
+        h[q] = rl < RP && atom < m ? make_key(ct[rr][lane], static_cast<int>(atom)) : 0ull;
       }
       sort8_keys(h);
       if (g == 0) {
@@ -697,11 +699,20 @@ hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, floa
 // Atoms per product tile for a round expected to have `nact_hint` active
 // signals: the more signals, the larger the tile (fewer dictionary re-reads
 // per signal); the fewer, the smaller (more workgroups for the same work).
-int bcorr_tile_m(int nact_hint, const BConfig& cf, int64_t ld) {
+// The split-K tiles (32 and 16 atoms) sum each product in the same order,
+// so they give the same values.  A larger tile yields to the next smaller
+// one where its grid would leave CUs without a workgroup.
+int bcorr_tile_m(int nact_hint, const BConfig& cf, int64_t ld, int64_t m, int num_cus) {
   const bool staged = ld % (2 * kSChunk) == 0;
-  if (nact_hint > cf.atoms128_above && staged) return 128;
-  if (nact_hint > cf.atoms64_above || nact_hint > cf.atoms128_above) return 64;
-  return 32;
+  int t = 16;
+  if (nact_hint > cf.atoms128_above && staged) t = 128;
+  else if (nact_hint > cf.atoms64_above || nact_hint > cf.atoms128_above) t = 64;
+  else if (nact_hint > cf.atoms32_above) t = 32;
+  // a 128- or 64-atom tile only where its grid still gives every CU a
+  // workgroup (a short dictionary: fewer atom tiles than CUs)
+  const int64_t btiles = (nact_hint + kBCorrTileB - 1) / kBCorrTileB;
+  while (t > 32 && (m + t - 1) / t * btiles < num_cus) t /= 2;
+  return t;
 }
 int bcorr_mtiles(int64_t m, int tile_m) { return static_cast<int>((m + tile_m - 1) / tile_m); }
 
@@ -709,8 +720,9 @@ hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, i
                          int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
                          BSlot* slots, int* act, int* keep, int64_t cap, BState* bs,
                          uint64_t* partials, long long round, int nact_hint, const BConfig& cf,
-                         int rescore_k, mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const int tile_m = bcorr_tile_m(nact_hint, cf, ld);
+                         int num_cus, int rescore_k, mp_trace tr, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
+  const int tile_m = bcorr_tile_m(nact_hint, cf, ld, m, num_cus);
   const int mtiles = bcorr_mtiles(m, tile_m);
   const int btiles = (nact_hint + kBCorrTileB - 1) / kBCorrTileB;  // >= the round's tiles
   const int par = static_cast<int>(round & 1);
@@ -726,8 +738,11 @@ hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, i
   else if (tile_m == 64)
     k_bcorr<4><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
                                                      mtiles, par);
-  else
+  else if (tile_m == 32)
     k_bcorr<2><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
+                                                     mtiles, par);
+  else
+    k_bcorr<1><<<grid, dim3(kBCorrThreads), 0, s>>>(psit, ld, m, Rq, ldq, act, cap, bs, partials,
                                                      mtiles, par);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (e1 && (e = hipEventRecord(e1, s)) != hipSuccess) return e;

@@ -1183,7 +1183,8 @@ mp_status mp_solve_batched(mp_ctx* ctx, const float* Y, int64_t ldy, int64_t B, 
         hipError_t e = mp::launch_bround(c->psibt, c->psi32, c->ld, c->n, c->m, c->b_r32,
                                          c->b_rq, c->ldq, X, ldx, c->b_slots, c->b_act,
                                          c->b_keep, c->bcap, c->b_state, c->b_partials,
-                                         issued + j, nact_hint, c->b_cfg, rk, tr, s, e0, e1);
+                                         issued + j, nact_hint, c->b_cfg, c->num_cus, rk, tr, s,
+                                         e0, e1);
         if (e != hipSuccess) {
           status = fail(c, MP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
           break;
@@ -1412,9 +1413,9 @@ mp_status mp_batched_set_config(mp_ctx* ctx, const mp_batched_config* cfg) {
   if (!ctx || !cfg) return MP_EINVAL;
   if (ctx->ragged || ctx->storage == MP_F64 || ctx->storage == MP_SIGN1)
     return fail(ctx, MP_EINVAL, "batched decoding needs an FP32, BF16 or FP8 context");
-  if (cfg->atoms128_above < 0 || cfg->atoms64_above < 0)
+  if (cfg->atoms128_above < 0 || cfg->atoms64_above < 0 || cfg->atoms32_above < 0)
     return fail(ctx, MP_EINVAL, "the active counts must be >= 0");
-  ctx->b_cfg = mp::BConfig{cfg->atoms128_above, cfg->atoms64_above};
+  ctx->b_cfg = mp::BConfig{cfg->atoms128_above, cfg->atoms64_above, cfg->atoms32_above};
   return MP_OK;
 }
 
@@ -1422,6 +1423,7 @@ mp_status mp_batched_get_config(const mp_ctx* ctx, mp_batched_config* cfg) {
   if (!ctx || !cfg || ctx->ragged) return MP_EINVAL;
   cfg->atoms128_above = ctx->b_cfg.atoms128_above;
   cfg->atoms64_above = ctx->b_cfg.atoms64_above;
+  cfg->atoms32_above = ctx->b_cfg.atoms32_above;
   return MP_OK;
 }
 

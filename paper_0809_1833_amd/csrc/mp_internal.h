@@ -226,17 +226,21 @@ hipError_t launch_binit(const float* Y, int64_t ldy, int64_t n, int64_t ld, floa
                         int* act, int* keep, int64_t cap, BState* bs, hipStream_t s);
 // Product tile by the number of active signals: 128 atoms (eight waves)
 // while more than atoms128_above are active, 64 atoms while more than
-// atoms64_above, else 32 atoms; the two staged forms need ld % 256 == 0
-// (otherwise 64 atoms without staging).  Chosen by the autotuner.
+// atoms64_above, 32 while more than atoms32_above, else 16; the two staged
+// forms need ld % 256 == 0 (otherwise 64 atoms without staging), and a 128-
+// or 64-atom tile yields to the next smaller one where its grid would have
+// fewer workgroups than the device has CUs.  Chosen by the autotuner.
 struct BConfig {
   int atoms128_above;
   int atoms64_above;
+  int atoms32_above;
 };
-// By default no 128-atom tile: on N=2048, M=8192, B=256 it made the decode
-// slower at every switch point tried (46.4 against 44.4 ms).
-constexpr BConfig kBConfigDefault{0x7fffffff, 96};
-constexpr int kBTileMinAtoms = 32;  // the smallest tile, which has the most partial lists
-int bcorr_tile_m(int nact_hint, const BConfig& cf, int64_t ld);
+// By default no 128-atom tile (on N=2048, M=8192, B=256 it made the decode
+// slower at every switch point tried: 46.4 against 44.4 ms) and no 16-atom
+// tile.
+constexpr BConfig kBConfigDefault{0x7fffffff, 96, 0};
+constexpr int kBTileMinAtoms = 16;  // the smallest tile, which has the most partial lists
+int bcorr_tile_m(int nact_hint, const BConfig& cf, int64_t ld, int64_t m, int num_cus);
 int bcorr_mtiles(int64_t m, int tile_m);
 // Round `round` (0, 1, ...).  nact_hint >= the number of active signals (the
 // host's last reading; the count only decreases): it sizes the grids and
@@ -247,7 +251,8 @@ hipError_t launch_bround(const uint16_t* psit, const float* psi32, int64_t ld, i
                          int64_t m, float* R32, uint16_t* Rq, int64_t ldq, float* X, int64_t ldx,
                          BSlot* slots, int* act, int* keep, int64_t cap, BState* bs,
                          uint64_t* partials, long long round, int nact_hint, const BConfig& cf,
-                         int rescore_k, mp_trace tr, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                         int num_cus, int rescore_k, mp_trace tr, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1);
 
 // ---- many independent instances (k_ragged.hip) -------------------------------
 struct RInst {             // one instance, device-resident descriptor

@@ -62,7 +62,8 @@ class RaggedConfig(ctypes.Structure):
 
 
 class BatchedConfig(ctypes.Structure):
-    _fields_ = [("atoms128_above", ctypes.c_int32), ("atoms64_above", ctypes.c_int32)]
+    _fields_ = [("atoms128_above", ctypes.c_int32), ("atoms64_above", ctypes.c_int32),
+                ("atoms32_above", ctypes.c_int32)]
 
 
 class MPError(RuntimeError):
@@ -281,15 +282,17 @@ def mp_solve_ragged(ctx, y_ptr: int, x_ptr: int, r_ptr: Optional[int], opts: Opt
     return res
 
 
-def mp_batched_set_config(ctx, atoms128_above: int, atoms64_above: int) -> None:
-    cfg = BatchedConfig(atoms128_above, atoms64_above)
+def mp_batched_set_config(ctx, atoms128_above: int, atoms64_above: int,
+                          atoms32_above: int = 0) -> None:
+    cfg = BatchedConfig(atoms128_above, atoms64_above, atoms32_above)
     _check(_load().mp_batched_set_config(ctx, ctypes.byref(cfg)), "mp_batched_set_config", ctx)
 
 
 def mp_batched_get_config(ctx):
     cfg = BatchedConfig()
     _check(_load().mp_batched_get_config(ctx, ctypes.byref(cfg)), "mp_batched_get_config", ctx)
-    return dict(atoms128_above=cfg.atoms128_above, atoms64_above=cfg.atoms64_above)
+    return dict(atoms128_above=cfg.atoms128_above, atoms64_above=cfg.atoms64_above,
+                atoms32_above=cfg.atoms32_above)
 
 
 def mp_ragged_set_config(ctx, threads: int, cols_per_wave: int, wgs_per_cu: int,
@@ -479,11 +482,12 @@ class Decoder:
                     stop=STOP_NAMES.get(res.stop_reason, res.stop_reason),
                     persistent=bool(res.persistent))
 
-    def set_batched_config(self, atoms128_above: int, atoms64_above: int) -> None:
+    def set_batched_config(self, atoms128_above: int, atoms64_above: int,
+                           atoms32_above: int = 0) -> None:
         """Product tile rule of solve_batched: 128 atoms while more than
         atoms128_above signals are active, 64 while more than atoms64_above,
-        else 32."""
-        mp_batched_set_config(self._ctx, atoms128_above, atoms64_above)
+        32 while more than atoms32_above, else 16."""
+        mp_batched_set_config(self._ctx, atoms128_above, atoms64_above, atoms32_above)
 
     def get_batched_config(self):
         return mp_batched_get_config(self._ctx)

@@ -37,8 +37,11 @@ def _column_major(a: np.ndarray) -> torch.Tensor:
 def phase_diagram(rhos: Optional[Sequence[float]] = None,
                   sigmas: Optional[Sequence[float]] = None, trials: Optional[int] = None,
                   draws: Optional[int] = None, seed: int = 0, m: Optional[int] = None,
-                  log: Optional[Callable[[str], None]] = None) -> dict:
+                  log: Optional[Callable[[str], None]] = None,
+                  tile_rule: Optional[Sequence[int]] = None) -> dict:
     """E(sigma, rho) in percent on the grid, with per-cell mean iterations.
+    ``tile_rule``: the batched product's switch points (Decoder.
+    set_batched_config), else the library's default.
 
     Returns dict(rhos, sigmas, E (len(rhos) x len(sigmas)), iters (same
     shape), decodes, decode_seconds (device decode time only, input drawing
@@ -60,6 +63,8 @@ def phase_diagram(rhos: Optional[Sequence[float]] = None,
             x_true = torch.from_numpy(np.ascontiguousarray(pb.x.T)).cuda()  # (B, M)
             y = _column_major(pb.y)
             with Decoder(_column_major(pb.psi)) as dec:
+                if tile_rule is not None:
+                    dec.set_batched_config(*tile_rule)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 out = dec.solve_batched(y, pb.eps, pb.max_iters, want_r=False)

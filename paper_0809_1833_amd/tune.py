@@ -10,9 +10,10 @@ architecture, the storage type and the multiset of instance sizes, so later
 runs with the same shape of work reuse it.
 
 The batched decode (``mp_solve_batched``) picks the product's tile every
-round from the number of signals still active: 128, 64 or 32 atoms per
+round from the number of signals still active: 128, 64, 32 or 16 atoms per
 workgroup.  ``tune_batched`` times whole batched decodes under each rule of
-a small grid of switch points and keeps the fastest, cached by architecture,
+a small grid of the 128- and 64-atom switch points, then the 16-atom switch
+points on the fastest, and keeps the fastest, cached by architecture,
 dictionary shape, batch size and the multiset of per-signal caps.
 
 Cache file: ``$MP_TUNE_CACHE`` if set, else ``~/.cache/mp_mi355x_tune.json``.
@@ -122,6 +123,7 @@ def tune_ragged(dec, y_packed: torch.Tensor, eps: float, max_iters, reps: int = 
 NEVER = 2**31 - 1  # a switch point no active count exceeds: the tile is not used
 ATOMS128_ABOVE = (64, 128, 192, NEVER)
 ATOMS64_ABOVE = (32, 64, 96, 160, NEVER)
+ATOMS32_ABOVE = (16, 32, 64)  # tried on the fastest pair; 0 (no 16-atom tile) first
 
 
 def batched_key(dec, n_signals: int, max_iters, arch: Optional[str] = None) -> str:
@@ -133,25 +135,29 @@ def batched_key(dec, n_signals: int, max_iters, arch: Optional[str] = None) -> s
 
 
 def batched_rules():
-    """The switch-point pairs tried: a 64-atom switch at or below the
-    128-atom one (above it the 64-atom tile would never run), or none."""
-    return [(a128, a64) for a128 in ATOMS128_ABOVE for a64 in ATOMS64_ABOVE
+    """The switch-point pairs tried first (no 16-atom tile): a 64-atom
+    switch at or below the 128-atom one (above it the 64-atom tile would
+    never run), or none."""
+    return [(a128, a64, 0) for a128 in ATOMS128_ABOVE for a64 in ATOMS64_ABOVE
             if a64 <= a128 or a64 == NEVER]
 
 
 def tune_batched(dec, Y: torch.Tensor, eps: float, max_iters, reps: int = 2,
                  rules: Optional[Iterable] = None, use_cache: bool = True, log=None) -> dict:
-    """Time whole batched decodes of Y under each tile rule, apply and return
-    the fastest: dict(config=..., ms=..., timings=[...], cached=bool)."""
+    """Time whole batched decodes of Y under each tile rule (triples of
+    switch points; by default batched_rules(), then ATOMS32_ABOVE on the
+    fastest), apply and return the fastest: dict(config=..., ms=...,
+    timings=[...], cached=bool)."""
     key = batched_key(dec, Y.shape[1], max_iters)
     cache = _load_cache() if use_cache else {}
-    if use_cache and key in cache:
+    if use_cache and key in cache and "atoms32_above" in cache[key]["config"]:
         cfg = cache[key]["config"]
-        dec.set_batched_config(cfg["atoms128_above"], cfg["atoms64_above"])
+        dec.set_batched_config(cfg["atoms128_above"], cfg["atoms64_above"], cfg["atoms32_above"])
         return dict(cache[key], cached=True)
     timings = []
-    for (a128, a64) in (rules if rules is not None else batched_rules()):
-        dec.set_batched_config(a128, a64)
+
+    def time_rule(a128, a64, a32):
+        dec.set_batched_config(a128, a64, a32)
         dec.solve_batched(Y, eps, max_iters, want_r=False)  # warm-up
         torch.cuda.synchronize()
         best = float("inf")
@@ -160,11 +166,21 @@ def tune_batched(dec, Y: torch.Tensor, eps: float, max_iters, reps: int = 2,
             dec.solve_batched(Y, eps, max_iters, want_r=False)
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
-        timings.append(dict(atoms128_above=a128, atoms64_above=a64, ms=round(best * 1e3, 3)))
+        timings.append(dict(atoms128_above=a128, atoms64_above=a64, atoms32_above=a32,
+                            ms=round(best * 1e3, 3)))
         if log:
-            log(f"[tune] batched tiles: 128 above {a128}, 64 above {a64}: {best * 1e3:.2f} ms")
+            log(f"[tune] batched tiles: 128 above {a128}, 64 above {a64}, 32 above {a32}: "
+                f"{best * 1e3:.2f} ms")
+
+    for rule in (rules if rules is not None else batched_rules()):
+        time_rule(*rule)
+    if rules is None:
+        w = min(timings, key=lambda d: d["ms"])
+        for a32 in ATOMS32_ABOVE:
+            time_rule(w["atoms128_above"], w["atoms64_above"], a32)
     win = min(timings, key=lambda d: d["ms"])
-    cfg = dict(atoms128_above=win["atoms128_above"], atoms64_above=win["atoms64_above"])
+    cfg = dict(atoms128_above=win["atoms128_above"], atoms64_above=win["atoms64_above"],
+               atoms32_above=win["atoms32_above"])
     dec.set_batched_config(**cfg)
     entry = dict(config=cfg, ms=win["ms"], timings=timings)
     if use_cache:

@@ -166,6 +166,7 @@ def test_batched_tile_rules_tried():
     from paper_0809_1833_amd import tune
     rules = tune.batched_rules()
     assert len(rules) == len(set(rules))
-    for a128, a64 in rules:
-        assert a64 <= a128 or a64 == tune.NEVER
-    assert (tune.NEVER, 96) in rules and (tune.NEVER, tune.NEVER) in rules
+    for a128, a64, a32 in rules:
+        assert (a64 <= a128 or a64 == tune.NEVER) and a32 == 0
+    assert (tune.NEVER, 96, 0) in rules and (tune.NEVER, tune.NEVER, 0) in rules
+    assert all(a > 0 for a in tune.ATOMS32_ABOVE)

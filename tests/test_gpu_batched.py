@@ -136,19 +136,22 @@ def test_batched_workload_whole_run():
 NEVER = 2**31 - 1
 
 
-@pytest.mark.parametrize("rule", [(0, 0), (0, NEVER), (NEVER, 0), (NEVER, NEVER), (100, 40)])
+@pytest.mark.parametrize("rule", [(0, 0, 0), (0, NEVER, 0), (NEVER, 0, 0), (NEVER, NEVER, 0),
+                                  (NEVER, NEVER, NEVER), (100, 40, 12)])
 def test_batched_tile_rules(rule):
     """Every tile rule of the batched product -- 128 atoms on eight waves, 64
-    staged, 32, and a rule that switches tiles as signals stop -- decodes
-    160 signals with every step judged by the FP64 oracle (no selection off
-    the FP64 argmax where the gap exceeds 1e-5 ||r||, x~ and r within 1e-5 of
-    the oracle's replay).  M = 4000 leaves a ragged last tile for each tile
-    height; N = 512 lets the staged forms run."""
-    bt = mpgen.make_batch(5, b=160, n=512, m=4000, kmin=2, kmax=12)
+    staged, 32, 16, and a rule that switches tiles as signals stop --
+    decodes 160 signals with every step judged by the FP64 oracle (no
+    selection off the FP64 argmax where the gap exceeds 1e-5 ||r||, x~ and r
+    within 1e-5 of the oracle's replay).  M = 11000 leaves a ragged last
+    tile for each tile height and gives even the 128-atom tile a workgroup
+    for every CU at 160 signals; N = 512 lets the staged forms run."""
+    bt = mpgen.make_batch(5, b=160, n=512, m=11000, kmin=2, kmax=8)
     eps = 1e-5
     with _decoder(bt.psi) as dec:
         dec.set_batched_config(*rule)
-        assert dec.get_batched_config() == dict(atoms128_above=rule[0], atoms64_above=rule[1])
+        assert dec.get_batched_config() == dict(atoms128_above=rule[0], atoms64_above=rule[1],
+                                                atoms32_above=rule[2])
         cap = int(bt.max_iters.max())
         out = dec.solve_batched(_dev(bt.y), eps, list(bt.max_iters), trace_cap=cap, trace_r=True)
         torch.cuda.synchronize()
@@ -178,7 +181,7 @@ def test_batched_tuner(tmp_path, monkeypatch):
     with _decoder(bt.psi) as dec:
         Y = _dev(bt.y)
         res = tune.tune_batched(dec, Y, 1e-5, caps, reps=1,
-                                rules=[(NEVER, NEVER), (NEVER, 16), (16, 16)])
+                                rules=[(NEVER, NEVER, 0), (NEVER, 16, 0), (16, 16, 8)])
         assert not res["cached"] and len(res["timings"]) == 3
         assert dec.get_batched_config() == res["config"]
         again = tune.tune_batched(dec, Y, 1e-5, caps)
@@ -189,11 +192,13 @@ def test_batched_config_errors():
     from paper_0809_1833_amd import mp
     bt = mpgen.make_batch(1, b=2, n=64, m=256, kmin=2, kmax=4)
     with _decoder(bt.psi) as dec:
-        assert dec.get_batched_config() == dict(atoms128_above=NEVER, atoms64_above=96)
-        with pytest.raises(mp.MPError) as e:
-            dec.set_batched_config(-1, 5)
-        assert e.value.status == mp.MP_EINVAL
-        assert dec.get_batched_config() == dict(atoms128_above=NEVER, atoms64_above=96)
+        default = dict(atoms128_above=NEVER, atoms64_above=96, atoms32_above=0)
+        assert dec.get_batched_config() == default
+        for bad in [(-1, 5, 0), (5, 5, -1)]:
+            with pytest.raises(mp.MPError) as e:
+                dec.set_batched_config(*bad)
+            assert e.value.status == mp.MP_EINVAL
+        assert dec.get_batched_config() == default
 
 
 def test_mixed_stops_and_caps():
@@ -215,12 +220,13 @@ def test_mixed_stops_and_caps():
 
 
 @pytest.mark.parametrize("n,m,b", [(3, 5, 2), (64, 130, 70), (16384, 64, 3), (520, 300, 5),
-                                   (256, 1000, 130), (512, 4096, 100)])
+                                   (256, 1000, 130), (512, 4096, 100), (256, 16000, 100)])
 def test_batched_shapes(n, m, b):
-    """Ragged and extreme shapes; the last two keep more than 96 signals
-    active with column lengths a multiple of 256, so their early rounds run
-    the product with the residual operand staged in LDS (the first with a
-    ragged last atom tile)."""
+    """Ragged and extreme shapes.  The last three keep more than 96 signals
+    active with column lengths a multiple of 256; the first two of them have
+    too few atom tiles for the 64-atom tile to give every CU a workgroup, so
+    they run 32-atom tiles, the last one runs the 64-atom product with the
+    residual operand staged in LDS (a ragged last atom tile)."""
     rng = np.random.default_rng(n + m + b)
     psi = mpgen.gaussian_unit_dictionary(rng, n, m)
     Y = np.zeros((n, b), np.float32, order="F")
