@@ -203,15 +203,18 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
 // x~, the trace and the state) and the correlations (dot_column_f32 over
 // the column's LDS copy, the same FMAs in the same order as over its copy in
 // memory), so results are bit-identical to the stepping form; which
-// workgroup scores a column does not change its correlation.  In place of
-// the kernel boundary, each workgroup publishes its best key of pass k as
-// two 64-bit words, each a 32-bit tag (decode epoch, step) over 32 bits of
-// the key, with relaxed device-scope atomics, and reads every workgroup's
-// words of the pass before it goes on; steps alternate between two halves
-// of the slots (a workgroup overwrites its words of pass k only after
-// reading every record of pass k+1, each of which its owner published
-// after reading every record of pass k).  The epoch, new for every decode,
-// keeps words of an earlier decode from matching.
+// workgroup or wave scores a column does not change its correlation, and
+// the largest key does not depend on the order the keys are compared in.
+// In place of the kernel boundary, every wave publishes its best key of
+// pass k as two 64-bit words, each a 32-bit tag (decode epoch, step) over 32
+// bits of the key, with relaxed device-scope atomics, as soon as its columns
+// are scored (no reduction inside the workgroup first), and every workgroup
+// reads all waves' words of the pass before it goes on; steps alternate
+// between two halves of the slots (a wave overwrites its words of pass k
+// only after its workgroup read every record of pass k+1, each of which its
+// owner published after its own workgroup read every record of pass k).
+// The epoch, new for every decode, keeps words of an earlier decode from
+// matching.
 //
 // Every wait ends: the host launches this form only where the occupancy
 // query shows every workgroup resident at once (one per CU, G <= CUs), all
@@ -221,6 +224,10 @@ __global__ __launch_bounds__(kCorrThreads) void k_mp_step_f32(
 // gives up too.
 constexpr int kSmallLds = 150 * 1024;  // dynamic LDS for r and a share, at most
 constexpr int kSmallMaxWgs = 32;
+constexpr int kSmallWaves = kCorrThreads / kWave;  // records per workgroup and pass
+constexpr int kSmallRecs = kSmallMaxWgs * kSmallWaves;
+constexpr int kSmallCols = 8;  // columns a wave scores at once
+static_assert(kSmallRecs <= kCorrThreads, "one polling thread per record");
 constexpr unsigned kSmallEpochMod = 4096;
 
 __global__ __launch_bounds__(kCorrThreads) void k_f32_small(
@@ -261,11 +268,12 @@ __global__ __launch_bounds__(kCorrThreads) void k_f32_small(
 
   for (long long k = 0;; ++k) {
     if (k > 0) {
-      // every workgroup's key of pass k (published with step field k)
+      // every wave's key of pass k (published with step field k): record
+      // wg * kSmallWaves + wave of the pass's half
       uint64_t kp = 0;
-      if (static_cast<int>(threadIdx.x) < G) {
+      if (static_cast<int>(threadIdx.x) < G * kSmallWaves) {
         const unsigned want = ep | (static_cast<unsigned>(k) & 0xFFFFFu);
-        unsigned long long* w0 = slots + ((k & 1) * kSmallMaxWgs + threadIdx.x) * 2;
+        unsigned long long* w0 = slots + ((k & 1) * kSmallRecs + threadIdx.x) * 2;
         long long spins = 0;
         unsigned long long hi = 0, lo = 0;
         for (;;) {
@@ -299,18 +307,53 @@ __global__ __launch_bounds__(kCorrThreads) void k_f32_small(
                                        thr, 1, dred))
         return;
     }
-    // pass k+1 over the share, from LDS
+    // pass k+1 over the share, from LDS: kSmallCols of the wave's columns at
+    // a time, so that their loads and lane sums overlap, each with
+    // dot_column_f32's arithmetic (the two chains over the column's halves,
+    // each lane's elements in increasing order, then the lane sum), then the
+    // rest one by one
     uint64_t best = 0;
-    for (int64_t col = col0 + wave; col < col1; col += kCorrThreads / kWave) {
+    int64_t col = col0 + wave;
+    const int h0 = ld4 / 2;
+    for (; col + kSmallWaves * (kSmallCols - 1) < col1; col += kSmallWaves * kSmallCols) {
+      float acc_a[kSmallCols], acc_b[kSmallCols];
+#pragma unroll
+      for (int u = 0; u < kSmallCols; ++u) acc_a[u] = acc_b[u] = 0.0f;
+      for (int i = lane; i < h0; i += kWave) {
+        const v4f ra = r_lds[i], rb = r_lds[h0 + i];
+#pragma unroll
+        for (int u = 0; u < kSmallCols; ++u) {
+          const v4f* p = cols + (col + kSmallWaves * u - col0) * ld4;
+          const v4f a = p[i], b = p[h0 + i];
+          acc_a[u] = __builtin_fmaf(a.x, ra.x, acc_a[u]);
+          acc_a[u] = __builtin_fmaf(a.y, ra.y, acc_a[u]);
+          acc_a[u] = __builtin_fmaf(a.z, ra.z, acc_a[u]);
+          acc_a[u] = __builtin_fmaf(a.w, ra.w, acc_a[u]);
+          acc_b[u] = __builtin_fmaf(b.x, rb.x, acc_b[u]);
+          acc_b[u] = __builtin_fmaf(b.y, rb.y, acc_b[u]);
+          acc_b[u] = __builtin_fmaf(b.z, rb.z, acc_b[u]);
+          acc_b[u] = __builtin_fmaf(b.w, rb.w, acc_b[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSmallCols; ++u) {
+        const float cv = wave_sum(acc_a[u] + acc_b[u]);
+        const uint64_t key = make_key(cv, static_cast<int>(col + kSmallWaves * u));
+        best = key > best ? key : best;
+      }
+    }
+    for (; col < col1; col += kSmallWaves) {
       const float cv = dot_column_f32<false>(cols + (col - col0) * ld4, r_lds, ld4, lane);
       const uint64_t key = make_key(cv, static_cast<int>(col));
       best = key > best ? key : best;
     }
-    best = block_max<kCorrThreads>(best, kred);
-    if (threadIdx.x == 0) {
+    // this wave's key (the same in every lane: each correlation is the wave's
+    // lane sum) published at once
+    if (lane == 0) {
       const unsigned long long tag =
           static_cast<unsigned long long>(ep | (static_cast<unsigned>(k + 1) & 0xFFFFFu)) << 32;
-      unsigned long long* w0 = slots + (((k + 1) & 1) * kSmallMaxWgs + blockIdx.x) * 2;
+      unsigned long long* w0 =
+          slots + (((k + 1) & 1) * kSmallRecs + blockIdx.x * kSmallWaves + wave) * 2;
       __hip_atomic_store(w0, tag | (best >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(w0 + 1, tag | (best & 0xFFFFFFFFull), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -374,7 +417,7 @@ hipError_t launch_f32_small(const float* psi, int64_t ld, int64_t n, int64_t m, 
 }
 
 unsigned small_epoch_mod() { return kSmallEpochMod; }
-int small_max_wgs() { return kSmallMaxWgs; }
+int small_slot_words() { return 2 * kSmallRecs * 2; }
 
 // The first n floats of the residual half the state names (st->r_sel) into
 // r: the end of a carried decode, one launch instead of a host round trip.

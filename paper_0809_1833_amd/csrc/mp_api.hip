@@ -395,7 +395,7 @@ mp_status solve_carried(mp_ctx* c, const float* y, float* x, float* r, const mp_
     c->small_epoch = c->small_epoch % (mp::small_epoch_mod() - 1) + 1;
     if (c->small_epoch == 1)
       HIP_TRY(c, hipMemsetAsync(c->small_slots, 0,
-                                sizeof(unsigned long long) * 2 * 2 * mp::small_max_wgs(), s));
+                                sizeof(unsigned long long) * mp::small_slot_words(), s));
     const bool timed = c->profiling && !async;
     if (timed) HIP_TRY(c, hipEventRecord(c->ev[0], s));
     HIP_TRY(c, mp::launch_f32_small(c->psi32, c->ld, c->n, c->m, b.r_work, c->small,
@@ -548,7 +548,7 @@ mp_status mp_create(mp_ctx** out, const float* psi, int64_t n, int64_t m, int64_
   if (storage == MP_F32) {
     c->small = mp::small_geometry(c->ld, m, c->num_cus);
     if (c->small.grid > 0) {
-      const size_t bytes = sizeof(unsigned long long) * 2 * 2 * mp::small_max_wgs();
+      const size_t bytes = sizeof(unsigned long long) * mp::small_slot_words();
       if (hipMalloc(&c->small_slots, bytes) != hipSuccess) return bail(MP_ENOMEM, "step records");
       if (hipMemsetAsync(c->small_slots, 0, bytes, s) != hipSuccess)
         return bail(MP_EDEVICE, "step records");

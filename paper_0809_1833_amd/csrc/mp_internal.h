@@ -101,15 +101,16 @@ hipError_t noalloc_scratch(int device, void** out);
 // Small dictionaries (every workgroup's share of the columns in LDS): the
 // whole FP32 decode in one launch.  small_geometry gives grid 0 where it
 // does not apply.  rbuf: 2 x ld floats (r = y in half 0 from the init
-// kernel; r after the last step in half 1).  slots: 2 x small_max_wgs() x 2
-// words, zeroed at creation and whenever the epoch wraps.
+// kernel; r after the last step in half 1).  slots: small_slot_words()
+// words (two halves of one 2-word record per wave of every workgroup),
+// zeroed at creation and whenever the epoch wraps.
 CorrGeom small_geometry(int64_t ld, int64_t m, int num_cus);
 hipError_t launch_f32_small(const float* psi, int64_t ld, int64_t n, int64_t m, float* rbuf,
                             const CorrGeom& g, unsigned long long* slots, unsigned epoch,
                             long long max_iters, float* x, DevState* st, mp_trace tr,
                             hipStream_t s);
 unsigned small_epoch_mod();
-int small_max_wgs();
+int small_slot_words();
 
 // n floats of the residual half st->r_sel names (rbuf: 2 x ld) into r.
 hipError_t launch_copy_selected(const float* rbuf, int64_t ld, int64_t n, const DevState* st,
