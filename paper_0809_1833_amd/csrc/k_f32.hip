@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_f32_small(
     long long spin_limit, long long max_iters, float* __restrict__ x,
     DevState* __restrict__ st, mp_trace tr) {
   extern __shared__ v4f smem[];  // r (ld4 float4s), then the share's columns
-  __shared__ uint64_t kred[kCorrThreads / kWave];
+  __shared__ uint64_t s_keys[kSmallRecs];  // the polled keys of a pass
   __shared__ double dred[kCorrThreads / kWave];
   __shared__ int s_flag;
   const int ld4 = static_cast<int>(ld / 4);
@@ -290,6 +290,7 @@ __global__ __launch_bounds__(kCorrThreads) void k_f32_small(
           __builtin_amdgcn_s_sleep(1);
         }
         kp = ((hi & 0xFFFFFFFFull) << 32) | (lo & 0xFFFFFFFFull);
+        s_keys[threadIdx.x] = kp;
       }
       __syncthreads();
       if (s_flag) {
@@ -299,7 +300,13 @@ __global__ __launch_bounds__(kCorrThreads) void k_f32_small(
         }
         return;
       }
-      const uint64_t win = block_max<kCorrThreads>(kp, kred);
+      // every wave takes the largest of the polled keys itself (the same in
+      // all: the largest key does not depend on the order of comparison),
+      // with no further barrier; s_keys is written again only after the
+      // barriers of the update below
+      uint64_t v = 0;
+      for (int i = lane; i < G * kSmallWaves; i += kWave) v = s_keys[i] > v ? s_keys[i] : v;
+      const uint64_t win = wave_max(v);
       const int idx = key_index(win);
       const float c = key_value(win);
       if (carried_winner_stops(idx, c, m, st)) return;
