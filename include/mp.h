@@ -437,7 +437,7 @@ typedef struct mp_instance {
 /* Launch shape of the ragged decode (chosen by the autotuner). */
 typedef struct mp_ragged_config {
     int32_t threads;        /* workgroup size: 256, 512 or 1024 */
-    int32_t cols_per_wave;  /* columns one wave streams at once: 1, 2 or 4 (MP_BF16: 1) */
+    int32_t cols_per_wave;  /* columns one wave streams at once: 1, 2 or 4 */
     int32_t wgs_per_cu;     /* persistent workgroups per compute unit: 1..8 */
     int32_t split;          /* most parts one instance is cut into, 1..8 (0: the default,
                                2).  An instance whose estimated work (n^2 m) exceeds the

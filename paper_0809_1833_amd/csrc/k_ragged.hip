@@ -256,9 +256,17 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
           uint64_t L[kTopK];
 #pragma unroll
           for (int j = 0; j < kTopK; ++j) L[j] = 0;
-          for (int64_t col = cb + wave; col < ce; col += W)
-            top8_insert(L, make_key(dot_column_lp<2>(pq + col * nq, r_lds, nq, lane),
-                                    static_cast<int>(col)));
+          // CC columns at a time, each with dot_column_lp's arithmetic
+          for (int64_t c0 = cb + static_cast<int64_t>(wave) * CC; c0 < ce; c0 += W * CC) {
+            const v4u* p[CC];
+#pragma unroll
+            for (int c = 0; c < CC; ++c) p[c] = pq + (c0 + c < ce ? c0 + c : c0) * nq;
+            float acc[CC];
+            dot_columns_lp<2, CC>(p, r_lds, nq, lane, acc);
+#pragma unroll
+            for (int c = 0; c < CC; ++c)
+              if (c0 + c < ce) top8_insert(L, make_key(acc[c], static_cast<int>(c0 + c)));
+          }
           uint64_t v = 0;
 #pragma unroll
           for (int j = 0; j < kTopK; ++j)
@@ -370,9 +378,8 @@ static hipError_t launch_ragged_t(int grid, size_t lds, const RInst* inst, const
 
 bool ragged_config_valid(const RConfig& cf, bool lp) {
   const bool nt_ok = cf.threads == 256 || cf.threads == 512 || cf.threads == 1024;
-  const bool cc_ok = lp ? cf.cols_per_wave == 1
-                        : (cf.cols_per_wave == 1 || cf.cols_per_wave == 2 ||
-                           cf.cols_per_wave == 4);
+  const bool cc_ok = cf.cols_per_wave == 1 || cf.cols_per_wave == 2 || cf.cols_per_wave == 4;
+  (void)lp;
   return nt_ok && cc_ok && cf.wgs_per_cu >= 1 && cf.wgs_per_cu <= 8 && cf.split >= 1 &&
          cf.split <= kRaggedMaxParts;
 }
@@ -403,8 +410,14 @@ hipError_t launch_ragged(const RConfig& cf, bool lp, int grid, size_t lds, const
   MP_RAGGED_CASE(1024, 2, false)
   MP_RAGGED_CASE(1024, 4, false)
   MP_RAGGED_CASE(256, 1, true)
+  MP_RAGGED_CASE(256, 2, true)
+  MP_RAGGED_CASE(256, 4, true)
   MP_RAGGED_CASE(512, 1, true)
+  MP_RAGGED_CASE(512, 2, true)
+  MP_RAGGED_CASE(512, 4, true)
   MP_RAGGED_CASE(1024, 1, true)
+  MP_RAGGED_CASE(1024, 2, true)
+  MP_RAGGED_CASE(1024, 4, true)
 #undef MP_RAGGED_CASE
   return hipErrorInvalidValue;
 }

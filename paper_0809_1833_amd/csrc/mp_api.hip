@@ -1433,7 +1433,7 @@ mp_status mp_ragged_set_config(mp_ctx* ctx, const mp_ragged_config* cfg) {
   mp::RConfig cf{cfg->threads, cfg->cols_per_wave, cfg->wgs_per_cu,
                  cfg->split == 0 ? kRaggedDefaultSplit : cfg->split};
   if (!mp::ragged_config_valid(cf, ctx->storage == MP_BF16))
-    return fail(ctx, MP_EINVAL, "threads must be 256/512/1024, cols_per_wave 1/2/4 (BF16: 1), "
+    return fail(ctx, MP_EINVAL, "threads must be 256/512/1024, cols_per_wave 1/2/4, "
                                 "wgs_per_cu 1..8, split 0..8");
   ctx->r_cfg = cf;
   return MP_OK;

@@ -282,7 +282,7 @@ constexpr int kRaggedMaxParts = 8;
 constexpr int kRaggedRecWords = 16;  // words of one part's record: 8 keys, 2 words each
 struct RConfig {           // launch shape, chosen by the autotuner
   int threads;             // workgroup size: 256, 512 or 1024
-  int cols_per_wave;       // columns a wave streams at once: 1, 2 or 4 (BF16: 1)
+  int cols_per_wave;       // columns a wave streams at once: 1, 2 or 4
   int wgs_per_cu;          // persistent workgroups per CU
   int split;               // most parts an instance is cut into: 1 .. kRaggedMaxParts
 };

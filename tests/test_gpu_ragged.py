@@ -151,8 +151,6 @@ def test_launch_shape_does_not_change_selections(storage):
         ref = _solve(dec, yp, 1e-5, caps, 64)
         shapes = [(256, 1, 1, 1), (512, 2, 2, 2), (1024, 4, 1, 4), (256, 4, 2, 8),
                   (1024, 1, 2, 3), (1024, 2, 1, 2), (512, 1, 1, 8)]
-        if storage == "bf16":
-            shapes = [(t, 1, w, sp) for (t, c, w, sp) in shapes]
         for shape in shapes:
             print(f"[ragged {storage} shape {shape}]", flush=True)
             dec.set_config(*shape)
