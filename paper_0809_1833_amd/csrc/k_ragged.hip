@@ -4,8 +4,9 @@
 // workgroups takes items from an on-device work list (largest first, as the
 // host ordered them) and runs one instance's whole Section 3 loop (eqs. 8-12)
 // for each: the residual stays in LDS, the correlation pass streams the
-// instance's dictionary with every wave taking CC columns at a time, and the
-// argmax (smallest index on ties, eq. 16), the x~ and r updates and the FP64
+// instance's dictionary with every wave taking CC columns at a time (short
+// columns, of at most 32 16-byte elements, side by side in lane groups), and
+// the argmax (smallest index on ties, eq. 16), the x~ and r updates and the FP64
 // stopping test use only workgroup barriers.  An instance whose work would
 // hold one workgroup far longer than the average item is cut by the host
 // into `parts` consecutive items, one per column share: every part keeps the
@@ -73,6 +74,177 @@ __device__ inline void dot_cols_f32(const v4f* const (&p)[CC], const v4f* __rest
   }
 #pragma unroll
   for (int c = 0; c < CC; ++c) acc[c] = wave_sum(acc[c]);
+}
+
+// dot_columns_lp's sums (BF16 storage) with at most 8 16-byte loads in
+// flight per lane in all: blocks of 8/CC per column, so that a 1024-thread
+// workgroup's register share holds them.  A lane's sum runs over its
+// elements i, i+64, i+128, ... in order whatever the blocking, so every sum
+// is dot_columns_lp's bit for bit.
+template <int CC>
+__device__ inline void dot_cols_lp(const v4u* const (&p)[CC], const v4f* __restrict__ r_lds,
+                                   int nq, int lane, float (&out)[CC]) {
+  constexpr int U = 8 / CC;
+  float acc[CC];
+#pragma unroll
+  for (int c = 0; c < CC; ++c) acc[c] = 0.0f;
+  int i = lane;
+  while (i + kWave * (U - 1) < nq) lp_block_cols<2, U, CC>(p, r_lds, i, acc);
+  if constexpr (U >= 8)
+    if (i + kWave * 3 < nq) lp_block_cols<2, 4, CC>(p, r_lds, i, acc);
+  if constexpr (U >= 4)
+    if (i + kWave * 1 < nq) lp_block_cols<2, 2, CC>(p, r_lds, i, acc);
+  if constexpr (U >= 2)
+    if (i < nq) lp_block_cols<2, 1, CC>(p, r_lds, i, acc);
+#pragma unroll
+  for (int c = 0; c < CC; ++c) out[c] = wave_sum(acc[c]);
+}
+
+// The correlation pass of one step over columns [cb, ce), CC columns at a
+// time per wave.  FP32: returns the best key of this wave's columns.
+template <int CC>
+__device__ inline uint64_t f32_pass_wave(const float* __restrict__ psi32, int64_t ld, int ld4,
+                                         const v4f* __restrict__ r_lds, int64_t cb, int64_t ce,
+                                         int wave, int W, int lane) {
+  uint64_t best = 0;
+  for (int64_t c0 = cb + static_cast<int64_t>(wave) * CC; c0 < ce;
+       c0 += static_cast<int64_t>(W) * CC) {
+    const v4f* p[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c)
+      p[c] = reinterpret_cast<const v4f*>(psi32 + (c0 + c < ce ? c0 + c : c0) * ld);
+    float acc[CC];
+    dot_cols_f32<CC>(p, r_lds, ld4, lane, acc);
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      if (c0 + c < ce) {
+        const uint64_t k = make_key(acc[c], static_cast<int>(c0 + c));
+        best = k > best ? k : best;
+      }
+    }
+  }
+  return best;
+}
+
+// BF16: each column's sum (dot_columns_lp's), inserted into L.
+template <int CC>
+__device__ inline void lp_pass_wave(const v4u* __restrict__ pq, int nq,
+                                    const v4f* __restrict__ r_lds, int64_t cb, int64_t ce,
+                                    int wave, int W, int lane, uint64_t (&L)[kTopK]) {
+  for (int64_t c0 = cb + static_cast<int64_t>(wave) * CC; c0 < ce;
+       c0 += static_cast<int64_t>(W) * CC) {
+    const v4u* p[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) p[c] = pq + (c0 + c < ce ? c0 + c : c0) * nq;
+    float acc[CC];
+    dot_cols_lp<CC>(p, r_lds, nq, lane, acc);
+#pragma unroll
+    for (int c = 0; c < CC; ++c)
+      if (c0 + c < ce) top8_insert(L, make_key(acc[c], static_cast<int>(c0 + c)));
+  }
+}
+
+// ---- short columns: several side by side in one wave -----------------------
+//
+// A column of at most G 16-byte elements (G = 16 or 32) leaves most of a
+// wave idle and its sum alone on the critical path.  These passes put
+// P = 64/G columns side by side: lane group h (lanes h*G .. h*G+G-1) takes
+// column c0 + c*P + h, each lane one element, as the wave-wide form has at
+// these sizes.  group_sum takes the first steps of wave_sum, whose later
+// steps there only add the other lanes' zeros, so every sum, and so every
+// key, is the wave-wide form's bit for bit.  Each group keeps its own best
+// key (FP32) or top-8 list (BF16); the lists are merged into one per wave at
+// the end of the pass, the best keys by the workgroup's max, so the
+// workgroup-wide result is the wave-wide form's.
+
+template <int G>
+__device__ inline float group_sum(float v) {
+  static_assert(G == 16 || G == 32, "lane groups of 16 or 32");
+  v += dpp_f32<kDppQuadSwap1>(v);
+  v += dpp_f32<kDppQuadSwap2>(v);
+  v += dpp_f32<kDppRowMirror>(v);
+  v += dpp_f32<kDppRowHalfMirror>(v);
+  if constexpr (G == 32) v += __shfl_xor(v, 16, kWave);
+  return v;
+}
+
+// FP32 columns of ld4 <= G elements; returns the best key of this lane
+// group's columns (lanes differ).
+template <int G, int CC>
+__device__ inline uint64_t f32_pass_grouped(const float* __restrict__ psi32, int64_t ld, int ld4,
+                                            const v4f* __restrict__ r_lds, int64_t cb,
+                                            int64_t ce, int wave, int W, int lane) {
+  constexpr int P = kWave / G;
+  const int h = lane / G, sl = lane % G;
+  uint64_t best = 0;
+  for (int64_t c0 = cb + static_cast<int64_t>(wave) * P * CC; c0 < ce;
+       c0 += static_cast<int64_t>(W) * P * CC) {
+    float acc[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) acc[c] = 0.0f;
+    if (sl < ld4) {
+      const v4f b = r_lds[sl];
+#pragma unroll
+      for (int c = 0; c < CC; ++c) {
+        const int64_t col = c0 + c * P + h;
+        const v4f a = __builtin_nontemporal_load(
+            reinterpret_cast<const v4f*>(psi32 + (col < ce ? col : c0) * ld) + sl);
+        acc[c] = __builtin_fmaf(a.x, b.x, acc[c]);
+        acc[c] = __builtin_fmaf(a.y, b.y, acc[c]);
+        acc[c] = __builtin_fmaf(a.z, b.z, acc[c]);
+        acc[c] = __builtin_fmaf(a.w, b.w, acc[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int64_t col = c0 + c * P + h;
+      const uint64_t k = make_key(group_sum<G>(acc[c]), static_cast<int>(col));
+      if (col < ce) best = k > best ? k : best;
+    }
+  }
+  return best;
+}
+
+// BF16 columns of nq <= G elements, each with dot_columns_lp's arithmetic;
+// leaves this wave's 8 best in L, the same in every lane.
+template <int G, int CC>
+__device__ inline void lp_pass_grouped(const v4u* __restrict__ pq, int nq,
+                                       const v4f* __restrict__ r_lds, int64_t cb, int64_t ce,
+                                       int wave, int W, int lane, uint64_t (&L)[kTopK]) {
+  constexpr int P = kWave / G;
+  const int h = lane / G, sl = lane % G;
+  for (int64_t c0 = cb + static_cast<int64_t>(wave) * P * CC; c0 < ce;
+       c0 += static_cast<int64_t>(W) * P * CC) {
+    const v4u* p[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int64_t col = c0 + c * P + h;
+      p[c] = pq + (col < ce ? col : c0) * nq;
+    }
+    float acc[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) acc[c] = 0.0f;
+    if (sl < nq) {
+      int i = sl;
+      lp_block_cols<2, 1, CC>(p, r_lds, i, acc);
+    }
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int64_t col = c0 + c * P + h;
+      const uint64_t k = make_key(group_sum<G>(acc[c]), static_cast<int>(col));
+      if (col < ce) top8_insert(L, k);
+    }
+  }
+  // the groups' lists into one: group 0's, then the others' entries inserted
+  uint64_t M[kTopK];
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) M[j] = lane_u64(L[j], 0);
+#pragma unroll
+  for (int g = 1; g < P; ++g)
+#pragma unroll
+    for (int j = 0; j < kTopK; ++j) top8_insert(M, lane_u64(L[j], g * G));
+#pragma unroll
+  for (int j = 0; j < kTopK; ++j) L[j] = M[j];
 }
 
 // Before a decode: the work list from its start, no failure, record slots
@@ -215,21 +387,12 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
         // ---- correlation pass (eq. 9) over this part's columns and argmax ----
         uint64_t best = 0;
         if constexpr (!LP) {
-          for (int64_t c0 = cb + static_cast<int64_t>(wave) * CC; c0 < ce; c0 += W * CC) {
-            const v4f* p[CC];
-#pragma unroll
-            for (int c = 0; c < CC; ++c)
-              p[c] = reinterpret_cast<const v4f*>(d.psi32 + (c0 + c < ce ? c0 + c : c0) * ld);
-            float acc[CC];
-            dot_cols_f32<CC>(p, r_lds, ld4, lane, acc);
-#pragma unroll
-            for (int c = 0; c < CC; ++c) {
-              if (c0 + c < ce) {
-                const uint64_t k = make_key(acc[c], static_cast<int>(c0 + c));
-                best = k > best ? k : best;
-              }
-            }
-          }
+          if (ld4 <= 16)
+            best = f32_pass_grouped<16, CC>(d.psi32, ld, ld4, r_lds, cb, ce, wave, W, lane);
+          else if (ld4 <= 32)
+            best = f32_pass_grouped<32, CC>(d.psi32, ld, ld4, r_lds, cb, ce, wave, W, lane);
+          else
+            best = f32_pass_wave<CC>(d.psi32, ld, ld4, r_lds, cb, ce, wave, W, lane);
           best = block_max<NT>(best, kred);
           if (parts > 1) {
             // the siblings' best keys of this step; the largest is the winner
@@ -256,17 +419,17 @@ __global__ __launch_bounds__(NT) void k_ragged(const RInst* __restrict__ inst,
           uint64_t L[kTopK];
 #pragma unroll
           for (int j = 0; j < kTopK; ++j) L[j] = 0;
-          // CC columns at a time, each with dot_column_lp's arithmetic
-          for (int64_t c0 = cb + static_cast<int64_t>(wave) * CC; c0 < ce; c0 += W * CC) {
-            const v4u* p[CC];
-#pragma unroll
-            for (int c = 0; c < CC; ++c) p[c] = pq + (c0 + c < ce ? c0 + c : c0) * nq;
-            float acc[CC];
-            dot_columns_lp<2, CC>(p, r_lds, nq, lane, acc);
-#pragma unroll
-            for (int c = 0; c < CC; ++c)
-              if (c0 + c < ce) top8_insert(L, make_key(acc[c], static_cast<int>(c0 + c)));
+          // (not at 1024 threads: with the grouped passes in, the 128
+          // registers a lane has there spill in the wave-wide pass)
+          bool grouped = false;
+          if constexpr (NT <= 512) {
+            grouped = nq <= 32;
+            if (nq <= 16)
+              lp_pass_grouped<16, CC>(pq, nq, r_lds, cb, ce, wave, W, lane, L);
+            else if (nq <= 32)
+              lp_pass_grouped<32, CC>(pq, nq, r_lds, cb, ce, wave, W, lane, L);
           }
+          if (!grouped) lp_pass_wave<CC>(pq, nq, r_lds, cb, ce, wave, W, lane, L);
           uint64_t v = 0;
 #pragma unroll
           for (int j = 0; j < kTopK; ++j)
