@@ -142,7 +142,9 @@ def test_launch_shape_does_not_change_selections(storage):
     instances on a grid of 256 or more workgroups: each exceeds the average
     work per workgroup, so each is cut into `split` parts that exchange
     their candidates every step), gives the same atoms, x~ and r bit for
-    bit."""
+    bit.  With BF16 storage the 1024-thread shapes score the short columns
+    (N <= 256) with the wave-wide pass and the others side by side in lane
+    groups, so the two passes are compared bit for bit too."""
     probs = mpgen.make_ragged(1, count=40, n_choices=(64, 128, 256, 512))
     caps = [p.max_iters for p in probs]
     with _ragged(probs, storage) as dec:
