@@ -31,7 +31,7 @@ import torch
 
 FP32_SHAPES = [(t, c, w) for t in (256, 512, 1024) for c in (1, 2, 4) for w in (1, 2)]
 BF16_SHAPES = FP32_SHAPES
-SPLITS = (1, 2, 4)
+SPLITS = (1, 2, 3, 4)
 DEFAULT_SPLIT = 2
 SPLIT_SHAPES = 3  # shapes whose other splits are timed too
 
