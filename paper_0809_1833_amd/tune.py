@@ -4,7 +4,7 @@ The ragged decode (``mp_solve_ragged``) runs one persistent launch whose
 shape -- workgroup size, columns streamed per wave, workgroups per CU, and
 the most parts one large instance is cut into -- changes speed but never
 results.  ``tune_ragged`` times every valid shape on the actual instances
-(with the default split), then the other split choices on the three fastest
+(with the default split), then the other split choices on the six fastest
 shapes, and keeps the fastest; the choice is cached in a JSON file keyed by the GPU
 architecture, the storage type and the multiset of instance sizes, so later
 runs with the same shape of work reuse it.
@@ -33,7 +33,7 @@ FP32_SHAPES = [(t, c, w) for t in (256, 512, 1024) for c in (1, 2, 4) for w in (
 BF16_SHAPES = FP32_SHAPES
 SPLITS = (1, 2, 3, 4)
 DEFAULT_SPLIT = 2
-SPLIT_SHAPES = 3  # shapes whose other splits are timed too
+SPLIT_SHAPES = 6  # shapes whose other splits are timed too
 
 
 def cache_path() -> str:

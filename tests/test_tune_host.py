@@ -97,7 +97,7 @@ class FakeRaggedDecoder:
             time.sleep(0.002 if self.cfg[:3] == self.best[:3] else 0.004)
 
 
-def test_ragged_tuner_tries_splits_on_three_shapes(tmp_path, monkeypatch):
+def test_ragged_tuner_tries_splits_on_the_fastest_shapes(tmp_path, monkeypatch):
     from paper_0809_1833_amd import tune
     monkeypatch.setenv("MP_TUNE_CACHE", str(tmp_path / "tune.json"))
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
@@ -108,5 +108,5 @@ def test_ragged_tuner_tries_splits_on_three_shapes(tmp_path, monkeypatch):
     dec = FakeRaggedDecoder((512, 2, 1, 4))
     res = tune.tune_ragged(dec, torch.zeros(4), 1e-5, [5, 5, 5], reps=1, shapes=shapes)
     n_other = len(tune.SPLITS) - 1
-    assert len(res["timings"]) == len(shapes) + tune.SPLIT_SHAPES * n_other
+    assert len(res["timings"]) == len(shapes) + min(len(shapes), tune.SPLIT_SHAPES) * n_other
     assert res["config"] == dict(threads=512, cols_per_wave=2, wgs_per_cu=1, split=4)
