@@ -1299,7 +1299,6 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
   c->storage = storage;
   c->ragged = true;
   c->r_count = count;
-  if (storage == MP_BF16) c->r_cfg.cols_per_wave = 1;  // the BF16 pass takes one column per wave
   auto bail = [&](mp_status st, const std::string& msg) {
     free_ctx(c);
     return fail(nullptr, st, msg);
