@@ -440,7 +440,7 @@ typedef struct mp_ragged_config {
     int32_t cols_per_wave;  /* columns one wave streams at once: 1, 2 or 4 */
     int32_t wgs_per_cu;     /* persistent workgroups per compute unit: 1..8 */
     int32_t split;          /* most parts one instance is cut into, 1..8 (0: the default,
-                               2).  An instance whose estimated work (n^2 m) exceeds the
+                               3).  An instance whose estimated work (n^2 m) exceeds the
                                average per workgroup of the launch is decoded by up to
                                `split` workgroups at once, each streaming a share of its
                                columns; the parts exchange their candidates every step. */

@@ -20,7 +20,7 @@ constexpr int64_t kMaxN = 16384;          // the residual is staged whole in LDS
 constexpr int64_t kMaxSignN = 16384;      // two 16-byte chunks of a column per lane
 constexpr int64_t kMaxRaggedN = 8192;     // per-instance residual in LDS, 32 KB
 constexpr int kMaxRaggedSplit = 4096;     // instances cut into parts, at most
-constexpr int kRaggedDefaultSplit = 2;    // parts of an instance, at most, unless configured
+constexpr int kRaggedDefaultSplit = 3;    // parts of an instance, at most, unless configured
 constexpr int64_t kLdAlign = 64;          // padded column length (floats): 256 B aligned
 constexpr int kMaxChunk = 64;             // iterations enqueued per host check
 constexpr double kNormTol = 1e-4;
@@ -1299,6 +1299,11 @@ mp_status mp_create_ragged(mp_ctx** out, const mp_instance* inst, int64_t count,
   c->storage = storage;
   c->ragged = true;
   c->r_count = count;
+  // the untuned shape: the tuner's choice on the 512-instance mix of
+  // N in {128, ..., 1024} (one 1024-thread workgroup per CU, the largest
+  // instances in three parts)
+  c->r_cfg = storage == MP_BF16 ? mp::RConfig{1024, 2, 2, kRaggedDefaultSplit}
+                                : mp::RConfig{1024, 1, 2, kRaggedDefaultSplit};
   auto bail = [&](mp_status st, const std::string& msg) {
     free_ctx(c);
     return fail(nullptr, st, msg);

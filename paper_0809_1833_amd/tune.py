@@ -4,7 +4,7 @@ The ragged decode (``mp_solve_ragged``) runs one persistent launch whose
 shape -- workgroup size, columns streamed per wave, workgroups per CU, and
 the most parts one large instance is cut into -- changes speed but never
 results.  ``tune_ragged`` times every valid shape on the actual instances
-(with the default split), then the other split choices on the six fastest
+(at split 2), then the other split choices on the six fastest
 shapes, and keeps the fastest; the choice is cached in a JSON file keyed by the GPU
 architecture, the storage type and the multiset of instance sizes, so later
 runs with the same shape of work reuse it.
@@ -32,7 +32,7 @@ import torch
 FP32_SHAPES = [(t, c, w) for t in (256, 512, 1024) for c in (1, 2, 4) for w in (1, 2)]
 BF16_SHAPES = FP32_SHAPES
 SPLITS = (1, 2, 3, 4)
-DEFAULT_SPLIT = 2
+RANK_SPLIT = 2  # the split every shape is first timed at
 SPLIT_SHAPES = 6  # shapes whose other splits are timed too
 
 
@@ -101,13 +101,13 @@ def tune_ragged(dec, y_packed: torch.Tensor, eps: float, max_iters, reps: int = 
             log(f"[tune] threads={t} cols/wave={c} wgs/cu={w} split={sp}: {best * 1e3:.2f} ms")
 
     for (t, c, w) in shapes:
-        time_shape(t, c, w, DEFAULT_SPLIT)
+        time_shape(t, c, w, RANK_SPLIT)
     # the other splits on the best few shapes: the best split depends on the
-    # shape (shapes that tie at the default split can part at another)
+    # shape (shapes that tie at split 2 can part at another)
     ranked = sorted(timings, key=lambda d: d["ms"])[:SPLIT_SHAPES]
     for d in ranked:
         for sp in SPLITS:
-            if sp != DEFAULT_SPLIT:
+            if sp != RANK_SPLIT:
                 time_shape(d["threads"], d["cols_per_wave"], d["wgs_per_cu"], sp)
     win = min(timings, key=lambda d: d["ms"])
     cfg = dict(threads=win["threads"], cols_per_wave=win["cols_per_wave"],

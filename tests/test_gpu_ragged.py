@@ -250,7 +250,7 @@ def test_autotuner_picks_a_valid_shape(tmp_path, monkeypatch):
         yp = _ypacked(probs)
         res = tune.tune_ragged(dec, yp, 1e-5, caps, reps=1,
                                shapes=[(256, 1, 1), (1024, 2, 1), (512, 4, 2)])
-        # three shapes at the default split, then the other splits on the best
+        # three shapes at split 2, then the other splits on the best
         # (here all three)
         assert not res["cached"]
         assert len(res["timings"]) == 3 + min(3, tune.SPLIT_SHAPES) * (len(tune.SPLITS) - 1)
